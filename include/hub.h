@@ -1,0 +1,221 @@
+/*
+ * hub.h — C ABI of the MI355X exact-diagonalization time stepper for the
+ * Peierls-driven Hubbard model (arXiv:2005.13498).
+ *
+ * The library evolves a state of one particle-number sector with the
+ * exponential midpoint rule of Eq. (time-stepping),
+ *     v(t + dt) = exp(-i dt H(t + dt/2)) v(t),
+ * each exponential taken by the adaptive Lanczos/Krylov step of Alg. 6 with
+ * the a-posteriori error estimate of Sec. 3.4.  H(t) is Eq. (hubbardhamiltonian)
+ * with the Peierls phases of Eq. (peierls), applied matrix-free.
+ *
+ * Conventions shared by every call
+ *  - Geometry (Sec. 2.1): undirected bonds (i, j) with amplitude t_ij > 0 and
+ *    displacement dx_ij = (R_i - R_j) projected on the field.  Each bond adds
+ *        -t_ij e^{+i A dx_ij} c^dag_{i s} c_{j s} - t_ij e^{-i A dx_ij} c^dag_{j s} c_{i s}
+ *    for both spins s.  On a periodic wrap bond dx is the minimum image.
+ *    Optional on-site energies eps_i add eps_i (n_{i up} + n_{i down})
+ *    (eps_i = -v_ii in the paper's notation).
+ *  - Basis and layout: a sector state is the pair (a, b) of an up string and
+ *    a down string (bit i = site i); a (b) is the rank of the up (down)
+ *    string among all strings with n_up (n_dn) bits in increasing integer
+ *    order, which equals the combinatorial rank of Eq. (hashing).  The
+ *    operator order is spin-separated: all up creators (site 0 leftmost),
+ *    then all down creators.  (The paper's interleaved order of Eq. (statedef)
+ *    differs from this by a sign per basis state only.)  A vector is
+ *    psi[a * dim_dn + b], complex interleaved (re, im): double pairs for
+ *    HUB_C128, float pairs for HUB_C64.  nvec vectors are stored one after the
+ *    other: psi[v * dim + a * dim_dn + b].
+ *  - Memory: every vector argument is a caller-owned DEVICE pointer on the
+ *    handle's device; every struct or scalar array argument is a HOST pointer.
+ *    Input and output vectors must not alias unless stated.
+ *  - Streams: `stream` is a hipStream_t (NULL = default stream).  Calls that
+ *    only write device memory are asynchronous; calls that fill host structs
+ *    synchronise `stream` before returning.
+ *  - Errors: every call returns a hub_status and never aborts; arguments are
+ *    validated before any launch.  hub_last_error() gives a message for the
+ *    last non-OK status on the calling thread.  A handle may not be used by
+ *    two threads at once.
+ */
+#ifndef HUB_H
+#define HUB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HUB_OK = 0,
+  HUB_E_INVALID = -1,       /* bad argument (null, out of range, aliasing)      */
+  HUB_E_SECTOR = -2,        /* particle numbers impossible for the lattice     */
+  HUB_E_NOMEM = -3,         /* device allocation failed                        */
+  HUB_E_DEVICE = -4,        /* HIP runtime error                               */
+  HUB_E_NOT_CONVERGED = -5, /* Krylov step hit m_max before the tolerance      */
+  HUB_E_DEGENERATE = -6     /* ground state not separated from the next level  */
+} hub_status;
+
+typedef enum { HUB_C128 = 0, HUB_C64 = 1 } hub_prec;
+
+/* Geometry = the paper's hopping matrix v (Sec. 2.1, Fig. 1). Host arrays. */
+typedef struct {
+  int32_t n_sites;          /* 1 .. 16                                          */
+  int32_t n_bonds;          /* >= 0                                             */
+  const int32_t *bond_i;    /* [n_bonds], 0 <= i < n_sites                      */
+  const int32_t *bond_j;    /* [n_bonds], j != i, no bond listed twice          */
+  const double *bond_t;     /* [n_bonds], hopping amplitude t_ij                */
+  const double *bond_dx;    /* [n_bonds], (R_i - R_j) along the field           */
+  const double *onsite;     /* [n_sites] eps_i, or NULL                         */
+  double U;                 /* on-site interaction                              */
+} hub_lattice;
+
+/* Pulse (Sec. 2.2).  kind 0: A(t) = A0 exp(-(t-t0)^2/(2 sigma^2)) sin(omega (t-t0)),
+ * a Gaussian-windowed sine (the shape of Eq. (efield)) used as the vector
+ * potential.  kind 1: the phase of Eq. (vt), A(t) = a [cos(omega (t-t_p)) - b]
+ * exp(-(t-t_p)^2/(2 sigma^2)) with a = A0, t_p = t0, so bonds with dx = 1 carry f(t). */
+typedef struct {
+  int32_t kind;
+  double A0, omega, t0, sigma, b;
+} hub_pulse;
+
+/* Krylov options (Alg. 6).  tol: stop when the a-posteriori estimate eps < tol
+ * or the new off-diagonal element beta_j < |H|_inf * tol.  m_max: N_max of
+ * Alg. 6 (1..60).  reorth: 0 = three-term recurrence only (as printed),
+ * 1 = full reorthogonalisation (classical Gram-Schmidt, twice) against all
+ * previous Krylov vectors with FP64 coefficients.  substeps: the step's
+ * exponential exp(-i dt H(t_mid)) is split into this many equal factors of
+ * the same H(t_mid) (>= 1).  m_hint: Lanczos iterations enqueued before the
+ * first convergence check (0 = the library's own choice). */
+typedef struct {
+  double tol;
+  int32_t m_max;
+  int32_t reorth;
+  int32_t substeps;
+  int32_t m_hint;
+} hub_krylov_opts;
+
+/* Per step (per vector) report. err_est = last a-posteriori estimate eps. */
+typedef struct {
+  int32_t m_used, substeps, converged, breakdown;
+  double err_est, beta_last;
+} hub_step_info;
+
+/* Observables at one sample time (Eqs. (docc), (energy), Sec. 3.5), per vector:
+ * norm |psi|, <psi|H(t)|psi>/n_sites, <psi|sum_i d_i|psi>/n_sites.  For a
+ * vector that is not normalised the expectation values are NOT divided by
+ * the norm. */
+typedef struct {
+  double t, norm, energy_per_site, docc_per_site;
+} hub_obs;
+
+typedef struct hub_basis_s *hub_basis;
+
+/* ------------------------------------------------------------------------ */
+/* Sector basis and hop tables (Sec. 3.1 "Discrete basis", Sec. 3.2 linear-
+ * complexity structure via the ranking of Eq. (hashing)).  Builds, on the
+ * host, the increasing list of up and down strings, and for every string the
+ * list of one-electron hops along the bonds (target rank, fermionic sign of
+ * Eq. (sign-explanation), amplitude class), then copies them to `device`.
+ * device = -1 builds a host-only handle: tables can be inspected
+ * (hub_basis_info/states/hops/classes) but every compute call returns
+ * HUB_E_DEVICE.  Errors: HUB_E_INVALID (bad geometry, more than 8 distinct
+ * (t, dx) hop classes), HUB_E_SECTOR (n_up or n_dn outside 0..n_sites),
+ * HUB_E_NOMEM, HUB_E_DEVICE.  On error *out is NULL. */
+hub_status hub_basis_create(const hub_lattice *lattice, int32_t n_up, int32_t n_dn,
+                            int32_t device, hub_basis *out);
+
+/* Frees the handle, its tables and its workspace.  NULL is ignored.
+ * Synchronises the handle's device first. */
+void hub_basis_destroy(hub_basis basis);
+
+/* Sector dimension C(Ns,n_up) C(Ns,n_dn) (Eq. (statedim)) and its factors. */
+hub_status hub_basis_info(hub_basis basis, int64_t *dim, int32_t *dim_up, int32_t *dim_dn);
+
+/* Host copies of the up strings [dim_up] and down strings [dim_dn] (bit i =
+ * site i), in rank order.  Either pointer may be NULL. */
+hub_status hub_basis_states(hub_basis basis, uint32_t *up_bits, uint32_t *dn_bits);
+
+/* Hop classes: class c contributes -t[c] exp(i A d[c]) per hop (d = R_dst -
+ * R_src along the field).  t, d: host arrays of length >= 8 or NULL;
+ * n_classes receives the count.  norm_inf (nullable) receives |H|_inf, the
+ * largest absolute row sum of H, which the Peierls phases leave unchanged. */
+hub_status hub_basis_classes(hub_basis basis, double *t, double *d, int32_t *n_classes,
+                             double *norm_inf);
+
+/* Gather-form hop table of one spin (0 = up, 1 = down): for target rank r
+ * the hops are entries ptr[r] .. ptr[r+1]-1 with source rank src[k], sign
+ * sgn[k] in {+1, -1} (Eq. (sign-explanation)) and class cls[k], so that the
+ * one-spin hopping matrix is T[r][src] += sgn * coef_cls.  Call with NULL
+ * arrays to get *n_hops first; ptr has dim_spin + 1 entries. */
+hub_status hub_basis_hops(hub_basis basis, int32_t spin, int32_t *ptr, int32_t *src, int32_t *sgn,
+                          int32_t *cls, int64_t *n_hops);
+
+/* ------------------------------------------------------------------------ */
+/* y = H(A_v) x_v for nvec vectors (Eq. (hubbardhamiltonian) with the Peierls
+ * phases of Eq. (peierls) at vector potential A_v; matrix-free).  A: host
+ * array [nvec].  x, y: device, nvec * dim complex of precision `prec`,
+ * distinct buffers.  Asynchronous on `stream`. */
+hub_status hub_apply_H(hub_basis basis, const double *A, hub_prec prec, int32_t nvec,
+                       const void *x, void *y, void *stream);
+
+/* Observables of Sec. 3.5 at vector potential A_v (host [nvec]) for the nvec
+ * device vectors v.  out: host [nvec] (out[k].t is set to 0).  site_docc:
+ * host [nvec * n_sites] <n_{i up} n_{i down}> per site, or NULL.
+ * Synchronises `stream`. */
+hub_status hub_observables(hub_basis basis, const double *A, hub_prec prec, int32_t nvec,
+                           const void *v, hub_obs *out, double *site_docc, void *stream);
+
+/* One Krylov step (Alg. 6): v_k <- exp(-i dt H(A_mid_k)) v_k for nvec device
+ * vectors (in place).  A_mid: host [nvec].  info: host [nvec] or NULL.
+ * Returns HUB_E_NOT_CONVERGED if any vector hit m_max (its result is then
+ * the m_max approximation, info.converged = 0).  Synchronises `stream`. */
+hub_status hub_krylov_expm_step(hub_basis basis, const double *A_mid, double dt,
+                                const hub_krylov_opts *opts, hub_prec prec, int32_t nvec,
+                                void *v_inout, hub_step_info *info, void *stream);
+
+/* n_steps midpoint steps (Eq. (time-stepping)) from t_start: step n uses
+ * H(A_k(t_start + n dt + dt/2)) for vector k with pulse pulses[k] (host
+ * [nvec]).  v_inout: device, nvec vectors, in place.  obs: host
+ * [(n_steps + 1) * nvec] or NULL: observables at t_start + n dt (row n,
+ * column k), with H(t) evaluated at the sample time.  log: host
+ * [n_steps * nvec] or NULL.  Returns HUB_E_NOT_CONVERGED (and stops) at the
+ * first step where a vector hits m_max; v_inout then holds that step's
+ * m_max approximation.  Synchronises `stream`. */
+hub_status hub_propagate(hub_basis basis, const hub_pulse *pulses, double t_start, double dt,
+                         int32_t n_steps, const hub_krylov_opts *opts, hub_prec prec,
+                         int32_t nvec, void *v_inout, hub_obs *obs, hub_step_info *log,
+                         void *stream);
+
+/* Ground state of H(A) (Sec. 3.4 "Ground state"): restarted Lanczos with
+ * full reorthogonalisation in FP64 until the residual |H x - E0 x| falls
+ * below opts->tol * |H|_inf (opts NULL: tol 1e-12, m_max 60).  v_out:
+ * device, dim complex doubles, normalised, phase fixed so that the component
+ * of largest modulus is real positive (lowest index among ties within 1e-12).
+ * E0, gap (E1 - E0 of the Ritz values): host, gap may be NULL.  Returns
+ * HUB_E_DEGENERATE when gap < 1e-8 * |H|_inf (v_out and E0 still written).
+ * Synchronises `stream`. */
+hub_status hub_ground_state(hub_basis basis, double A, const hub_krylov_opts *opts,
+                            void *v_out, double *E0, double *gap, void *stream);
+
+/* Value of the pulse's A(t) (host arithmetic, as used by hub_propagate). */
+hub_status hub_pulse_A(const hub_pulse *pulse, double t, double *A);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *hub_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing of the matrix-free apply (for roofline reporting).  While
+ * enabled, the library brackets every H*v launch with HIP events on the
+ * launch stream.  hub_profile_read returns the number of timed launches, the
+ * summed kernel time in ms, and the algorithmic bytes of one launch
+ * (2 * nvec * dim * complex size: read x once, write y once) of the last
+ * timed launch, then resets the counters.  Synchronises the device. */
+hub_status hub_profile_enable(hub_basis basis, int32_t on);
+hub_status hub_profile_read(hub_basis basis, int64_t *launches, double *total_ms,
+                            double *bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HUB_H */

@@ -1,0 +1,343 @@
+"""Python binding of libhub (include/hub.h): argument marshalling only.
+
+Every step of the time evolution runs in the HIP library; this module turns
+Python objects into the C structs and raw device pointers the ABI expects.
+Device vectors are torch tensors (complex128 for HUB_C128, complex64 for
+HUB_C64) on the handle's GPU; torch supplies the memory and the stream.
+
+The library is loaded from this package directory (libhub.so, built by
+`paper_2005_13498_amd.build`).  If it is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhub.so")
+
+HUB_OK = 0
+HUB_E_INVALID = -1
+HUB_E_SECTOR = -2
+HUB_E_NOMEM = -3
+HUB_E_DEVICE = -4
+HUB_E_NOT_CONVERGED = -5
+HUB_E_DEGENERATE = -6
+HUB_C128 = 0
+HUB_C64 = 1
+
+STATUS_NAMES = {0: "HUB_OK", -1: "HUB_E_INVALID", -2: "HUB_E_SECTOR", -3: "HUB_E_NOMEM",
+                -4: "HUB_E_DEVICE", -5: "HUB_E_NOT_CONVERGED", -6: "HUB_E_DEGENERATE"}
+
+# Every symbol include/hub.h declares.
+EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis_states",
+           "hub_basis_classes", "hub_basis_hops",
+           "hub_apply_H", "hub_observables", "hub_krylov_expm_step", "hub_propagate",
+           "hub_ground_state", "hub_pulse_A", "hub_last_error", "hub_profile_enable",
+           "hub_profile_read")
+
+
+class HubError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class hub_lattice(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("n_bonds", ctypes.c_int32),
+                ("bond_i", ctypes.POINTER(ctypes.c_int32)), ("bond_j", ctypes.POINTER(ctypes.c_int32)),
+                ("bond_t", ctypes.POINTER(ctypes.c_double)), ("bond_dx", ctypes.POINTER(ctypes.c_double)),
+                ("onsite", ctypes.POINTER(ctypes.c_double)), ("U", ctypes.c_double)]
+
+
+class hub_pulse(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("A0", ctypes.c_double), ("omega", ctypes.c_double),
+                ("t0", ctypes.c_double), ("sigma", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class hub_krylov_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("m_max", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("substeps", ctypes.c_int32), ("m_hint", ctypes.c_int32)]
+
+
+class hub_step_info(ctypes.Structure):
+    _fields_ = [("m_used", ctypes.c_int32), ("substeps", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32), ("err_est", ctypes.c_double), ("beta_last", ctypes.c_double)]
+
+
+class hub_obs(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("norm", ctypes.c_double), ("energy_per_site", ctypes.c_double),
+                ("docc_per_site", ctypes.c_double)]
+
+
+_lib_handle = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhub.so (raises if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(path):
+        raise RuntimeError(f"libhub.so not found at {path}: run paper_2005_13498_amd.build first")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "hub_basis_create": ([P(hub_lattice), i32, i32, i32, P(vp)], i32),
+        "hub_basis_destroy": ([vp], None),
+        "hub_basis_info": ([vp, P(i64), P(i32), P(i32)], i32),
+        "hub_basis_states": ([vp, P(ctypes.c_uint32), P(ctypes.c_uint32)], i32),
+        "hub_basis_classes": ([vp, P(dbl), P(dbl), P(i32), P(dbl)], i32),
+        "hub_basis_hops": ([vp, i32, P(i32), P(i32), P(i32), P(i32), P(i64)], i32),
+        "hub_apply_H": ([vp, P(dbl), i32, i32, vp, vp, vp], i32),
+        "hub_observables": ([vp, P(dbl), i32, i32, vp, P(hub_obs), P(dbl), vp], i32),
+        "hub_krylov_expm_step": ([vp, P(dbl), dbl, P(hub_krylov_opts), i32, i32, vp, P(hub_step_info), vp], i32),
+        "hub_propagate": ([vp, P(hub_pulse), dbl, dbl, i32, P(hub_krylov_opts), i32, i32, vp, P(hub_obs),
+                           P(hub_step_info), vp], i32),
+        "hub_ground_state": ([vp, dbl, P(hub_krylov_opts), vp, P(dbl), P(dbl), vp], i32),
+        "hub_pulse_A": ([P(hub_pulse), dbl, P(dbl)], i32),
+        "hub_last_error": ([], ctypes.c_char_p),
+        "hub_profile_enable": ([vp, i32], i32),
+        "hub_profile_read": ([vp, P(i64), P(dbl), P(dbl)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib_handle = lib
+    return lib
+
+
+def _check(status: int, allow=()):
+    if status != HUB_OK and status not in allow:
+        msg = load_library().hub_last_error()
+        raise HubError(status, msg.decode() if msg else "")
+    return status
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dbl_array(vals):
+    arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+    return arr
+
+
+def make_lattice(lattice, U: float):
+    """hub_lattice from a synth.Lattice (keeps the backing arrays alive)."""
+    bi, bj, bt, bdx = lattice.arrays()
+    nb = len(bi)
+    keep = [(ctypes.c_int32 * max(nb, 1))(*bi), (ctypes.c_int32 * max(nb, 1))(*bj),
+            (ctypes.c_double * max(nb, 1))(*bt), (ctypes.c_double * max(nb, 1))(*bdx)]
+    onsite = None
+    if lattice.onsite is not None:
+        onsite = (ctypes.c_double * lattice.n_sites)(*lattice.onsite)
+        keep.append(onsite)
+    L = hub_lattice(lattice.n_sites, nb, keep[0], keep[1], keep[2], keep[3],
+                    ctypes.cast(onsite, ctypes.POINTER(ctypes.c_double)) if onsite is not None else None,
+                    float(U))
+    return L, keep
+
+
+def make_pulse(p) -> hub_pulse:
+    kind, A0, omega, t0, sigma, b = p.as_tuple() if hasattr(p, "as_tuple") else p
+    return hub_pulse(int(kind), float(A0), float(omega), float(t0), float(sigma), float(b))
+
+
+def make_opts(tol=1e-10, m_max=30, reorth=0, substeps=1, m_hint=0) -> hub_krylov_opts:
+    return hub_krylov_opts(float(tol), int(m_max), int(reorth), int(substeps), int(m_hint))
+
+
+# ------------------------------------------------------------------- ABI calls
+
+def hub_basis_create(lattice, U: float, n_up: int, n_dn: int, device: int = 0) -> int:
+    lib = load_library()
+    L, keep = make_lattice(lattice, U)
+    h = ctypes.c_void_p()
+    _check(lib.hub_basis_create(ctypes.byref(L), int(n_up), int(n_dn), int(device), ctypes.byref(h)))
+    return h.value
+
+
+def hub_basis_destroy(h) -> None:
+    load_library().hub_basis_destroy(ctypes.c_void_p(h))
+
+
+def hub_basis_info(h):
+    d, du, dd = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().hub_basis_info(ctypes.c_void_p(h), ctypes.byref(d), ctypes.byref(du), ctypes.byref(dd)))
+    return d.value, du.value, dd.value
+
+
+def hub_basis_states(h):
+    _, du, dd = hub_basis_info(h)
+    up = np.zeros(du, dtype=np.uint32)
+    dn = np.zeros(dd, dtype=np.uint32)
+    _check(load_library().hub_basis_states(ctypes.c_void_p(h),
+                                           up.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                           dn.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return up, dn
+
+
+def hub_basis_classes(h):
+    """(t[nc], d[nc], norm_inf)."""
+    t = np.zeros(8)
+    d = np.zeros(8)
+    nc = ctypes.c_int32()
+    ni = ctypes.c_double()
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().hub_basis_classes(ctypes.c_void_p(h), t.ctypes.data_as(P), d.ctypes.data_as(P),
+                                            ctypes.byref(nc), ctypes.byref(ni)))
+    return t[: nc.value], d[: nc.value], ni.value
+
+
+def hub_basis_hops(h, spin: int):
+    """(ptr[dim_spin+1], src, sign, cls) of the gather-form hop table."""
+    lib = load_library()
+    n = ctypes.c_int64()
+    _check(lib.hub_basis_hops(ctypes.c_void_p(h), int(spin), None, None, None, None, ctypes.byref(n)))
+    _, du, dd = hub_basis_info(h)
+    ptr = np.zeros((du if spin == 0 else dd) + 1, dtype=np.int32)
+    src = np.zeros(max(n.value, 1), dtype=np.int32)
+    sgn = np.zeros(max(n.value, 1), dtype=np.int32)
+    cls = np.zeros(max(n.value, 1), dtype=np.int32)
+    P = ctypes.POINTER(ctypes.c_int32)
+    _check(lib.hub_basis_hops(ctypes.c_void_p(h), int(spin), ptr.ctypes.data_as(P), src.ctypes.data_as(P),
+                              sgn.ctypes.data_as(P), cls.ctypes.data_as(P), ctypes.byref(n)))
+    k = n.value
+    return ptr, src[:k], sgn[:k], cls[:k]
+
+
+def _prec_of(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return HUB_C128
+    if t.dtype == torch.complex64:
+        return HUB_C64
+    raise TypeError("device vectors must be complex128 or complex64 tensors")
+
+
+def hub_apply_H(h, A: Sequence[float], x, y, stream=None) -> None:
+    """y = H(A_k) x_k for the nvec = len(A) vectors stored in x (contiguous)."""
+    A = list(np.atleast_1d(A))
+    assert x.is_contiguous() and y.is_contiguous() and x.dtype == y.dtype
+    _check(load_library().hub_apply_H(ctypes.c_void_p(h), _dbl_array(A), _prec_of(x), len(A), _dptr(x), _dptr(y),
+                                      _stream_ptr(stream)))
+
+
+def hub_observables(h, A: Sequence[float], v, site=False, stream=None):
+    """(obs array [nvec, 4] = t, norm, energy/site, docc/site; site docc or None)."""
+    A = list(np.atleast_1d(A))
+    n = len(A)
+    out = (hub_obs * n)()
+    sd = np.zeros(n * _n_sites_cache.get(h, 16), dtype=np.float64) if site else None
+    _check(load_library().hub_observables(ctypes.c_void_p(h), _dbl_array(A), _prec_of(v), n, _dptr(v), out,
+                                          sd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if site else None,
+                                          _stream_ptr(stream)))
+    arr = np.array([[o.t, o.norm, o.energy_per_site, o.docc_per_site] for o in out])
+    if site:
+        ns = _n_sites_cache.get(h, 16)
+        return arr, sd.reshape(n, ns)
+    return arr, None
+
+
+_n_sites_cache = {}
+
+
+def _info_array(info, n):
+    return np.array([(i.m_used, i.substeps, i.converged, i.breakdown, i.err_est, i.beta_last) for i in info[:n]])
+
+
+def hub_krylov_expm_step(h, A_mid: Sequence[float], dt: float, opts: hub_krylov_opts, v, stream=None,
+                         allow_not_converged=False):
+    A = list(np.atleast_1d(A_mid))
+    info = (hub_step_info * len(A))()
+    st = _check(load_library().hub_krylov_expm_step(ctypes.c_void_p(h), _dbl_array(A), float(dt),
+                                                    ctypes.byref(opts), _prec_of(v), len(A), _dptr(v), info,
+                                                    _stream_ptr(stream)),
+                allow=(HUB_E_NOT_CONVERGED,) if allow_not_converged else ())
+    return st, _info_array(info, len(A))
+
+
+def hub_propagate(h, pulses, t_start: float, dt: float, n_steps: int, opts: hub_krylov_opts, v,
+                  want_obs=True, want_log=True, stream=None, allow_not_converged=False):
+    """Returns (status, obs [n_steps+1, nvec, 4] or None, log [n_steps, nvec, 6] or None)."""
+    pulses = list(pulses)
+    nvec = len(pulses)
+    parr = (hub_pulse * nvec)(*[make_pulse(p) for p in pulses])
+    obs = (hub_obs * ((n_steps + 1) * nvec))() if want_obs else None
+    log = (hub_step_info * max(1, n_steps * nvec))() if want_log else None
+    st = _check(load_library().hub_propagate(ctypes.c_void_p(h), parr, float(t_start), float(dt), int(n_steps),
+                                             ctypes.byref(opts), _prec_of(v), nvec, _dptr(v), obs, log,
+                                             _stream_ptr(stream)),
+                allow=(HUB_E_NOT_CONVERGED,) if allow_not_converged else ())
+    o = None
+    if want_obs:
+        o = np.array([[x.t, x.norm, x.energy_per_site, x.docc_per_site] for x in obs]).reshape(n_steps + 1, nvec, 4)
+    lg = _info_array(log, n_steps * nvec).reshape(n_steps, nvec, 6) if (want_log and n_steps > 0) else None
+    return st, o, lg
+
+
+def hub_ground_state(h, A: float, v_out, opts: Optional[hub_krylov_opts] = None, stream=None,
+                     allow_degenerate=False):
+    E0, gap = ctypes.c_double(), ctypes.c_double()
+    st = _check(load_library().hub_ground_state(ctypes.c_void_p(h), float(A),
+                                                ctypes.byref(opts) if opts is not None else None,
+                                                _dptr(v_out), ctypes.byref(E0), ctypes.byref(gap),
+                                                _stream_ptr(stream)),
+                allow=(HUB_E_DEGENERATE,) if allow_degenerate else ())
+    return st, E0.value, gap.value
+
+
+def hub_pulse_A(pulse, t: float) -> float:
+    A = ctypes.c_double()
+    p = make_pulse(pulse)
+    _check(load_library().hub_pulse_A(ctypes.byref(p), float(t), ctypes.byref(A)))
+    return A.value
+
+
+def hub_profile_enable(h, on: bool) -> None:
+    _check(load_library().hub_profile_enable(ctypes.c_void_p(h), 1 if on else 0))
+
+
+def hub_profile_read(h):
+    n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().hub_profile_read(ctypes.c_void_p(h), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)))
+    return n.value, ms.value, b.value
+
+
+class Basis:
+    """Owning wrapper of a basis handle."""
+
+    def __init__(self, lattice, U: float, n_up: int, n_dn: int, device: int = 0):
+        self.lattice = lattice
+        self.U = U
+        self.handle = hub_basis_create(lattice, U, n_up, n_dn, device)
+        self.dim, self.dim_up, self.dim_dn = hub_basis_info(self.handle)
+        self.n_sites = lattice.n_sites
+        _n_sites_cache[self.handle] = lattice.n_sites
+
+    def close(self):
+        if self.handle:
+            hub_basis_destroy(self.handle)
+            _n_sites_cache.pop(self.handle, None)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

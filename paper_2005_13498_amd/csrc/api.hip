@@ -1,0 +1,1027 @@
+// C ABI of the library (include/hub.h): argument validation, device tables,
+// workspace, and the host orchestration of the Krylov midpoint steps.
+#include "hub.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <cstddef>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "basis.h"
+#include "host_eig.h"
+#include "kernels.h"
+
+using hub::CombineLog;
+using hub::DevBasis;
+using hub::kMaxClasses;
+using hub::kMaxNV;
+using hub::kMMax;
+using hub::kObsQ;
+using hub::StepCtl;
+using hub::VecState;
+
+namespace {
+
+thread_local std::string g_err;
+
+hub_status fail(hub_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HUB_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? HUB_E_NOMEM : HUB_E_DEVICE,               \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+size_t elem_bytes(hub_prec p) { return p == HUB_C128 ? 16 : 8; }
+
+}  // namespace
+
+struct hub_basis_s {
+  hub::Basis B;
+  DevBasis D;
+  int device = 0;
+  std::vector<void*> allocs;  // table allocations
+  // workspace
+  void* slots = nullptr;
+  size_t slots_bytes = 0;
+  void* blockbuf = nullptr;
+  size_t blockbuf_bytes = 0;
+  void** slot_ptrs = nullptr;     // device [kMMax + 2]
+  VecState* st = nullptr;         // device [kMaxNV]
+  StepCtl* ctl = nullptr;         // device
+  StepCtl* h_ctl = nullptr;       // pinned host
+  double* partials = nullptr;
+  size_t partials_bytes = 0;
+  uint32_t* tickets = nullptr;    // device [8]
+  double* scal = nullptr;         // device scalars [kMMax*2 + 16]
+  int rows_c128 = 1, rows_c64 = 1;
+  // profiling of the apply kernel
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  double prof_bytes = 0.0;
+};
+
+namespace {
+
+hub_status dev_alloc(hub_basis h, void** p, size_t bytes) {
+  HUB_HIP(hipMalloc(p, bytes == 0 ? 16 : bytes));
+  return HUB_OK;
+}
+
+template <typename T>
+hub_status upload(hub_basis h, T** dst, const std::vector<T>& src) {
+  if (src.empty()) {
+    *dst = nullptr;
+    return HUB_OK;
+  }
+  void* p = nullptr;
+  hub_status s = dev_alloc(h, &p, src.size() * sizeof(T));
+  if (s != HUB_OK) return s;
+  h->allocs.push_back(p);
+  HUB_HIP(hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = static_cast<T*>(p);
+  return HUB_OK;
+}
+
+int pick_rows(const hub_basis h, int prec) {
+  const char* env = std::getenv(prec == 0 ? "HUB_ROWS_C128" : "HUB_ROWS_C64");
+  if (env) {
+    const int r = std::atoi(env);
+    if (r >= 1 && r <= 4) return r;
+  }
+  // largest row count that keeps >= 3 workgroups per CU (256 CUs) and <= 64 KB LDS
+  int best = 1;
+  for (int r = 2; r <= 4; r *= 2) {
+    if (hub::apply_grid(h->D, r) >= 768 && hub::apply_lds_bytes(h->D, prec, 1, r) <= 64 * 1024) best = r;
+  }
+  return best;
+}
+
+hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t blockbuf_bytes) {
+  const size_t need = slot_bytes * static_cast<size_t>(nslots);
+  if (need > h->slots_bytes) {
+    if (h->slots) HUB_HIP(hipFree(h->slots));
+    h->slots = nullptr;
+    h->slots_bytes = 0;
+    HUB_HIP(hipMalloc(&h->slots, need));
+    h->slots_bytes = need;
+  }
+  if (blockbuf_bytes > h->blockbuf_bytes) {
+    if (h->blockbuf) HUB_HIP(hipFree(h->blockbuf));
+    h->blockbuf = nullptr;
+    h->blockbuf_bytes = 0;
+    HUB_HIP(hipMalloc(&h->blockbuf, blockbuf_bytes));
+    h->blockbuf_bytes = blockbuf_bytes;
+  }
+  // partial sums: apply grid * (1 + kObsQ) * nv doubles at most
+  const size_t pb = std::max<size_t>(static_cast<size_t>(h->D.dim_up) * (1 + kObsQ) * kMaxNV,
+                                     static_cast<size_t>(2048) * 2 * 64) * sizeof(double);
+  if (pb > h->partials_bytes) {
+    if (h->partials) HUB_HIP(hipFree(h->partials));
+    h->partials = nullptr;
+    h->partials_bytes = 0;
+    HUB_HIP(hipMalloc(&h->partials, pb));
+    h->partials_bytes = pb;
+  }
+  return HUB_OK;
+}
+
+void coef_for(const hub::Basis& B, double A, double* out /* 2*nc */) {
+  for (size_t c = 0; c < B.classes.size(); ++c) {
+    const double t = B.classes[c].t, d = B.classes[c].d;
+    out[2 * c] = -t * std::cos(A * d);
+    out[2 * c + 1] = -t * std::sin(A * d);
+  }
+}
+
+double pulse_value(const hub_pulse& p, double t) {
+  const double s = t - p.t0;
+  const double env = std::exp(-s * s / (2.0 * p.sigma * p.sigma));
+  if (p.kind == 0) return p.A0 * env * std::sin(p.omega * s);
+  return p.A0 * (std::cos(p.omega * s) - p.b) * env;
+}
+
+hub_status check_pulse(const hub_pulse& p) {
+  if (p.kind != 0 && p.kind != 1) return fail(HUB_E_INVALID, "pulse kind must be 0 or 1");
+  if (!(p.sigma > 0.0) || !std::isfinite(p.A0) || !std::isfinite(p.omega) || !std::isfinite(p.t0) ||
+      !std::isfinite(p.b))
+    return fail(HUB_E_INVALID, "pulse parameters must be finite with sigma > 0");
+  return HUB_OK;
+}
+
+hub_status check_opts(const hub_krylov_opts& o) {
+  if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(HUB_E_INVALID, "opts.tol must be > 0");
+  if (o.m_max < 1 || o.m_max > kMMax) return fail(HUB_E_INVALID, "opts.m_max must be in 1..60");
+  if (o.substeps < 1) return fail(HUB_E_INVALID, "opts.substeps must be >= 1");
+  if (o.reorth != 0) return fail(HUB_E_INVALID, "opts.reorth = 1 is not supported by this build");
+  if (o.m_hint < 0) return fail(HUB_E_INVALID, "opts.m_hint must be >= 0");
+  return HUB_OK;
+}
+
+hub_status check_common(hub_basis h, hub_prec prec, int32_t nvec) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (prec != HUB_C128 && prec != HUB_C64) return fail(HUB_E_INVALID, "unknown precision");
+  if (nvec < 1) return fail(HUB_E_INVALID, "nvec must be >= 1");
+  if (h->device < 0) return fail(HUB_E_DEVICE, "host-only handle (created with device -1)");
+  HUB_HIP(hipSetDevice(h->device));
+  return HUB_OK;
+}
+
+hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof) {
+    if (!h->ev_free.empty()) {
+      e0 = h->ev_free.back().first;
+      e1 = h->ev_free.back().second;
+      h->ev_free.pop_back();
+    } else {
+      HUB_HIP(hipEventCreate(&e0));
+      HUB_HIP(hipEventCreate(&e1));
+    }
+    HUB_HIP(hipEventRecord(e0, L.stream));
+  }
+  HUB_HIP(hub::launch_apply(L));
+  if (h->prof) {
+    HUB_HIP(hipEventRecord(e1, L.stream));
+    h->ev_used.push_back({e0, e1});
+    h->prof_bytes = 2.0 * L.nv * static_cast<double>(h->D.dim) * (L.prec == 0 ? 16.0 : 8.0);
+  }
+  return HUB_OK;
+}
+
+// Group sizes for nvec vectors: powers of two up to 8 whose staged row fits in LDS.
+std::vector<int> groups_for(hub_basis h, int nvec, int prec) {
+  int gmax = kMaxNV;
+  while (gmax > 1 && hub::apply_lds_bytes(h->D, prec, gmax, 1) > 160 * 1024) gmax /= 2;
+  std::vector<int> g;
+  int left = nvec;
+  while (left > 0) {
+    int s = gmax;
+    while (s > left) s /= 2;
+    g.push_back(s);
+    left -= s;
+  }
+  return g;
+}
+
+struct StepReport {
+  int m = 0, status = 0;
+  double eps = 0.0, beta_last = 0.0;
+};
+
+// Runs n_steps Krylov midpoint steps for one group of nv vectors stored in
+// the ABI layout at `user` (vector k at user + k*dim).  coef_mid[n][v][2*nc].
+hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps,
+                     const std::vector<double>& coef_mid, double dt, const hub_krylov_opts& o,
+                     bool want_obs, const std::vector<double>* coef_final, std::vector<double>* obs_out,
+                     std::vector<StepReport>* reports, hipStream_t stream, bool* not_converged,
+                     int* steps_done) {
+  const size_t es = elem_bytes(prec);
+  const int64_t dim = h->D.dim;
+  const size_t vbytes = static_cast<size_t>(dim) * nv * es;
+  const int nc = static_cast<int>(h->B.classes.size());
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  hub_status s = ensure_workspace(h, vbytes, o.m_max, nv > 1 ? vbytes : 0);
+  if (s != HUB_OK) return s;
+
+  void* slot0 = user;
+  if (nv > 1) {
+    slot0 = h->blockbuf;
+    HUB_HIP(hub::launch_interleave(pi, nv, dim, user, slot0, true, stream));
+  }
+  std::vector<void*> ptrs(kMMax + 2, nullptr);
+  ptrs[0] = slot0;
+  for (int k = 1; k <= o.m_max; ++k) ptrs[k] = static_cast<char*>(h->slots) + (k - 1) * vbytes;
+  HUB_HIP(hipMemcpyAsync(h->slot_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice,
+                         stream));
+  // the copy above reads `ptrs` asynchronously: wait before it goes out of scope
+  HUB_HIP(hipStreamSynchronize(stream));
+
+  // device logs
+  const int nobs_rows = want_obs ? n_steps + 1 : 0;
+  const size_t log_bytes = static_cast<size_t>(std::max(1, n_steps)) * o.substeps * nv * sizeof(CombineLog);
+  const size_t obs_bytes = static_cast<size_t>(std::max(1, nobs_rows)) * nv * kObsQ * sizeof(double);
+  void* dlog = nullptr;
+  double* dobs = nullptr;
+  HUB_HIP(hipMalloc(&dlog, log_bytes));
+  if (want_obs) HUB_HIP(hipMalloc(reinterpret_cast<void**>(&dobs), obs_bytes));
+  struct Freer {
+    void* a;
+    void* b;
+    ~Freer() {
+      if (a) (void)hipFree(a);
+      if (b) (void)hipFree(b);
+    }
+  } freer{dlog, dobs};
+
+  StepCtl ctl0{};
+  ctl0.m_max = o.m_max;
+  ctl0.tol = o.tol;
+  ctl0.norm_inf = h->B.norm_inf;
+  HUB_HIP(hipMemcpyAsync(h->ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
+  HUB_HIP(hipStreamSynchronize(stream));
+
+  const double tau = dt / o.substeps;
+  const int rows = pi == 0 ? h->rows_c128 : h->rows_c64;
+  hub::ApplyLaunch L{};
+  L.db = &h->D;
+  L.prec = pi;
+  L.nv = nv;
+  L.rows = rows;
+  L.st = h->st;
+  L.ctl = h->ctl;
+  L.partials = h->partials;
+  L.stream = stream;
+
+  int m_pred = o.m_hint > 0 ? std::min(o.m_hint, o.m_max) : std::min(8, o.m_max);
+  bool first = true;
+  *not_converged = false;
+  *steps_done = 0;
+  for (int n = 0; n < n_steps; ++n) {
+    const double* cf = coef_mid.data() + static_cast<size_t>(n) * nv * 2 * nc;
+    int m_step_max = 0;
+    for (int sub = 0; sub < o.substeps; ++sub) {
+      HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, o.m_max, o.tol, h->B.norm_inf,
+                                     !first, h->partials, stream));
+      first = false;
+      const bool obs_here = want_obs && sub == 0;
+      int j = 0;
+      auto enqueue_iter = [&](int jj) -> hub_status {
+        hub::ApplyLaunch A = L;
+        A.mode = hub::kLanczos;
+        A.obs = obs_here && jj == 0;
+        A.x = ptrs[jj];
+        A.y = ptrs[jj + 1];
+        A.xprev = jj > 0 ? ptrs[jj - 1] : nullptr;
+        A.coef = cf;
+        A.j = jj;
+        hub_status r = launch_apply_timed(h, A);
+        if (r != HUB_OK) return r;
+        HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, stream));
+        return HUB_OK;
+      };
+      for (; j < m_pred && j < o.m_max; ++j) {
+        hub_status r = enqueue_iter(j);
+        if (r != HUB_OK) return r;
+      }
+      while (true) {
+        HUB_HIP(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
+        HUB_HIP(hipStreamSynchronize(stream));
+        if (h->h_ctl->all_done) break;
+        if (j >= o.m_max) return fail(HUB_E_DEVICE, "Krylov loop ended without a decision");
+        hub_status r = enqueue_iter(j);
+        if (r != HUB_OK) return r;
+        ++j;
+      }
+      const int m_used = h->h_ctl->iter;
+      m_step_max = std::max(m_step_max, m_used);
+      const bool maxed = h->h_ctl->any_maxed != 0;
+      HUB_HIP(hub::launch_combine(pi, nv, dim, h->slot_ptrs, h->st, h->ctl, h->partials, stream));
+      CombineLog* lg = static_cast<CombineLog*>(dlog) + (static_cast<size_t>(n) * o.substeps + sub) * nv;
+      HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, lg,
+                                   obs_here ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr, kObsQ,
+                                   stream));
+      if (maxed) break;
+    }
+    // next step's speculative depth: the deepest this step needed, plus one
+    m_pred = std::min(o.m_max, m_step_max + 1);
+    *steps_done = n + 1;
+    // stop at the first step where a vector hit m_max (flag read at the last sync)
+    if (h->h_ctl->any_maxed) {
+      *not_converged = true;
+      break;
+    }
+  }
+  // observables at the final sample time
+  if (want_obs && *steps_done == n_steps) {
+    hub::ApplyLaunch A = L;
+    A.mode = hub::kObsOnly;
+    A.obs = true;
+    A.x = slot0;
+    A.y = nullptr;
+    A.coef = coef_final->data();
+    A.j = 0;
+    HUB_HIP(hub::launch_apply(A));
+    HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, nullptr, dobs + static_cast<size_t>(n_steps) * nv * kObsQ,
+                                 kObsQ, stream));
+  }
+  if (nv > 1) HUB_HIP(hub::launch_interleave(pi, nv, dim, slot0, user, false, stream));
+
+  // copy logs back
+  const int nd = *steps_done;
+  if (reports && nd > 0) {
+    std::vector<CombineLog> lg(static_cast<size_t>(nd) * o.substeps * nv);
+    HUB_HIP(hipMemcpyAsync(lg.data(), dlog, lg.size() * sizeof(CombineLog), hipMemcpyDeviceToHost, stream));
+    HUB_HIP(hipStreamSynchronize(stream));
+    reports->assign(static_cast<size_t>(nd) * nv, StepReport{});
+    for (int n = 0; n < nd; ++n)
+      for (int v = 0; v < nv; ++v) {
+        StepReport& R = (*reports)[static_cast<size_t>(n) * nv + v];
+        R.status = 1;
+        for (int sub = 0; sub < o.substeps; ++sub) {
+          const CombineLog& c = lg[(static_cast<size_t>(n) * o.substeps + sub) * nv + v];
+          R.m = std::max(R.m, static_cast<int>(c.m));
+          R.eps = std::max(R.eps, c.eps);
+          R.beta_last = c.beta_last;
+          if (c.status == 3) R.status = 3;
+          else if (c.status == 2 && R.status != 3) R.status = 2;
+        }
+      }
+  }
+  if (want_obs && obs_out) {
+    obs_out->assign(static_cast<size_t>(n_steps + 1) * nv * kObsQ, 0.0);
+    HUB_HIP(hipMemcpyAsync(obs_out->data(), dobs, obs_out->size() * sizeof(double), hipMemcpyDeviceToHost,
+                           stream));
+  }
+  HUB_HIP(hipStreamSynchronize(stream));
+  return HUB_OK;
+}
+
+void fill_obs(const hub::Basis& B, const double* o /* kObsQ */, const double* coef /* 2*nc */, double t,
+              hub_obs* out) {
+  const int nc = static_cast<int>(B.classes.size());
+  double e = o[0];
+  for (int c = 0; c < nc; ++c) e += coef[2 * c] * o[3 + 2 * c] - coef[2 * c + 1] * o[3 + 2 * c + 1];
+  out->t = t;
+  out->norm = std::sqrt(std::max(0.0, o[2]));
+  out->energy_per_site = e / B.lat.n_sites;
+  out->docc_per_site = o[1] / B.lat.n_sites;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hub_last_error(void) { return g_err.c_str(); }
+
+hub_status hub_pulse_A(const hub_pulse* pulse, double t, double* A) {
+  if (!pulse || !A) return fail(HUB_E_INVALID, "null argument");
+  hub_status s = check_pulse(*pulse);
+  if (s != HUB_OK) return s;
+  *A = pulse_value(*pulse, t);
+  return HUB_OK;
+}
+
+hub_status hub_basis_create(const hub_lattice* lat, int32_t n_up, int32_t n_dn, int32_t device,
+                            hub_basis* out) {
+  if (!out) return fail(HUB_E_INVALID, "null output handle");
+  *out = nullptr;
+  if (!lat) return fail(HUB_E_INVALID, "null lattice");
+  if (lat->n_bonds < 0) return fail(HUB_E_INVALID, "negative bond count");
+  if (lat->n_bonds > 0 && (!lat->bond_i || !lat->bond_j || !lat->bond_t || !lat->bond_dx))
+    return fail(HUB_E_INVALID, "null bond array");
+  if (lat->n_sites < 1 || lat->n_sites > hub::kMaxSites) return fail(HUB_E_INVALID, "n_sites must be in 1..16");
+  hub::Lattice L;
+  L.n_sites = lat->n_sites;
+  L.U = lat->U;
+  for (int k = 0; k < lat->n_bonds; ++k) {
+    L.bi.push_back(lat->bond_i[k]);
+    L.bj.push_back(lat->bond_j[k]);
+    L.bt.push_back(lat->bond_t[k]);
+    L.bdx.push_back(lat->bond_dx[k]);
+  }
+  if (lat->onsite) L.onsite.assign(lat->onsite, lat->onsite + lat->n_sites);
+  if (device != -1) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(HUB_E_DEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(HUB_E_INVALID, "device index out of range");
+  }
+
+  hub_basis h = new (std::nothrow) hub_basis_s();
+  if (!h) return fail(HUB_E_NOMEM, "host allocation failed");
+  bool sector_err = false;
+  const std::string msg = hub::build_basis(L, n_up, n_dn, h->B, sector_err);
+  if (!msg.empty()) {
+    delete h;
+    return fail(sector_err ? HUB_E_SECTOR : HUB_E_INVALID, msg);
+  }
+  h->device = device;
+  if (device == -1) {  // host-only handle: tables, no device state
+    *out = h;
+    g_err.clear();
+    return HUB_OK;
+  }
+  auto cleanup = [&](hub_status s) {
+    hub_basis_destroy(h);
+    return s;
+  };
+  if (hipSetDevice(device) != hipSuccess) return cleanup(fail(HUB_E_DEVICE, "hipSetDevice failed"));
+  DevBasis& D = h->D;
+  const hub::Basis& B = h->B;
+  D.dim_up = B.up.dim;
+  D.dim_dn = B.dn.dim;
+  D.dim = B.dim;
+  D.nc = static_cast<int>(B.classes.size());
+  D.n_sites = B.lat.n_sites;
+  D.U = B.lat.U;
+  hub_status s = HUB_OK;
+  if ((s = upload(h, &D.up_bits, B.up.states)) != HUB_OK) return cleanup(s);
+  if ((s = upload(h, &D.dn_bits, B.dn.states)) != HUB_OK) return cleanup(s);
+  if ((s = upload(h, &D.eps_up, B.up.onsite)) != HUB_OK) return cleanup(s);
+  if ((s = upload(h, &D.eps_dn, B.dn.onsite)) != HUB_OK) return cleanup(s);
+  if ((s = upload(h, &D.up_cls_ptr, B.up.cls_ptr)) != HUB_OK) return cleanup(s);
+  std::vector<uint32_t> uh = B.up.hops;
+  if (uh.empty()) uh.push_back(0);
+  if ((s = upload(h, &D.up_hops, uh)) != HUB_OK) return cleanup(s);
+  if ((s = upload(h, &D.dn_cls_ptr, B.dn.cls_ptr)) != HUB_OK) return cleanup(s);
+  std::vector<uint32_t> dh = B.dn.hops;
+  if (dh.empty()) dh.push_back(0);
+  if ((s = upload(h, &D.dn_hops, dh)) != HUB_OK) return cleanup(s);
+  std::vector<uint16_t> tab = B.dn.tab;
+  if (tab.empty()) tab.push_back(0);
+  if ((s = upload(h, &D.dn_tab, tab)) != HUB_OK) return cleanup(s);
+  for (int c = 0; c <= kMaxClasses; ++c)
+    D.dn_slot_begin[c] = c < static_cast<int>(B.dn.slot_begin.size()) ? B.dn.slot_begin[c] : B.dn.slot_begin.back();
+  D.up_max_hops = B.up.max_hops;
+  D.dn_max_hops = B.dn.max_hops;
+
+  if (hipMalloc(reinterpret_cast<void**>(&h->slot_ptrs), (kMMax + 2) * sizeof(void*)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&h->st), kMaxNV * sizeof(VecState)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&h->ctl), sizeof(StepCtl)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&h->tickets), 8 * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&h->scal), (2 * kMMax + 64) * sizeof(double) * 2) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(HUB_E_NOMEM, "workspace allocation failed"));
+  if (hipMemset(h->ctl, 0, sizeof(StepCtl)) != hipSuccess || hipMemset(h->tickets, 0, 8 * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(h->st, 0, kMaxNV * sizeof(VecState)) != hipSuccess)
+    return cleanup(fail(HUB_E_DEVICE, "workspace initialisation failed"));
+  h->rows_c128 = pick_rows(h, 0);
+  h->rows_c64 = pick_rows(h, 1);
+  *out = h;
+  g_err.clear();
+  return HUB_OK;
+}
+
+void hub_basis_destroy(hub_basis h) {
+  if (!h) return;
+  if (h->device < 0) {
+    delete h;
+    return;
+  }
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->slots) (void)hipFree(h->slots);
+  if (h->blockbuf) (void)hipFree(h->blockbuf);
+  if (h->slot_ptrs) (void)hipFree(h->slot_ptrs);
+  if (h->st) (void)hipFree(h->st);
+  if (h->ctl) (void)hipFree(h->ctl);
+  if (h->tickets) (void)hipFree(h->tickets);
+  if (h->scal) (void)hipFree(h->scal);
+  if (h->partials) (void)hipFree(h->partials);
+  if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  for (auto& e : h->ev_used) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : h->ev_free) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  delete h;
+}
+
+hub_status hub_basis_info(hub_basis h, int64_t* dim, int32_t* dim_up, int32_t* dim_dn) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (dim) *dim = h->B.dim;
+  if (dim_up) *dim_up = h->B.up.dim;
+  if (dim_dn) *dim_dn = h->B.dn.dim;
+  return HUB_OK;
+}
+
+hub_status hub_basis_states(hub_basis h, uint32_t* up_bits, uint32_t* dn_bits) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (up_bits) std::memcpy(up_bits, h->B.up.states.data(), h->B.up.states.size() * sizeof(uint32_t));
+  if (dn_bits) std::memcpy(dn_bits, h->B.dn.states.data(), h->B.dn.states.size() * sizeof(uint32_t));
+  return HUB_OK;
+}
+
+hub_status hub_basis_classes(hub_basis h, double* t, double* d, int32_t* n_classes, double* norm_inf) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  const int nc = static_cast<int>(h->B.classes.size());
+  for (int c = 0; c < nc; ++c) {
+    if (t) t[c] = h->B.classes[c].t;
+    if (d) d[c] = h->B.classes[c].d;
+  }
+  if (n_classes) *n_classes = nc;
+  if (norm_inf) *norm_inf = h->B.norm_inf;
+  return HUB_OK;
+}
+
+hub_status hub_basis_hops(hub_basis h, int32_t spin, int32_t* ptr, int32_t* src, int32_t* sgn, int32_t* cls,
+                          int64_t* n_hops) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (spin != 0 && spin != 1) return fail(HUB_E_INVALID, "spin must be 0 or 1");
+  const hub::SpinTable& T = spin == 0 ? h->B.up : h->B.dn;
+  const int nc = static_cast<int>(h->B.classes.size());
+  if (n_hops) *n_hops = static_cast<int64_t>(T.hops.size());
+  if (ptr) {
+    for (int r = 0; r < T.dim; ++r) ptr[r] = T.cls_ptr[static_cast<size_t>(r) * (nc + 1)];
+    ptr[T.dim] = static_cast<int32_t>(T.hops.size());
+  }
+  for (int r = 0; r < T.dim; ++r)
+    for (int c = 0; c < nc; ++c) {
+      const int b = T.cls_ptr[static_cast<size_t>(r) * (nc + 1) + c];
+      const int e = T.cls_ptr[static_cast<size_t>(r) * (nc + 1) + c + 1];
+      for (int k = b; k < e; ++k) {
+        if (src) src[k] = static_cast<int32_t>(T.hops[k] & 0xFFFFu);
+        if (sgn) sgn[k] = (T.hops[k] >> 31) ? -1 : 1;
+        if (cls) cls[k] = c;
+      }
+    }
+  return HUB_OK;
+}
+
+hub_status hub_apply_H(hub_basis h, const double* A, hub_prec prec, int32_t nvec, const void* x, void* y,
+                       void* stream) {
+  hub_status s = check_common(h, prec, nvec);
+  if (s != HUB_OK) return s;
+  if (!A || !x || !y) return fail(HUB_E_INVALID, "null argument");
+  if (x == y) return fail(HUB_E_INVALID, "x and y must be distinct buffers");
+  for (int k = 0; k < nvec; ++k)
+    if (!std::isfinite(A[k])) return fail(HUB_E_INVALID, "non-finite A");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const size_t es = elem_bytes(prec);
+  const int64_t dim = h->D.dim;
+  const int nc = h->D.nc;
+  const std::vector<int> groups = groups_for(h, nvec, pi);
+  int gmax = 1;
+  for (int g : groups) gmax = std::max(gmax, g);
+  s = ensure_workspace(h, static_cast<size_t>(dim) * gmax * es, 1, gmax > 1 ? static_cast<size_t>(dim) * gmax * es : 0);
+  if (s != HUB_OK) return s;
+  int k0 = 0;
+  for (int nv : groups) {
+    std::vector<double> cf(static_cast<size_t>(2) * kMaxNV * kMaxClasses, 0.0);
+    for (int v = 0; v < nv; ++v) coef_for(h->B, A[k0 + v], cf.data() + static_cast<size_t>(2) * v * nc);
+    const char* xin = static_cast<const char*>(x) + static_cast<size_t>(k0) * dim * es;
+    char* yout = static_cast<char*>(y) + static_cast<size_t>(k0) * dim * es;
+    hub::ApplyLaunch L{};
+    L.db = &h->D;
+    L.prec = pi;
+    L.nv = nv;
+    L.rows = pi == 0 ? h->rows_c128 : h->rows_c64;
+    L.mode = hub::kPlain;
+    L.coef = cf.data();
+    L.stream = st;
+    if (nv == 1) {
+      L.x = xin;
+      L.y = yout;
+      s = launch_apply_timed(h, L);
+      if (s != HUB_OK) return s;
+    } else {
+      HUB_HIP(hub::launch_interleave(pi, nv, dim, xin, h->blockbuf, true, st));
+      L.x = h->blockbuf;
+      L.y = h->slots;
+      s = launch_apply_timed(h, L);
+      if (s != HUB_OK) return s;
+      HUB_HIP(hub::launch_interleave(pi, nv, dim, h->slots, yout, false, st));
+    }
+    k0 += nv;
+  }
+  return HUB_OK;
+}
+
+hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t nvec, const void* v,
+                           hub_obs* out, double* site_docc, void* stream) {
+  hub_status s = check_common(h, prec, nvec);
+  if (s != HUB_OK) return s;
+  if (!A || !v || !out) return fail(HUB_E_INVALID, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const size_t es = elem_bytes(prec);
+  const int64_t dim = h->D.dim;
+  const int nc = h->D.nc;
+  s = ensure_workspace(h, 16, 1, 0);
+  if (s != HUB_OK) return s;
+  StepCtl ctl0{};
+  HUB_HIP(hipMemcpyAsync(h->ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, st));
+  HUB_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < nvec; ++k) {
+    std::vector<double> cf(static_cast<size_t>(2) * kMaxNV * kMaxClasses, 0.0);
+    coef_for(h->B, A[k], cf.data());
+    hub::ApplyLaunch L{};
+    L.db = &h->D;
+    L.prec = pi;
+    L.nv = 1;
+    L.rows = pi == 0 ? h->rows_c128 : h->rows_c64;
+    L.mode = hub::kObsOnly;
+    L.obs = true;
+    L.x = static_cast<const char*>(v) + static_cast<size_t>(k) * dim * es;
+    L.coef = cf.data();
+    L.st = h->st;
+    L.ctl = h->ctl;
+    L.partials = h->partials;
+    L.stream = st;
+    HUB_HIP(hub::launch_apply(L));
+    double o[kObsQ];
+    HUB_HIP(hipMemcpyAsync(o, reinterpret_cast<char*>(h->st) + offsetof(VecState, obs), sizeof(o),
+                           hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    fill_obs(h->B, o, cf.data(), 0.0, &out[k]);
+    out[k].t = 0.0;
+    if (site_docc) {
+      HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, h->scal, h->partials, h->tickets + 4, st));
+      HUB_HIP(hipMemcpyAsync(site_docc + static_cast<size_t>(k) * h->D.n_sites, h->scal,
+                             h->D.n_sites * sizeof(double), hipMemcpyDeviceToHost, st));
+      HUB_HIP(hipStreamSynchronize(st));
+    }
+  }
+  return HUB_OK;
+}
+
+static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inout, int n_steps,
+                          const std::vector<std::vector<double>>& A_mid /* [nvec][n_steps] */,
+                          const std::vector<std::vector<double>>* A_sample /* [nvec][n_steps+1] */,
+                          double t_start, double dt, const hub_krylov_opts& o, hub_obs* obs,
+                          hub_step_info* log, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const size_t es = elem_bytes(prec);
+  const int64_t dim = h->D.dim;
+  const int nc = h->D.nc;
+  const std::vector<int> groups = groups_for(h, nvec, pi);
+  bool any_nc = false;
+  int k0 = 0;
+  for (int nv : groups) {
+    std::vector<double> cm(static_cast<size_t>(n_steps) * nv * 2 * nc);
+    for (int n = 0; n < n_steps; ++n)
+      for (int v = 0; v < nv; ++v)
+        coef_for(h->B, A_mid[k0 + v][n], cm.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
+    const bool want_obs = obs != nullptr && A_sample != nullptr;
+    std::vector<double> cfin(static_cast<size_t>(2) * kMaxNV * kMaxClasses, 0.0);
+    if (want_obs)
+      for (int v = 0; v < nv; ++v)
+        coef_for(h->B, (*A_sample)[k0 + v][n_steps], cfin.data() + static_cast<size_t>(2) * v * nc);
+    std::vector<double> obs_raw;
+    std::vector<StepReport> reps;
+    bool ncv = false;
+    int done = 0;
+    char* user = static_cast<char*>(v_inout) + static_cast<size_t>(k0) * dim * es;
+    hub_status s = run_group(h, prec, nv, user, n_steps, cm, dt, o, want_obs, &cfin, &obs_raw, &reps, st, &ncv,
+                             &done);
+    if (s != HUB_OK) return s;
+    if (log)
+      for (int n = 0; n < done; ++n)
+        for (int v = 0; v < nv; ++v) {
+          const StepReport& R = reps[static_cast<size_t>(n) * nv + v];
+          hub_step_info& I = log[static_cast<size_t>(n) * nvec + k0 + v];
+          I.m_used = R.m;
+          I.substeps = o.substeps;
+          I.converged = R.status != 3;
+          I.breakdown = R.status == 2;
+          I.err_est = R.eps;
+          I.beta_last = R.beta_last;
+        }
+    if (want_obs) {
+      for (int n = 0; n <= n_steps; ++n)
+        for (int v = 0; v < nv; ++v) {
+          hub_obs& O = obs[static_cast<size_t>(n) * nvec + k0 + v];
+          if (n > done || (n == n_steps && done < n_steps)) {
+            O = hub_obs{t_start + n * dt, NAN, NAN, NAN};
+            continue;
+          }
+          double cs[2 * kMaxClasses];
+          coef_for(h->B, (*A_sample)[k0 + v][n], cs);
+          fill_obs(h->B, obs_raw.data() + (static_cast<size_t>(n) * nv + v) * kObsQ, cs, t_start + n * dt, &O);
+        }
+    }
+    any_nc |= ncv;
+    if (ncv) break;
+    k0 += nv;
+  }
+  if (any_nc) return fail(HUB_E_NOT_CONVERGED, "a Krylov step reached m_max before the tolerance");
+  return HUB_OK;
+}
+
+hub_status hub_krylov_expm_step(hub_basis h, const double* A_mid, double dt, const hub_krylov_opts* opts,
+                                hub_prec prec, int32_t nvec, void* v_inout, hub_step_info* info, void* stream) {
+  hub_status s = check_common(h, prec, nvec);
+  if (s != HUB_OK) return s;
+  if (!A_mid || !opts || !v_inout) return fail(HUB_E_INVALID, "null argument");
+  if ((s = check_opts(*opts)) != HUB_OK) return s;
+  if (!std::isfinite(dt)) return fail(HUB_E_INVALID, "non-finite dt");
+  std::vector<std::vector<double>> am(nvec, std::vector<double>(1));
+  for (int k = 0; k < nvec; ++k) {
+    if (!std::isfinite(A_mid[k])) return fail(HUB_E_INVALID, "non-finite A_mid");
+    am[k][0] = A_mid[k];
+  }
+  return run_all(h, prec, nvec, v_inout, 1, am, nullptr, 0.0, dt, *opts, nullptr, info, stream);
+}
+
+hub_status hub_propagate(hub_basis h, const hub_pulse* pulses, double t_start, double dt, int32_t n_steps,
+                         const hub_krylov_opts* opts, hub_prec prec, int32_t nvec, void* v_inout, hub_obs* obs,
+                         hub_step_info* log, void* stream) {
+  hub_status s = check_common(h, prec, nvec);
+  if (s != HUB_OK) return s;
+  if (!pulses || !opts || !v_inout) return fail(HUB_E_INVALID, "null argument");
+  if (n_steps < 0) return fail(HUB_E_INVALID, "n_steps must be >= 0");
+  if (!std::isfinite(dt) || !std::isfinite(t_start)) return fail(HUB_E_INVALID, "non-finite time");
+  if ((s = check_opts(*opts)) != HUB_OK) return s;
+  for (int k = 0; k < nvec; ++k)
+    if ((s = check_pulse(pulses[k])) != HUB_OK) return s;
+  std::vector<std::vector<double>> am(nvec, std::vector<double>(n_steps)), as(nvec, std::vector<double>(n_steps + 1));
+  for (int k = 0; k < nvec; ++k) {
+    for (int n = 0; n < n_steps; ++n) am[k][n] = pulse_value(pulses[k], t_start + n * dt + 0.5 * dt);
+    for (int n = 0; n <= n_steps; ++n) as[k][n] = pulse_value(pulses[k], t_start + n * dt);
+  }
+  return run_all(h, prec, nvec, v_inout, n_steps, am, &as, t_start, dt, *opts, obs, log, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Ground state: restarted Lanczos with full reorthogonalisation (classical
+// Gram-Schmidt applied twice), complex double; Ritz pairs from the
+// tridiagonal by Jacobi rotations on the host.
+namespace {
+
+struct GSBufs {
+  std::vector<void*> V;  // device vectors
+  void** Vdev = nullptr;
+  double2* coef = nullptr;
+  double2* coef2 = nullptr;
+};
+
+hub_status gs_lanczos(hub_basis h, double A, hipStream_t st, GSBufs& G, int kmax, const void* deflate,
+                      double tol_res, std::vector<double>& ritz, std::vector<double>& svec, int& kused,
+                      double& resid) {
+  const int64_t dim = h->D.dim;
+  std::vector<double> cf(static_cast<size_t>(2) * kMaxNV * kMaxClasses, 0.0);
+  coef_for(h->B, A, cf.data());
+  std::vector<double> alpha, beta;
+  // vectors used for orthogonalisation: [deflate] + V[0..j]
+  std::vector<void*> basis;
+  if (deflate) basis.push_back(const_cast<void*>(deflate));
+  int j = 0;
+  resid = INFINITY;
+  for (j = 0; j < kmax; ++j) {
+    basis.push_back(G.V[j]);
+    void* w = G.V[j + 1];
+    hub::ApplyLaunch L{};
+    L.db = &h->D;
+    L.prec = 0;
+    L.nv = 1;
+    L.rows = h->rows_c128;
+    L.mode = hub::kPlain;
+    L.coef = cf.data();
+    L.x = G.V[j];
+    L.y = w;
+    L.stream = st;
+    HUB_HIP(hub::launch_apply(L));
+    HUB_HIP(hipMemcpyAsync(G.Vdev, basis.data(), basis.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    double a_j = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int nb = static_cast<int>(basis.size());
+      for (int k0 = 0; k0 < nb; k0 += 64) {
+        const int kk = std::min(64, nb - k0);
+        HUB_HIP(hub::launch_multidot(dim, reinterpret_cast<const double2* const*>(G.Vdev) + k0, kk,
+                                     static_cast<const double2*>(w), G.coef + k0, h->partials, h->tickets, st));
+      }
+      for (int k0 = 0; k0 < nb; k0 += 64) {
+        const int kk = std::min(64, nb - k0);
+        HUB_HIP(hub::launch_multiaxpy(dim, reinterpret_cast<const double2* const*>(G.Vdev) + k0, kk, G.coef + k0,
+                                      static_cast<double2*>(w), st));
+      }
+      double2 cj;
+      HUB_HIP(hipMemcpyAsync(&cj, G.coef + nb - 1, sizeof(double2), hipMemcpyDeviceToHost, st));
+      HUB_HIP(hipStreamSynchronize(st));
+      a_j += cj.x;
+    }
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(w), h->scal, h->partials, h->tickets + 1, st));
+    double n2 = 0.0;
+    HUB_HIP(hipMemcpyAsync(&n2, h->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    const double b_j = std::sqrt(n2);
+    alpha.push_back(a_j);
+    beta.push_back(b_j);
+    // Ritz values of T_{j+1}
+    const int m = j + 1;
+    std::vector<double> T(static_cast<size_t>(m) * m, 0.0), vals, vecs;
+    for (int i = 0; i < m; ++i) {
+      T[static_cast<size_t>(i) * m + i] = alpha[i];
+      if (i + 1 < m) T[static_cast<size_t>(i) * m + i + 1] = T[static_cast<size_t>(i + 1) * m + i] = beta[i];
+    }
+    hub::sym_eig(m, T, vals, vecs);
+    resid = b_j * std::fabs(vecs[static_cast<size_t>(m - 1) * m + 0]);
+    ritz = vals;
+    svec.assign(m, 0.0);
+    for (int i = 0; i < m; ++i) svec[i] = vecs[static_cast<size_t>(i) * m + 0];
+    kused = m;
+    if (resid < tol_res || b_j < 1e-14 * h->B.norm_inf || m == dim - (deflate ? 1 : 0)) break;
+    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(w), h->scal, double2{0, 0}, st));
+  }
+  return HUB_OK;
+}
+
+// x = sum_i s_i V[i] into `out`
+hub_status gs_ritz_vector(hub_basis h, hipStream_t st, GSBufs& G, const std::vector<double>& s, void* out) {
+  const int64_t dim = h->D.dim;
+  const int m = static_cast<int>(s.size());
+  HUB_HIP(hipMemsetAsync(out, 0, dim * 16, st));
+  std::vector<double2> c(m);
+  for (int i = 0; i < m; ++i) c[i] = double2{-s[i], 0.0};  // multiaxpy subtracts
+  HUB_HIP(hipMemcpyAsync(G.coef, c.data(), m * sizeof(double2), hipMemcpyHostToDevice, st));
+  HUB_HIP(hipMemcpyAsync(G.Vdev, G.V.data(), m * sizeof(void*), hipMemcpyHostToDevice, st));
+  HUB_HIP(hipStreamSynchronize(st));
+  for (int k0 = 0; k0 < m; k0 += 64) {
+    const int kk = std::min(64, m - k0);
+    HUB_HIP(hub::launch_multiaxpy(dim, reinterpret_cast<const double2* const*>(G.Vdev) + k0, kk, G.coef + k0,
+                                  static_cast<double2*>(out), st));
+  }
+  // normalise
+  HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(out), h->scal, h->partials, h->tickets + 1, st));
+  HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(out), h->scal, double2{0, 0}, st));
+  HUB_HIP(hipStreamSynchronize(st));
+  return HUB_OK;
+}
+
+}  // namespace
+
+hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, void* v_out, double* E0,
+                            double* gap, void* stream) {
+  hub_status s = check_common(h, HUB_C128, 1);
+  if (s != HUB_OK) return s;
+  if (!v_out || !E0) return fail(HUB_E_INVALID, "null argument");
+  if (!std::isfinite(A)) return fail(HUB_E_INVALID, "non-finite A");
+  const double tol = opts ? opts->tol : 1e-12;
+  int kmax = opts ? opts->m_max : 60;
+  if (!(tol > 0.0)) return fail(HUB_E_INVALID, "opts.tol must be > 0");
+  if (kmax < 2) return fail(HUB_E_INVALID, "opts.m_max must be >= 2");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t dim = h->D.dim;
+  kmax = static_cast<int>(std::min<int64_t>(kmax, dim));
+  s = ensure_workspace(h, static_cast<size_t>(dim) * 16, kmax + 1, 0);
+  if (s != HUB_OK) return s;
+  GSBufs G;
+  for (int k = 0; k <= kmax; ++k) G.V.push_back(static_cast<char*>(h->slots) + static_cast<size_t>(k) * dim * 16);
+  void* extra = nullptr;
+  HUB_HIP(hipMalloc(&extra, (kmax + 2) * (sizeof(void*) + 2 * sizeof(double2))));
+  struct Fr {
+    void* p;
+    ~Fr() { (void)hipFree(p); }
+  } fr{extra};
+  G.Vdev = static_cast<void**>(extra);
+  G.coef = reinterpret_cast<double2*>(static_cast<char*>(extra) + (kmax + 2) * sizeof(void*));
+  G.coef2 = G.coef + (kmax + 2);
+
+  // seeded random start (host), normalised on the device
+  auto random_start = [&](void* dst, uint64_t seed) -> hub_status {
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<double2> x(static_cast<size_t>(dim));
+    for (auto& e : x) e = double2{nd(rng), nd(rng)};
+    HUB_HIP(hipMemcpy(dst, x.data(), x.size() * sizeof(double2), hipMemcpyHostToDevice));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(dst), h->scal, h->partials, h->tickets + 1, st));
+    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(dst), h->scal, double2{0, 0}, st));
+    return HUB_OK;
+  };
+  const double tol_res = tol * h->B.norm_inf;
+  s = random_start(G.V[0], 0x13498ULL);
+  if (s != HUB_OK) return s;
+  std::vector<double> ritz, svec;
+  int kused = 0;
+  double resid = INFINITY, e0 = 0.0;
+  bool conv = false;
+  for (int restart = 0; restart < 200; ++restart) {
+    s = gs_lanczos(h, A, st, G, kmax, nullptr, tol_res, ritz, svec, kused, resid);
+    if (s != HUB_OK) return s;
+    e0 = ritz[0];
+    s = gs_ritz_vector(h, st, G, svec, v_out);
+    if (s != HUB_OK) return s;
+    if (resid < tol_res) {
+      conv = true;
+      break;
+    }
+    HUB_HIP(hipMemcpyAsync(G.V[0], v_out, dim * 16, hipMemcpyDeviceToDevice, st));
+  }
+  if (!conv) return fail(HUB_E_NOT_CONVERGED, "ground-state Lanczos did not reach the tolerance");
+  // phase: largest-modulus component (lowest index within 1e-12 of the max) real positive
+  HUB_HIP(hub::launch_absmax(dim, static_cast<const double2*>(v_out), h->scal, h->partials, h->tickets + 2, st));
+  double mx2 = 0.0;
+  HUB_HIP(hipMemcpyAsync(&mx2, h->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  HUB_HIP(hipStreamSynchronize(st));
+  const double th = mx2 * (1.0 - 1e-12) * (1.0 - 1e-12);
+  HUB_HIP(hipMemcpy(h->scal + 1, &th, sizeof(double), hipMemcpyHostToDevice));
+  HUB_HIP(hub::launch_first_above(dim, static_cast<const double2*>(v_out), h->scal + 1,
+                                  reinterpret_cast<int64_t*>(h->scal + 2), reinterpret_cast<int64_t*>(h->partials),
+                                  h->tickets + 3, st));
+  int64_t kmaxidx = 0;
+  HUB_HIP(hipMemcpyAsync(&kmaxidx, h->scal + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HUB_HIP(hipStreamSynchronize(st));
+  double2 comp;
+  HUB_HIP(hipMemcpy(&comp, static_cast<double2*>(v_out) + kmaxidx, sizeof(double2), hipMemcpyDeviceToHost));
+  const double mag = std::hypot(comp.x, comp.y);
+  HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(v_out), nullptr, double2{comp.x / mag, -comp.y / mag}, st));
+  *E0 = e0;
+  // gap: lowest Ritz value of H restricted to the complement of the ground state
+  double g = INFINITY;
+  if (dim > 1) {
+    s = random_start(G.V[0], 0x5eedULL);
+    if (s != HUB_OK) return s;
+    // remove the ground-state component of the start vector
+    HUB_HIP(hipMemcpyAsync(G.Vdev, &v_out, sizeof(void*), hipMemcpyHostToDevice, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    HUB_HIP(hub::launch_multidot(dim, reinterpret_cast<const double2* const*>(G.Vdev), 1,
+                                 static_cast<const double2*>(G.V[0]), G.coef, h->partials, h->tickets, st));
+    HUB_HIP(hub::launch_multiaxpy(dim, reinterpret_cast<const double2* const*>(G.Vdev), 1, G.coef,
+                                  static_cast<double2*>(G.V[0]), st));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(G.V[0]), h->scal, h->partials, h->tickets + 1, st));
+    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(G.V[0]), h->scal, double2{0, 0}, st));
+    double r1 = INFINITY;
+    for (int restart = 0; restart < 20; ++restart) {
+      s = gs_lanczos(h, A, st, G, kmax, v_out, 1e-6 * h->B.norm_inf, ritz, svec, kused, r1);
+      if (s != HUB_OK) return s;
+      if (r1 < 1e-6 * h->B.norm_inf) break;
+      void* tmp = G.V[kmax];  // Ritz vector into the spare slot, then restart from it
+      s = gs_ritz_vector(h, st, G, svec, tmp);
+      if (s != HUB_OK) return s;
+      HUB_HIP(hipMemcpyAsync(G.V[0], tmp, dim * 16, hipMemcpyDeviceToDevice, st));
+    }
+    g = ritz[0] - e0;
+  }
+  HUB_HIP(hipStreamSynchronize(st));
+  if (gap) *gap = g;
+  if (g < 1e-8 * h->B.norm_inf) return fail(HUB_E_DEGENERATE, "ground state is degenerate within 1e-8 |H|");
+  return HUB_OK;
+}
+
+// ---------------------------------------------------------------------------
+hub_status hub_profile_enable(hub_basis h, int32_t on) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  h->prof = on != 0;
+  return HUB_OK;
+}
+
+hub_status hub_profile_read(hub_basis h, int64_t* launches, double* total_ms, double* bytes_per_launch) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  HUB_HIP(hipSetDevice(h->device));
+  HUB_HIP(hipDeviceSynchronize());
+  double tot = 0.0;
+  for (auto& e : h->ev_used) {
+    float ms = 0.0f;
+    HUB_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    tot += ms;
+    h->ev_free.push_back(e);
+  }
+  if (launches) *launches = static_cast<int64_t>(h->ev_used.size());
+  if (total_ms) *total_ms = tot;
+  if (bytes_per_launch) *bytes_per_launch = h->prof_bytes;
+  h->ev_used.clear();
+  return HUB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// Device data structures and launchers of the HIP kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "basis.h"
+
+namespace hub {
+
+constexpr int kMMax = 60;                       // largest Krylov dimension (one wavefront)
+constexpr int kObsQ = 3 + 2 * kMaxClasses;      // <D>, docc, |x|^2, (Re, Im) <x|K_c|x>
+constexpr int kMaxNV = 8;                       // vectors per interleaved block
+constexpr int kBlock = 256;                     // threads per workgroup
+
+// Krylov state of one vector during one step, device resident.
+struct VecState {
+  double alpha[kMMax];       // T_jj
+  double beta[kMMax];        // T_{j+1,j}
+  double scale[kMMax + 1];   // v_k = scale[k] * u_k (u_k stored unnormalised)
+  double y[2 * kMMax];       // y^(j) = exp(-i tau T_j) e_1 of the last iteration
+  double beta0;              // |v| at the step start
+  double eps;                // a-posteriori estimate of the last iteration
+  double tau;                // step length of the current Krylov step
+  int32_t m;                 // Krylov vectors in use (iterations done)
+  int32_t status;            // 0 running, 1 converged, 2 invariant subspace, 3 hit m_max
+  double obs[kObsQ];         // observables of the step's first vector (unnormalised)
+  double site[kMaxSites];    // site-resolved double occupation
+};
+
+struct StepCtl {
+  int32_t all_done;          // every vector of the block has stopped
+  int32_t iter;              // Lanczos iterations completed in this step
+  int32_t m_max;
+  int32_t any_maxed;         // some vector reached m_max in this step
+  double tol;
+  double norm_inf;
+  uint32_t ticket[4];        // last-workgroup counters (apply, update, combine, norm)
+};
+
+// Device copy of a basis.
+struct DevBasis {
+  int dim_up = 0, dim_dn = 0, nc = 0, n_sites = 0;
+  int64_t dim = 0;
+  double U = 0.0;
+  uint32_t* up_bits = nullptr;
+  uint32_t* dn_bits = nullptr;
+  double* eps_up = nullptr;      // null if no on-site energies
+  double* eps_dn = nullptr;
+  int32_t* up_cls_ptr = nullptr; // [dim_up*(nc+1)]
+  uint32_t* up_hops = nullptr;
+  int32_t* dn_cls_ptr = nullptr; // [dim_dn*(nc+1)]
+  uint32_t* dn_hops = nullptr;
+  uint16_t* dn_tab = nullptr;    // lane-major padded table
+  int dn_slot_begin[kMaxClasses + 1] = {0};
+  int up_max_hops = 0, dn_max_hops = 0;
+};
+
+enum ApplyMode : int {
+  kPlain = 0,     // y = H x
+  kLanczos = 1,   // y = s_j H u_j - beta_{j-1} s_{j-1} u_{j-1}, alpha_j reduced
+  kObsOnly = 2,   // observables of x, no y
+};
+
+struct ApplyLaunch {
+  const DevBasis* db;
+  int prec;              // 0 = c128, 1 = c64
+  int nv;                // vectors interleaved per (a, b): 1, 2, 4, 8
+  int rows;              // rows of the tile per workgroup
+  int mode;
+  bool obs;              // also accumulate observables of x (Lanczos/obs modes)
+  const void* x;
+  void* y;
+  const void* xprev;     // Lanczos: u_{j-1} (null at j = 0)
+  const double* coef;    // host [nv][nc] complex pairs (copied into the launch arguments)
+  VecState* st;          // device [nv] (Lanczos/obs)
+  StepCtl* ctl;
+  int j;                 // Lanczos iteration (0-based)
+  double* partials;      // device scratch [grid * nq * nv]
+  hipStream_t stream;
+};
+
+// Each launcher returns the hipError_t of its launch.
+hipError_t launch_apply(const ApplyLaunch& L, int* grid_out = nullptr);
+int apply_grid(const DevBasis& db, int rows);
+size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows);
+
+// u_next = w - alpha_j s_j u_j (in place in w), beta_j = |u_next|, small
+// exponential and stopping rule.  w and u_next may be the same buffer.
+hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, VecState* st,
+                         StepCtl* ctl, int j, double* partials, hipStream_t s);
+
+// v = beta0 sum_k y_k s_k u_k over the m_v vectors of each vector v (in place
+// into slot 0), then |v|^2 for the next step's beta0.
+hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, VecState* st,
+                          StepCtl* ctl, double* partials, hipStream_t s);
+
+// beta0 = |v| and scale[0] = 1/beta0 for each vector; resets the step state.
+hipError_t launch_step_begin(int prec, int nv, int64_t n, const void* v, VecState* st,
+                             StepCtl* ctl, double tau, int m_max, double tol, double norm_inf,
+                             bool norm_known, double* partials, hipStream_t s);
+
+struct CombineLog {
+  int32_t m, status;
+  double eps, beta_last;
+};
+
+// Copies the finished step's Krylov report and first-apply observables.
+hipError_t launch_step_log(int nv, VecState* st, StepCtl* ctl, void* log, double* obs_log, int nobs,
+                           hipStream_t s);
+
+// Site-resolved double occupation sum_k n_{i up} n_{i down} |x_k|^2 of one vector.
+hipError_t launch_site_docc(int prec, const DevBasis& db, const void* x, double* out, double* partials,
+                            uint32_t* ticket, hipStream_t s);
+
+// Layout changes between [v][k] (ABI) and [k][v] (interleaved block).
+hipError_t launch_interleave(int prec, int nv, int64_t n, const void* src, void* dst, bool to_block,
+                             hipStream_t s);
+
+// BLAS-1 helpers for the ground-state Lanczos (complex double, one vector).
+hipError_t launch_multidot(int64_t n, const double2* const* vecs, int k, const double2* w,
+                           double2* out, double* partials, uint32_t* ticket, hipStream_t s);
+hipError_t launch_multiaxpy(int64_t n, const double2* const* vecs, int k, const double2* coef,
+                            double2* w, hipStream_t s);
+hipError_t launch_norm2(int64_t n, const double2* w, double* out, double* partials, uint32_t* ticket,
+                        hipStream_t s);
+hipError_t launch_scale(int64_t n, double2* w, const double* inv_from, double2 factor, hipStream_t s);
+hipError_t launch_absmax(int64_t n, const double2* w, double* out, double* partials, uint32_t* ticket,
+                         hipStream_t s);
+hipError_t launch_first_above(int64_t n, const double2* w, const double* thresh, int64_t* out,
+                              int64_t* partials, uint32_t* ticket, hipStream_t s);
+
+}  // namespace hub
