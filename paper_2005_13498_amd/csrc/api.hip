@@ -66,7 +66,8 @@ struct hub_basis_s {
   StepCtl* h_ctl = nullptr;       // pinned host
   double* partials = nullptr;
   size_t partials_bytes = 0;
-  uint32_t* tickets = nullptr;    // device [8]
+  double* partials_e = nullptr;   // partial sums of the elementwise kernels
+  size_t partials_e_bytes = 0;
   double* scal = nullptr;         // device scalars [kMMax*2 + 16]
   int rows_c128 = 1, rows_c64 = 1;
   // profiling of the apply kernel
@@ -136,6 +137,15 @@ hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t b
     h->partials_bytes = 0;
     HUB_HIP(hipMalloc(&h->partials, pb));
     h->partials_bytes = pb;
+  }
+  // elementwise partials: elem_grid (<= 1024) rows of up to 2 * 64 columns
+  const size_t pe = static_cast<size_t>(1024) * 2 * 64 * sizeof(double);
+  if (pe > h->partials_e_bytes) {
+    if (h->partials_e) HUB_HIP(hipFree(h->partials_e));
+    h->partials_e = nullptr;
+    h->partials_e_bytes = 0;
+    HUB_HIP(hipMalloc(&h->partials_e, pe));
+    h->partials_e_bytes = pe;
   }
   return HUB_OK;
 }
@@ -269,9 +279,6 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   } freer{dlog, dobs};
 
   StepCtl ctl0{};
-  ctl0.m_max = o.m_max;
-  ctl0.tol = o.tol;
-  ctl0.norm_inf = h->B.norm_inf;
   HUB_HIP(hipMemcpyAsync(h->ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
   HUB_HIP(hipStreamSynchronize(stream));
 
@@ -284,9 +291,18 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   L.rows = rows;
   L.st = h->st;
   L.ctl = h->ctl;
+  L.m_max = o.m_max;
+  L.tol = o.tol;
+  L.norm_inf = h->B.norm_inf;
   L.partials = h->partials;
+  L.prev_partials = h->partials_e;
+  L.prev_nblk = hub::elem_grid(dim * nv);
   L.stream = stream;
+  const int agrid = hub::apply_grid(h->D, rows);
 
+  // The decision for Krylov dimension m is taken by the first workgroup of
+  // the m-th apply; iterations are enqueued speculatively up to the previous
+  // step's m plus one, later kernels exit at once when the step is decided.
   int m_pred = o.m_hint > 0 ? std::min(o.m_hint, o.m_max) : std::min(8, o.m_max);
   bool first = true;
   *not_converged = false;
@@ -294,27 +310,29 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   for (int n = 0; n < n_steps; ++n) {
     const double* cf = coef_mid.data() + static_cast<size_t>(n) * nv * 2 * nc;
     int m_step_max = 0;
+    bool maxed = false;
     for (int sub = 0; sub < o.substeps; ++sub) {
-      HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, o.m_max, o.tol, h->B.norm_inf,
-                                     !first, h->partials, stream));
+      HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, first, h->partials_e, stream));
       first = false;
       const bool obs_here = want_obs && sub == 0;
-      int j = 0;
       auto enqueue_iter = [&](int jj) -> hub_status {
         hub::ApplyLaunch A = L;
         A.mode = hub::kLanczos;
         A.obs = obs_here && jj == 0;
         A.x = ptrs[jj];
-        A.y = ptrs[jj + 1];
+        A.y = jj < o.m_max ? ptrs[jj + 1] : nullptr;
         A.xprev = jj > 0 ? ptrs[jj - 1] : nullptr;
         A.coef = cf;
         A.j = jj;
         hub_status r = launch_apply_timed(h, A);
         if (r != HUB_OK) return r;
-        HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, stream));
+        if (jj < o.m_max)
+          HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
+                                     hub::apply_nq(hub::kLanczos, A.obs, nc), h->partials_e, stream));
         return HUB_OK;
       };
-      for (; j < m_pred && j < o.m_max; ++j) {
+      int j = 0;
+      for (; j <= m_pred && j <= o.m_max; ++j) {
         hub_status r = enqueue_iter(j);
         if (r != HUB_OK) return r;
       }
@@ -322,15 +340,14 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         HUB_HIP(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
         HUB_HIP(hipStreamSynchronize(stream));
         if (h->h_ctl->all_done) break;
-        if (j >= o.m_max) return fail(HUB_E_DEVICE, "Krylov loop ended without a decision");
+        if (j > o.m_max) return fail(HUB_E_DEVICE, "Krylov loop ended without a decision");
         hub_status r = enqueue_iter(j);
         if (r != HUB_OK) return r;
         ++j;
       }
-      const int m_used = h->h_ctl->iter;
-      m_step_max = std::max(m_step_max, m_used);
-      const bool maxed = h->h_ctl->any_maxed != 0;
-      HUB_HIP(hub::launch_combine(pi, nv, dim, h->slot_ptrs, h->st, h->ctl, h->partials, stream));
+      m_step_max = std::max(m_step_max, static_cast<int>(h->h_ctl->iter));
+      maxed = h->h_ctl->any_maxed != 0;
+      HUB_HIP(hub::launch_combine(pi, nv, dim, h->slot_ptrs, h->st, h->partials_e, stream));
       CombineLog* lg = static_cast<CombineLog*>(dlog) + (static_cast<size_t>(n) * o.substeps + sub) * nv;
       HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, lg,
                                    obs_here ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr, kObsQ,
@@ -340,8 +357,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     // next step's speculative depth: the deepest this step needed, plus one
     m_pred = std::min(o.m_max, m_step_max + 1);
     *steps_done = n + 1;
-    // stop at the first step where a vector hit m_max (flag read at the last sync)
-    if (h->h_ctl->any_maxed) {
+    if (maxed) {  // stop at the first step where a vector hit m_max
       *not_converged = true;
       break;
     }
@@ -356,6 +372,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.coef = coef_final->data();
     A.j = 0;
     HUB_HIP(hub::launch_apply(A));
+    HUB_HIP(hub::launch_finalize_obs(nv, h->partials, agrid, hub::apply_nq(hub::kObsOnly, true, nc), h->st, stream));
     HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, nullptr, dobs + static_cast<size_t>(n_steps) * nv * kObsQ,
                                  kObsQ, stream));
   }
@@ -473,30 +490,25 @@ hub_status hub_basis_create(const hub_lattice* lat, int32_t n_up, int32_t n_dn, 
   if ((s = upload(h, &D.dn_bits, B.dn.states)) != HUB_OK) return cleanup(s);
   if ((s = upload(h, &D.eps_up, B.up.onsite)) != HUB_OK) return cleanup(s);
   if ((s = upload(h, &D.eps_dn, B.dn.onsite)) != HUB_OK) return cleanup(s);
-  if ((s = upload(h, &D.up_cls_ptr, B.up.cls_ptr)) != HUB_OK) return cleanup(s);
+  std::vector<int32_t> uptr(static_cast<size_t>(B.up.dim) + 1);
+  for (int r = 0; r < B.up.dim; ++r) uptr[r] = B.up.cls_ptr[static_cast<size_t>(r) * (D.nc + 1)];
+  uptr[B.up.dim] = static_cast<int32_t>(B.up.hops.size());
+  if ((s = upload(h, &D.up_ptr, uptr)) != HUB_OK) return cleanup(s);
   std::vector<uint32_t> uh = B.up.hops;
-  if (uh.empty()) uh.push_back(0);
+  uh.resize(uh.size() + 8, 0u);  // batches of eight may read past the last hop
   if ((s = upload(h, &D.up_hops, uh)) != HUB_OK) return cleanup(s);
-  if ((s = upload(h, &D.dn_cls_ptr, B.dn.cls_ptr)) != HUB_OK) return cleanup(s);
-  std::vector<uint32_t> dh = B.dn.hops;
-  if (dh.empty()) dh.push_back(0);
-  if ((s = upload(h, &D.dn_hops, dh)) != HUB_OK) return cleanup(s);
-  std::vector<uint16_t> tab = B.dn.tab;
-  if (tab.empty()) tab.push_back(0);
-  if ((s = upload(h, &D.dn_tab, tab)) != HUB_OK) return cleanup(s);
-  for (int c = 0; c <= kMaxClasses; ++c)
-    D.dn_slot_begin[c] = c < static_cast<int>(B.dn.slot_begin.size()) ? B.dn.slot_begin[c] : B.dn.slot_begin.back();
-  D.up_max_hops = B.up.max_hops;
-  D.dn_max_hops = B.dn.max_hops;
+  if ((s = upload(h, &D.dn_tab, B.dn.tabc)) != HUB_OK) return cleanup(s);
+  D.nslots = B.dn.nslots;
+  D.maxs_pad = B.dn.maxs_pad;
+  for (int k = 0; k < 64; ++k) D.slot_class[k] = B.dn.slot_class[k];
 
   if (hipMalloc(reinterpret_cast<void**>(&h->slot_ptrs), (kMMax + 2) * sizeof(void*)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&h->st), kMaxNV * sizeof(VecState)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&h->ctl), sizeof(StepCtl)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&h->tickets), 8 * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&h->scal), (2 * kMMax + 64) * sizeof(double) * 2) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(HUB_E_NOMEM, "workspace allocation failed"));
-  if (hipMemset(h->ctl, 0, sizeof(StepCtl)) != hipSuccess || hipMemset(h->tickets, 0, 8 * sizeof(uint32_t)) != hipSuccess ||
+  if (hipMemset(h->ctl, 0, sizeof(StepCtl)) != hipSuccess ||
       hipMemset(h->st, 0, kMaxNV * sizeof(VecState)) != hipSuccess)
     return cleanup(fail(HUB_E_DEVICE, "workspace initialisation failed"));
   h->rows_c128 = pick_rows(h, 0);
@@ -520,7 +532,7 @@ void hub_basis_destroy(hub_basis h) {
   if (h->slot_ptrs) (void)hipFree(h->slot_ptrs);
   if (h->st) (void)hipFree(h->st);
   if (h->ctl) (void)hipFree(h->ctl);
-  if (h->tickets) (void)hipFree(h->tickets);
+  if (h->partials_e) (void)hipFree(h->partials_e);
   if (h->scal) (void)hipFree(h->scal);
   if (h->partials) (void)hipFree(h->partials);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
@@ -648,9 +660,6 @@ hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t 
   const int nc = h->D.nc;
   s = ensure_workspace(h, 16, 1, 0);
   if (s != HUB_OK) return s;
-  StepCtl ctl0{};
-  HUB_HIP(hipMemcpyAsync(h->ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, st));
-  HUB_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < nvec; ++k) {
     std::vector<double> cf(static_cast<size_t>(2) * kMaxNV * kMaxClasses, 0.0);
     coef_for(h->B, A[k], cf.data());
@@ -667,7 +676,9 @@ hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t 
     L.ctl = h->ctl;
     L.partials = h->partials;
     L.stream = st;
-    HUB_HIP(hub::launch_apply(L));
+    int grid = 0;
+    HUB_HIP(hub::launch_apply(L, &grid));
+    HUB_HIP(hub::launch_finalize_obs(1, h->partials, grid, hub::apply_nq(hub::kObsOnly, true, nc), h->st, st));
     double o[kObsQ];
     HUB_HIP(hipMemcpyAsync(o, reinterpret_cast<char*>(h->st) + offsetof(VecState, obs), sizeof(o),
                            hipMemcpyDeviceToHost, st));
@@ -675,7 +686,7 @@ hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t 
     fill_obs(h->B, o, cf.data(), 0.0, &out[k]);
     out[k].t = 0.0;
     if (site_docc) {
-      HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, h->scal, h->partials, h->tickets + 4, st));
+      HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, h->scal, h->partials_e, st));
       HUB_HIP(hipMemcpyAsync(site_docc + static_cast<size_t>(k) * h->D.n_sites, h->scal,
                              h->D.n_sites * sizeof(double), hipMemcpyDeviceToHost, st));
       HUB_HIP(hipStreamSynchronize(st));
@@ -829,7 +840,7 @@ hub_status gs_lanczos(hub_basis h, double A, hipStream_t st, GSBufs& G, int kmax
       for (int k0 = 0; k0 < nb; k0 += 64) {
         const int kk = std::min(64, nb - k0);
         HUB_HIP(hub::launch_multidot(dim, reinterpret_cast<const double2* const*>(G.Vdev) + k0, kk,
-                                     static_cast<const double2*>(w), G.coef + k0, h->partials, h->tickets, st));
+                                     static_cast<const double2*>(w), G.coef + k0, h->partials_e, st));
       }
       for (int k0 = 0; k0 < nb; k0 += 64) {
         const int kk = std::min(64, nb - k0);
@@ -841,7 +852,7 @@ hub_status gs_lanczos(hub_basis h, double A, hipStream_t st, GSBufs& G, int kmax
       HUB_HIP(hipStreamSynchronize(st));
       a_j += cj.x;
     }
-    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(w), h->scal, h->partials, h->tickets + 1, st));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(w), h->scal, h->partials_e, st));
     double n2 = 0.0;
     HUB_HIP(hipMemcpyAsync(&n2, h->scal, sizeof(double), hipMemcpyDeviceToHost, st));
     HUB_HIP(hipStreamSynchronize(st));
@@ -883,7 +894,7 @@ hub_status gs_ritz_vector(hub_basis h, hipStream_t st, GSBufs& G, const std::vec
                                   static_cast<double2*>(out), st));
   }
   // normalise
-  HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(out), h->scal, h->partials, h->tickets + 1, st));
+  HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(out), h->scal, h->partials_e, st));
   HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(out), h->scal, double2{0, 0}, st));
   HUB_HIP(hipStreamSynchronize(st));
   return HUB_OK;
@@ -925,7 +936,7 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
     std::vector<double2> x(static_cast<size_t>(dim));
     for (auto& e : x) e = double2{nd(rng), nd(rng)};
     HUB_HIP(hipMemcpy(dst, x.data(), x.size() * sizeof(double2), hipMemcpyHostToDevice));
-    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(dst), h->scal, h->partials, h->tickets + 1, st));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(dst), h->scal, h->partials_e, st));
     HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(dst), h->scal, double2{0, 0}, st));
     return HUB_OK;
   };
@@ -950,15 +961,15 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
   }
   if (!conv) return fail(HUB_E_NOT_CONVERGED, "ground-state Lanczos did not reach the tolerance");
   // phase: largest-modulus component (lowest index within 1e-12 of the max) real positive
-  HUB_HIP(hub::launch_absmax(dim, static_cast<const double2*>(v_out), h->scal, h->partials, h->tickets + 2, st));
+  HUB_HIP(hub::launch_absmax(dim, static_cast<const double2*>(v_out), h->scal, h->partials_e, st));
   double mx2 = 0.0;
   HUB_HIP(hipMemcpyAsync(&mx2, h->scal, sizeof(double), hipMemcpyDeviceToHost, st));
   HUB_HIP(hipStreamSynchronize(st));
   const double th = mx2 * (1.0 - 1e-12) * (1.0 - 1e-12);
   HUB_HIP(hipMemcpy(h->scal + 1, &th, sizeof(double), hipMemcpyHostToDevice));
   HUB_HIP(hub::launch_first_above(dim, static_cast<const double2*>(v_out), h->scal + 1,
-                                  reinterpret_cast<int64_t*>(h->scal + 2), reinterpret_cast<int64_t*>(h->partials),
-                                  h->tickets + 3, st));
+                                  reinterpret_cast<int64_t*>(h->scal + 2), reinterpret_cast<int64_t*>(h->partials_e),
+                                  st));
   int64_t kmaxidx = 0;
   HUB_HIP(hipMemcpyAsync(&kmaxidx, h->scal + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HUB_HIP(hipStreamSynchronize(st));
@@ -976,10 +987,10 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
     HUB_HIP(hipMemcpyAsync(G.Vdev, &v_out, sizeof(void*), hipMemcpyHostToDevice, st));
     HUB_HIP(hipStreamSynchronize(st));
     HUB_HIP(hub::launch_multidot(dim, reinterpret_cast<const double2* const*>(G.Vdev), 1,
-                                 static_cast<const double2*>(G.V[0]), G.coef, h->partials, h->tickets, st));
+                                 static_cast<const double2*>(G.V[0]), G.coef, h->partials_e, st));
     HUB_HIP(hub::launch_multiaxpy(dim, reinterpret_cast<const double2* const*>(G.Vdev), 1, G.coef,
                                   static_cast<double2*>(G.V[0]), st));
-    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(G.V[0]), h->scal, h->partials, h->tickets + 1, st));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(G.V[0]), h->scal, h->partials_e, st));
     HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(G.V[0]), h->scal, double2{0, 0}, st));
     double r1 = INFINITY;
     for (int restart = 0; restart < 20; ++restart) {

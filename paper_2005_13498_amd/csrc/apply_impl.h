@@ -1,0 +1,376 @@
+// Matrix-free Hamiltonian apply (templated); instantiated per precision by
+// apply_c128.hip and apply_c64.hip.
+#pragma once
+
+#include "kernels_common.h"
+
+namespace hub {
+namespace dev {
+
+// Matrix-free H x on the [dim_up x dim_dn] tile (NV vectors interleaved per
+// element):
+//   y[a,b] = (U popc(u_a & d_b) + e_a + e_b) x[a,b]
+//          + sum over up hops a'->a:   sgn coef_c x[a',b]
+//          + sum over down hops b'->b: sgn coef_c x[a,b'].
+// A workgroup owns one tile row.  The row is staged in LDS twice, as +x and
+// -x, followed by a zero slot, so a down hop is one LDS read at an index that
+// already encodes its fermion sign (pad slots read the zero).  Each thread
+// takes one column at a time: it loads the column's padded, class-sorted hop
+// indices with 16-byte loads and runs a fully unrolled, branch-free slot loop
+// (one LDS read, one complex FMA with the slot's class coefficient).  Up hops
+// read whole source rows from global memory (coalesced; the hop list is
+// uniform over the workgroup), in independent batches of eight, each with a
+// uniform signed class coefficient.
+struct KArgs {
+  int dim_up, dim_dn, nc, j, nslots, m_max;
+  double tol, norm_inf, U;
+  const uint32_t* up_bits;
+  const uint32_t* dn_bits;
+  const double* eps_up;
+  const double* eps_dn;
+  const int32_t* up_ptr;      // [dim_up + 1]
+  const uint32_t* up_hops;    // src | class << 16 | sign << 31
+  const uint16_t* dn_tab;     // [dim_dn][MAXS] stage index (src + copy * (dim_dn + 1)), pad = dim_dn
+  uint8_t slot_class[64];
+  double coef[2 * kMaxNV * kMaxClasses];  // [v][c] complex
+  double slot_coef[2 * 64];                // vector 0: coefficient of every down slot
+  double up_coef[2 * 2 * kMaxClasses];     // vector 0: [c][sign] signed coefficient
+  const void* x;
+  void* y;
+  const void* xprev;
+  VecState* st;
+  StepCtl* ctl;
+  double* partials;
+  const double* prev_partials;
+  int prev_nblk;
+};
+
+template <typename V>
+__device__ __forceinline__ void add_class(double (&pr)[kMaxClasses], double (&pi)[kMaxClasses], int c, V x,
+                                          V s) {
+  const double re = (double)x.x * s.x + (double)x.y * s.y;  // conj(x) * s
+  const double im = (double)x.x * s.y - (double)x.y * s.x;
+#pragma unroll
+  for (int k = 0; k < kMaxClasses; ++k)
+    if (k == c) {
+      pr[k] += re;
+      pi[k] += im;
+    }
+}
+
+// Threads per apply workgroup.  Long rows of single vectors use 1024 threads
+// (fewer column passes per thread); short rows, interleaved blocks and the
+// observables pass use 256 (more workgroups per CU, more registers per thread).
+constexpr int kRowsLong = 2048;
+
+// Per-quantity workgroup reduction with a small LDS buffer (W waves, NV
+// interleaved vectors): out[q * NV + v] = sum over the workgroup's threads of
+// vector v.  Fixed order.
+template <int NV, int W>
+__device__ void block_partials_seq(const double* vals, int nq, double* lds, double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int q = 0; q < nq; ++q) {
+    double v = vals[q];
+#pragma unroll
+    for (int off = 32; off >= NV; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if (lane < NV) lds[w * NV + lane] = v;
+    __syncthreads();
+    if (threadIdx.x < NV) {
+      double s = 0.0;
+      for (int k = 0; k < W; ++k) s += lds[k * NV + threadIdx.x];
+      out[q * NV + threadIdx.x] = s;
+    }
+  }
+}
+
+template <typename R, int NV, int MODE, int MAXS, int BLK>
+__global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
+  using V = typename CT<R>::T;
+  constexpr int kBlockA = BLK;
+  constexpr int kWavesA = kBlockA / 64;
+  constexpr bool kL = (MODE == M_LANCZOS || MODE == M_LANCZOS_OBS);
+  constexpr bool kO = (MODE == M_LANCZOS_OBS || MODE == M_OBS);
+  constexpr bool kW = (MODE != M_OBS);
+  constexpr int kNQ = 1 + 3 + 2 * kMaxClasses;
+  constexpr int kUB = 8;  // up hops gathered in the first batch
+  __shared__ double red[kWavesA * kMaxNV];
+  __shared__ double sh_beta[kMaxNV];
+  __shared__ V sh_slot[NV > 1 ? 64 * NV : 1];
+  __shared__ V sh_up[NV > 1 ? 2 * kMaxClasses * NV : 1];
+
+  const int tid = threadIdx.x;
+  const int v = tid % NV;
+  const int nc = p.nc;
+
+  R sj = 1, bprev = 0;
+  if (kL) {
+    if (p.ctl->all_done) return;
+    // norm of the vector just completed (|u_j|, j >= 1) or of the step input
+    for (int t = 0; t < NV; ++t) {
+      const double s = reduce_column<kWavesA>(p.prev_partials, p.prev_nblk, NV, t, red);
+      if (tid == 0) sh_beta[t] = sqrt(s);
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) krylov_decide<NV, kWavesA>(p.j, sh_beta, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+    if (p.j >= p.m_max) return;  // only the decision was needed
+    const double bv = sh_beta[v];
+    sj = static_cast<R>(bv > 0.0 ? 1.0 / bv : 0.0);
+    if (p.j > 0) bprev = static_cast<R>(bv * p.st[v].scale[p.j - 1]);
+  }
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V* xs = reinterpret_cast<V*>(smem_raw);
+  const V* __restrict__ x = static_cast<const V*>(p.x);
+  V* __restrict__ y = static_cast<V*>(p.y);
+  const int rowlen = p.dim_dn * NV;       // complex elements of one tile row
+  const int half = (p.dim_dn + 1) * NV;   // one staged copy incl. the zero slot
+  const int a = xcd_remap(blockIdx.x, gridDim.x);
+  const int hb = p.up_ptr[a], hcnt = p.up_ptr[a + 1] - hb;
+  const uint32_t ua = p.up_bits[a];
+  const double ea = p.eps_up ? p.eps_up[a] : 0.0;
+  const uint2* tab2 = reinterpret_cast<const uint2*>(p.dn_tab);
+  constexpr int kQ2 = MAXS / 4;
+
+  // Global loads of this thread's first column (table entries, the first
+  // batch of up-hop sources, the previous Lanczos vector) are issued before
+  // the row is staged, so their latency overlaps the staging.
+  int q = tid;
+  uint2 ev[kQ2];
+  uint32_t eu[kUB];
+  V tu[kUB];
+  V pv = V{0, 0};
+  auto load_column = [&](int qq) {
+    const int b = qq / NV;
+#pragma unroll
+    for (int k = 0; k < kQ2; ++k) ev[k] = tab2[(size_t)b * kQ2 + k];
+#pragma unroll
+    for (int k = 0; k < kUB; ++k) eu[k] = (k < hcnt) ? p.up_hops[hb + k] : 0u;
+#pragma unroll
+    for (int k = 0; k < kUB; ++k) tu[k] = (k < hcnt) ? x[(size_t)(eu[k] & 0xFFFFu) * rowlen + qq] : V{0, 0};
+    if (kL && p.j > 0) pv = static_cast<const V*>(p.xprev)[(size_t)a * rowlen + qq];
+  };
+  if (q < rowlen) load_column(q);
+
+  // stage +x, -x (zero slot at column dim_dn of each copy)
+  {
+    const V* src = x + (size_t)a * rowlen;
+    for (int t = tid; t < half; t += kBlockA) {
+      const V val = (t < rowlen) ? src[t] : V{0, 0};
+      xs[t] = val;
+      xs[half + t] = V{-val.x, -val.y};
+    }
+  }
+  if (NV > 1) {
+    for (int t = tid; t < 64 * NV; t += kBlockA) {
+      const int s = t / NV, vv = t % NV;
+      const int c = p.slot_class[s];
+      sh_slot[t] = (s < p.nslots) ? V{static_cast<R>(p.coef[2 * (vv * nc + c)]),
+                                       static_cast<R>(p.coef[2 * (vv * nc + c) + 1])}
+                                  : V{0, 0};
+    }
+    for (int t = tid; t < 2 * nc * NV; t += kBlockA) {
+      const int cs = t / NV, vv = t % NV, c = cs >> 1;
+      const R sg = (cs & 1) ? R(-1) : R(1);
+      sh_up[t] = V{sg * static_cast<R>(p.coef[2 * (vv * nc + c)]), sg * static_cast<R>(p.coef[2 * (vv * nc + c) + 1])};
+    }
+  }
+  __syncthreads();
+
+  double q_alpha = 0.0, q_diag = 0.0, q_docc = 0.0, q_n2 = 0.0;
+  double q_pr[kMaxClasses], q_pi[kMaxClasses];
+#pragma unroll
+  for (int c = 0; c < kMaxClasses; ++c) {
+    q_pr[c] = 0.0;
+    q_pi[c] = 0.0;
+  }
+
+  while (q < rowlen) {
+    const int b = q / NV;
+    const uint32_t db = p.dn_bits[b];
+    const double eb = p.eps_dn ? p.eps_dn[b] : 0.0;
+    const V xv = xs[q];
+    const double nd = static_cast<double>(__popc(ua & db));
+    const double dg = p.U * nd + ea + eb;
+    V acc = V{static_cast<R>(dg) * xv.x, static_cast<R>(dg) * xv.y};
+    if (kO) {
+      const double m2 = (double)xv.x * xv.x + (double)xv.y * xv.y;
+      q_diag += dg * m2;
+      q_docc += nd * m2;
+      q_n2 += m2;
+    }
+    // down hops: one LDS read and one complex FMA per slot, no branches
+    // (slots past the string's hops read the zero slot with a zero coefficient)
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      const uint32_t w2 = (s & 3) < 2 ? ev[s >> 2].x : ev[s >> 2].y;
+      const uint32_t idx = (s & 1) ? (w2 >> 16) : (w2 & 0xFFFFu);
+      const V t = xs[idx * NV + v];
+      V cf;
+      if (NV == 1) cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
+      else cf = sh_slot[s * NV + v];
+      acc = cfma(cf, t, acc);
+      if (kO) add_class(q_pr, q_pi, p.slot_class[s], xv, t);  // the staged value carries the sign
+    }
+    // up hops: whole source rows from global memory, uniform signed coefficients
+    auto up_term = [&](uint32_t e, V t) {
+      const int cs = static_cast<int>(((e >> 16) & 0xFFu) * 2u + (e >> 31));
+      V cf;
+      if (NV == 1) cf = V{static_cast<R>(p.up_coef[2 * cs]), static_cast<R>(p.up_coef[2 * cs + 1])};
+      else cf = sh_up[cs * NV + v];
+      acc = cfma(cf, t, acc);
+      if (kO) {
+        const V ts = (e >> 31) ? V{-t.x, -t.y} : t;
+        add_class(q_pr, q_pi, static_cast<int>((e >> 16) & 0xFFu), xv, ts);
+      }
+    };
+#pragma unroll
+    for (int k = 0; k < kUB; ++k)
+      if (k < hcnt) up_term(eu[k], tu[k]);
+    for (int h0 = kUB; h0 < hcnt; h0 += 8) {
+      uint32_t e[8];
+      V t[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) e[k] = (h0 + k < hcnt) ? p.up_hops[hb + h0 + k] : 0u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[k] = (h0 + k < hcnt) ? x[(size_t)(e[k] & 0xFFFFu) * rowlen + q] : V{0, 0};
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (h0 + k < hcnt) up_term(e[k], t[k]);
+    }
+    const size_t idx = (size_t)a * rowlen + q;
+    V out = acc;
+    if (kL) {
+      out.x = out.x * sj - bprev * pv.x;
+      out.y = out.y * sj - bprev * pv.y;
+      // alpha_j = Re <s_j u_j, w>
+      q_alpha += (double)sj * ((double)xv.x * out.x + (double)xv.y * out.y);
+    }
+    if (kW) y[idx] = out;
+    q += kBlockA;
+    if (q < rowlen) load_column(q);
+  }
+
+  // workgroup partials: [alpha] [diag, docc, n2, (Re, Im) <x|K_c|x> ...]
+  constexpr int nqL = kL ? 1 : 0;
+  const int nqO = kO ? 3 + 2 * nc : 0;
+  const int nq = nqL + nqO;
+  if (nq == 0) return;
+  double vals[kNQ];
+  int k = 0;
+  if (kL) vals[k++] = q_alpha;
+  if (kO) {
+    vals[k++] = q_diag;
+    vals[k++] = q_docc;
+    vals[k++] = q_n2;
+#pragma unroll
+    for (int cc = 0; cc < kMaxClasses; ++cc) {
+      if (cc < nc) {
+        vals[k++] = q_pr[cc];
+        vals[k++] = q_pi[cc];
+      }
+    }
+  }
+  block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)a * nq * NV);
+}
+
+template <typename R, int NV, int MODE, int MAXS, int BLK>
+hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
+  const DevBasis& db = *L.db;
+  KArgs p;
+  p.dim_up = db.dim_up;
+  p.dim_dn = db.dim_dn;
+  p.nc = db.nc;
+  p.j = L.j;
+  p.nslots = db.nslots;
+  p.m_max = L.m_max;
+  p.tol = L.tol;
+  p.norm_inf = L.norm_inf;
+  p.U = db.U;
+  p.up_bits = db.up_bits;
+  p.dn_bits = db.dn_bits;
+  p.eps_up = db.eps_up;
+  p.eps_dn = db.eps_dn;
+  p.up_ptr = db.up_ptr;
+  p.up_hops = db.up_hops;
+  p.dn_tab = db.dn_tab;
+  for (int s = 0; s < 64; ++s) p.slot_class[s] = db.slot_class[s];
+  for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef[k] = L.coef ? L.coef[k] : 0.0;
+  for (int s = 0; s < 64; ++s) {
+    const int c = db.slot_class[s];
+    p.slot_coef[2 * s] = (s < db.nslots && L.coef) ? L.coef[2 * c] : 0.0;
+    p.slot_coef[2 * s + 1] = (s < db.nslots && L.coef) ? L.coef[2 * c + 1] : 0.0;
+  }
+  for (int c = 0; c < kMaxClasses; ++c)
+    for (int sg = 0; sg < 2; ++sg) {
+      const double f = sg ? -1.0 : 1.0;
+      const bool ok = c < db.nc && L.coef;
+      p.up_coef[2 * (2 * c + sg)] = ok ? f * L.coef[2 * c] : 0.0;
+      p.up_coef[2 * (2 * c + sg) + 1] = ok ? f * L.coef[2 * c + 1] : 0.0;
+    }
+  p.x = L.x;
+  p.y = L.y;
+  p.xprev = L.xprev;
+  p.st = L.st;
+  p.ctl = L.ctl;
+  p.partials = L.partials;
+  p.prev_partials = L.prev_partials;
+  p.prev_nblk = L.prev_nblk;
+  auto fn = k_apply<R, NV, MODE, MAXS, BLK>;
+  // dynamic LDS above the 64 KB default must be opted into (CU total 160 KB)
+  static int max_dyn = -1;
+  if (max_dyn < 0) {
+    hipFuncAttributes fa{};
+    size_t stat = 0;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(fn)) == hipSuccess) stat = fa.sharedSizeBytes;
+    const int want = 160 * 1024 - static_cast<int>(stat);
+    max_dyn = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  want) == hipSuccess
+                  ? want
+                  : 64 * 1024 - static_cast<int>(stat);
+    (void)hipGetLastError();  // a refused opt-in is not a launch error
+  }
+  if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(BLK), lds, L.stream, p);
+  return hipGetLastError();
+}
+
+template <typename R, int NV, int MODE, int BLK>
+hipError_t apply_s(const ApplyLaunch& L, int grid, size_t lds) {
+  switch (L.db->maxs_pad) {
+    case 4: return apply_t<R, NV, MODE, 4, BLK>(L, grid, lds);
+    case 8: return apply_t<R, NV, MODE, 8, BLK>(L, grid, lds);
+    case 12: return apply_t<R, NV, MODE, 12, BLK>(L, grid, lds);
+    case 16: return apply_t<R, NV, MODE, 16, BLK>(L, grid, lds);
+    case 20: return apply_t<R, NV, MODE, 20, BLK>(L, grid, lds);
+    case 24: return apply_t<R, NV, MODE, 24, BLK>(L, grid, lds);
+    case 32: return apply_t<R, NV, MODE, 32, BLK>(L, grid, lds);
+    case 48: return apply_t<R, NV, MODE, 48, BLK>(L, grid, lds);
+    case 64: return apply_t<R, NV, MODE, 64, BLK>(L, grid, lds);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, int NV>
+hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds) {
+  const bool longrow = NV == 1 && L.db->dim_dn >= kRowsLong;
+  if (L.mode == kPlain)
+    return longrow ? apply_s<R, NV, M_PLAIN, 1024>(L, grid, lds) : apply_s<R, NV, M_PLAIN, 256>(L, grid, lds);
+  if (L.mode == kObsOnly) return apply_s<R, NV, M_OBS, 256>(L, grid, lds);
+  if (L.obs) return apply_s<R, NV, M_LANCZOS_OBS, 256>(L, grid, lds);
+  return longrow ? apply_s<R, NV, M_LANCZOS, 1024>(L, grid, lds) : apply_s<R, NV, M_LANCZOS, 256>(L, grid, lds);
+}
+
+template <typename R>
+hipError_t apply_nv(const ApplyLaunch& L, int grid, size_t lds) {
+  switch (L.nv) {
+    case 1: return apply_mode<R, 1>(L, grid, lds);
+    case 2: return apply_mode<R, 2>(L, grid, lds);
+    case 4: return apply_mode<R, 4>(L, grid, lds);
+    case 8: return apply_mode<R, 8>(L, grid, lds);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dev
+}  // namespace hub

@@ -84,7 +84,7 @@ static void build_spin(const Lattice& lat, int n_el, const std::vector<HopClass>
         const int lo = std::min(dst, src), hi = std::max(dst, src);
         const uint32_t between = (hi - lo > 1) ? ((s >> (lo + 1)) & ((1u << (hi - lo - 1)) - 1u)) : 0u;
         const uint32_t sign = static_cast<uint32_t>(__builtin_popcount(between) & 1);
-        T.hops.push_back(rank_of(from, ns) | (sign << 31));
+        T.hops.push_back(rank_of(from, ns) | (static_cast<uint32_t>(c) << 16) | (sign << 31));
         ++count[c][r];
         ++nh;
       }
@@ -92,7 +92,7 @@ static void build_spin(const Lattice& lat, int n_el, const std::vector<HopClass>
     T.cls_ptr[static_cast<size_t>(r) * (nc + 1) + nc] = static_cast<int32_t>(T.hops.size());
     T.max_hops = std::max(T.max_hops, nh);
   }
-  // padded lane-major table
+  // padded, class-sorted copy for the apply kernel
   T.slot_begin.assign(nc + 1, 0);
   for (int c = 0; c < nc; ++c) {
     int mx = 0;
@@ -100,18 +100,30 @@ static void build_spin(const Lattice& lat, int n_el, const std::vector<HopClass>
     T.slot_begin[c + 1] = T.slot_begin[c] + mx;
   }
   const int slots = T.slot_begin[nc];
-  T.tab.assign(static_cast<size_t>(slots) * T.dim, static_cast<uint16_t>(T.dim));
+  T.nslots = slots;
+  T.maxs_pad = 64;
+  for (int cand : {4, 8, 12, 16, 20, 24, 32, 48, 64})
+    if (slots <= cand) {
+      T.maxs_pad = cand;
+      break;
+    }
+  // entry = source rank, plus (dim + 1) when the hop's sign is negative: the
+  // apply stages each row as +x, -x with a zero slot at index dim; pads read it
+  T.tabc.assign(static_cast<size_t>(T.maxs_pad) * T.dim, static_cast<uint16_t>(T.dim));
   for (int r = 0; r < T.dim; ++r) {
     for (int c = 0; c < nc; ++c) {
       const int b = T.cls_ptr[static_cast<size_t>(r) * (nc + 1) + c];
       const int e = T.cls_ptr[static_cast<size_t>(r) * (nc + 1) + c + 1];
       for (int k = b; k < e; ++k) {
         const uint32_t h = T.hops[k];
-        const uint16_t v = static_cast<uint16_t>((h & 0xFFFFu) | ((h >> 31) << 15));
-        T.tab[static_cast<size_t>(T.slot_begin[c] + (k - b)) * T.dim + r] = v;
+        const uint32_t v = (h & 0xFFFFu) + ((h >> 31) ? static_cast<uint32_t>(T.dim + 1) : 0u);
+        T.tabc[static_cast<size_t>(r) * T.maxs_pad + T.slot_begin[c] + (k - b)] = static_cast<uint16_t>(v);
       }
     }
   }
+  T.slot_class.assign(64, 0);
+  for (int c = 0; c < nc; ++c)
+    for (int s = T.slot_begin[c]; s < T.slot_begin[c + 1] && s < 64; ++s) T.slot_class[s] = static_cast<uint8_t>(c);
 }
 
 std::string build_basis(const Lattice& lat, int n_up, int n_dn, Basis& B, bool& sector_error) {
@@ -157,6 +169,7 @@ std::string build_basis(const Lattice& lat, int n_up, int n_dn, Basis& B, bool& 
     return "more than 8 distinct (t, displacement) hop classes";
   build_spin(lat, n_up, B.classes, directed, B.up);
   build_spin(lat, n_dn, B.classes, directed, B.dn);
+  if (B.dn.nslots > 64) return "more than 64 padded hop slots per string (too many bonds for the apply kernel)";
   B.dim = static_cast<int64_t>(B.up.dim) * B.dn.dim;
 
   // |H|_inf = max over (a, b) of |diag| + sum of |hop amplitudes|

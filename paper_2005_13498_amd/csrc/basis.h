@@ -33,13 +33,18 @@ struct SpinTable {
   // gather hops, CSR by target with class sub-ranges:
   // hops of target r and class c are hops[cls_ptr[r*(nc+1)+c] .. cls_ptr[r*(nc+1)+c+1])
   std::vector<int32_t> cls_ptr;       // [dim*(nc+1)]
-  std::vector<uint32_t> hops;         // packed: src (bits 0..15) | sign (bit 31)
+  std::vector<uint32_t> hops;         // packed: src (bits 0..15) | class (16..23) | sign (bit 31)
   int max_hops = 0;
-  // lane-major padded copy used by the row-staged apply: for class c the slots
-  // [slot_begin[c], slot_begin[c+1]); entry tab[s*dim + r] = src | sign<<15,
-  // padding entries = dim (the zero slot), sign 0.
+  // padded copy used by the row-staged apply: class c occupies slots
+  // [slot_begin[c], slot_begin[c+1]) of every string (slot_class[s] = c);
+  // entry tabc[r*maxs_pad + s] = src for a positive hop, src + dim + 1 for a
+  // negative one, dim (a zero slot) where the string has fewer hops of that
+  // class.  maxs_pad is the slot count rounded up to 4, 8, 12, 16, 20, 24, 32,
+  // 48 or 64.
   std::vector<int32_t> slot_begin;    // [nc+1]
-  std::vector<uint16_t> tab;          // [slots*dim]
+  std::vector<uint16_t> tabc;         // [dim*maxs_pad]
+  std::vector<uint8_t> slot_class;    // [64]
+  int nslots = 0, maxs_pad = 8;
 };
 
 struct Lattice {

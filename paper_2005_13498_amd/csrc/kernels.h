@@ -36,7 +36,6 @@ struct StepCtl {
   int32_t any_maxed;         // some vector reached m_max in this step
   double tol;
   double norm_inf;
-  uint32_t ticket[4];        // last-workgroup counters (apply, update, combine, norm)
 };
 
 // Device copy of a basis.
@@ -48,12 +47,11 @@ struct DevBasis {
   uint32_t* dn_bits = nullptr;
   double* eps_up = nullptr;      // null if no on-site energies
   double* eps_dn = nullptr;
-  int32_t* up_cls_ptr = nullptr; // [dim_up*(nc+1)]
-  uint32_t* up_hops = nullptr;
-  int32_t* dn_cls_ptr = nullptr; // [dim_dn*(nc+1)]
-  uint32_t* dn_hops = nullptr;
-  uint16_t* dn_tab = nullptr;    // lane-major padded table
-  int dn_slot_begin[kMaxClasses + 1] = {0};
+  int32_t* up_ptr = nullptr;     // [dim_up + 1] hop ranges of each up string
+  uint32_t* up_hops = nullptr;   // src | class << 16 | sign << 31
+  uint16_t* dn_tab = nullptr;    // [dim_dn][maxs_pad] staged-row index src + sign * (dim_dn + 1), pad dim_dn
+  uint8_t slot_class[64] = {0};  // class of every down slot (uniform over strings)
+  int nslots = 0, maxs_pad = 8;
   int up_max_hops = 0, dn_max_hops = 0;
 };
 
@@ -76,30 +74,36 @@ struct ApplyLaunch {
   const double* coef;    // host [nv][nc] complex pairs (copied into the launch arguments)
   VecState* st;          // device [nv] (Lanczos/obs)
   StepCtl* ctl;
-  int j;                 // Lanczos iteration (0-based)
-  double* partials;      // device scratch [grid * nq * nv]
+  int j;                 // Lanczos iteration (0-based); the Krylov decision for m = j is taken here
+  int m_max;
+  double tol, norm_inf;
+  double* partials;      // device [grid][nq][nv] partial sums written by this launch
+  const double* prev_partials;  // Lanczos: |u_j|^2 (or |v|^2) partials [prev_nblk][nv]
+  int prev_nblk;
   hipStream_t stream;
 };
 
 // Each launcher returns the hipError_t of its launch.
 hipError_t launch_apply(const ApplyLaunch& L, int* grid_out = nullptr);
 int apply_grid(const DevBasis& db, int rows);
+int apply_nq(int mode, bool obs, int nc);
 size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows);
+int elem_grid(int64_t n);  // grid of the elementwise kernels (update, combine, norms)
 
-// u_next = w - alpha_j s_j u_j (in place in w), beta_j = |u_next|, small
-// exponential and stopping rule.  w and u_next may be the same buffer.
-hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, VecState* st,
-                         StepCtl* ctl, int j, double* partials, hipStream_t s);
+// u_{j+1} = w - alpha_j s_j u_j in place; alpha_j from the apply's partials;
+// |u_{j+1}|^2 partials [elem_grid][nv].
+hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, VecState* st, StepCtl* ctl, int j,
+                         const double* apply_partials, int apply_nblk, int apply_nq, double* partials,
+                         hipStream_t s);
 
 // v = beta0 sum_k y_k s_k u_k over the m_v vectors of each vector v (in place
-// into slot 0), then |v|^2 for the next step's beta0.
-hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, VecState* st,
-                          StepCtl* ctl, double* partials, hipStream_t s);
+// into slot 0), and |v|^2 partials [elem_grid][nv].
+hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
+                          double* partials, hipStream_t s);
 
-// beta0 = |v| and scale[0] = 1/beta0 for each vector; resets the step state.
-hipError_t launch_step_begin(int prec, int nv, int64_t n, const void* v, VecState* st,
-                             StepCtl* ctl, double tau, int m_max, double tol, double norm_inf,
-                             bool norm_known, double* partials, hipStream_t s);
+// |v|^2 partials of the step input (if norm), tau of every vector, cleared control block.
+hipError_t launch_step_begin(int prec, int nv, int64_t n, const void* v, VecState* st, StepCtl* ctl, double tau,
+                             bool norm, double* partials, hipStream_t s);
 
 struct CombineLog {
   int32_t m, status;
@@ -107,28 +111,30 @@ struct CombineLog {
 };
 
 // Copies the finished step's Krylov report and first-apply observables.
-hipError_t launch_step_log(int nv, VecState* st, StepCtl* ctl, void* log, double* obs_log, int nobs,
+hipError_t launch_step_log(int nv, const VecState* st, StepCtl* ctl, void* log, double* obs_log, int nobs,
                            hipStream_t s);
+
+// One-workgroup reductions of partial sums.
+hipError_t launch_finalize_obs(int nv, const double* partials, int nrows, int nq, VecState* st, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int nrows, int ncols, double* out, int op, hipStream_t s);
 
 // Site-resolved double occupation sum_k n_{i up} n_{i down} |x_k|^2 of one vector.
 hipError_t launch_site_docc(int prec, const DevBasis& db, const void* x, double* out, double* partials,
-                            uint32_t* ticket, hipStream_t s);
+                            hipStream_t s);
 
 // Layout changes between [v][k] (ABI) and [k][v] (interleaved block).
 hipError_t launch_interleave(int prec, int nv, int64_t n, const void* src, void* dst, bool to_block,
                              hipStream_t s);
 
 // BLAS-1 helpers for the ground-state Lanczos (complex double, one vector).
-hipError_t launch_multidot(int64_t n, const double2* const* vecs, int k, const double2* w,
-                           double2* out, double* partials, uint32_t* ticket, hipStream_t s);
-hipError_t launch_multiaxpy(int64_t n, const double2* const* vecs, int k, const double2* coef,
-                            double2* w, hipStream_t s);
-hipError_t launch_norm2(int64_t n, const double2* w, double* out, double* partials, uint32_t* ticket,
-                        hipStream_t s);
+hipError_t launch_multidot(int64_t n, const double2* const* vecs, int k, const double2* w, double2* out,
+                           double* partials, hipStream_t s);
+hipError_t launch_multiaxpy(int64_t n, const double2* const* vecs, int k, const double2* coef, double2* w,
+                            hipStream_t s);
+hipError_t launch_norm2(int64_t n, const double2* w, double* out, double* partials, hipStream_t s);
 hipError_t launch_scale(int64_t n, double2* w, const double* inv_from, double2 factor, hipStream_t s);
-hipError_t launch_absmax(int64_t n, const double2* w, double* out, double* partials, uint32_t* ticket,
-                         hipStream_t s);
-hipError_t launch_first_above(int64_t n, const double2* w, const double* thresh, int64_t* out,
-                              int64_t* partials, uint32_t* ticket, hipStream_t s);
+hipError_t launch_absmax(int64_t n, const double2* w, double* out, double* partials, hipStream_t s);
+hipError_t launch_first_above(int64_t n, const double2* w, const double* thresh, int64_t* out, int64_t* partials,
+                              hipStream_t s);
 
 }  // namespace hub

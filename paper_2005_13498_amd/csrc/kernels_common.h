@@ -1,0 +1,197 @@
+// Device helpers shared by the HIP translation units of the library.
+#pragma once
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace hub {
+namespace dev {
+
+
+template <typename R> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+
+enum KMode : int { M_PLAIN = 0, M_LANCZOS = 1, M_LANCZOS_OBS = 2, M_OBS = 3 };
+
+constexpr int kWaves = kBlock / 64;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks (tile rows with the same high-site
+// occupation, whose up hops mostly stay inside the range) so they share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int q = nblk >> 3, rem = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + min(x, rem) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Sum over the workgroup (W waves), identical on every thread, fixed order.
+template <int W = kWaves>
+__device__ inline double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) r += lds[k];
+  __syncthreads();
+  return r;
+}
+
+// Reduce nq per-thread quantities separately for each of the NV interleaved
+// vectors (thread's vector = tid % NV) and store the workgroup's sums at
+// out[q * NV + v].
+template <int NV, int W = kWaves>
+__device__ void block_partials(const double* vals, int nq, double* lds, double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  for (int q = 0; q < nq; ++q) {
+    double v = vals[q];
+#pragma unroll
+    for (int off = 32; off >= NV; off >>= 1) v += __shfl_xor(v, off);
+    if (lane < NV) lds[(w * nq + q) * NV + lane] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nq * NV; t += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < W; ++k) s += lds[k * nq * NV + t];
+    out[t] = s;
+  }
+}
+
+// Fixed-order total of column t of a [nrows][ncols] partial-sum array,
+// identical on every thread of the workgroup.
+template <int W = kWaves>
+__device__ inline double reduce_column(const double* partials, int nrows, int ncols, int t, double* lds) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nrows; b += blockDim.x) s += partials[(size_t)b * ncols + t];
+  return block_sum<W>(s, lds);
+}
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V cfma(V c, V s, V acc) {
+  return V{acc.x + c.x * s.x - c.y * s.y, acc.y + c.x * s.y + c.y * s.x};
+}
+
+// ---------------------------------------------------------------------------
+// One wavefront: y = exp(-i tau T) e_1 for the j x j real symmetric
+// tridiagonal T (diagonal alpha, off-diagonal beta).  Taylor series of the
+// action on a vector with scaling, exp(-i tau T) = exp(-i (tau/s) T)^s, s
+// chosen so that |tau/s| |T|_inf <= 1/2; each factor's series is summed
+// until a term falls below 1e-18 of the partial sum.  Lane i holds
+// component i (j <= 64).
+__device__ inline void wave_small_expm(int j, const double* alpha, const double* beta, double tau,
+                                int lane, double& yr, double& yi) {
+  const double a = lane < j ? alpha[lane] : 0.0;
+  const double bl = (lane >= 1 && lane < j) ? beta[lane - 1] : 0.0;
+  const double bu = (lane + 1 < j) ? beta[lane] : 0.0;
+  const double nrm = wave_max(fabs(a) + fabs(bl) + fabs(bu));
+  const int s = max(1, static_cast<int>(ceil(fabs(tau) * nrm * 2.0)));
+  const double h = tau / s;
+  double zr = (lane == 0) ? 1.0 : 0.0, zi = 0.0;
+  for (int sub = 0; sub < s; ++sub) {
+    double tr = zr, ti = zi, sr = zr, si = zi;
+    for (int k = 1; k <= 60; ++k) {
+      const double tr_m = __shfl_up(tr, 1), ti_m = __shfl_up(ti, 1);
+      const double tr_p = __shfl_down(tr, 1), ti_p = __shfl_down(ti, 1);
+      const double ur = a * tr + bl * tr_m + bu * tr_p;
+      const double ui = a * ti + bl * ti_m + bu * ti_p;
+      const double f = h / k;
+      tr = f * ui;  // (-i f) (ur + i ui) = f ui - i f ur
+      ti = -f * ur;
+      sr += tr;
+      si += ti;
+      const double tm = wave_max(fabs(tr) + fabs(ti));
+      const double sm = wave_max(fabs(sr) + fabs(si));
+      if (tm <= 1e-18 * sm) break;
+    }
+    zr = sr;
+    zi = si;
+  }
+  yr = zr;
+  yi = zi;
+}
+
+// Krylov decision for Krylov dimension m = j (T_j complete: alpha[0..j-1],
+// beta[0..j-2]; the new off-diagonal beta_{j-1} = beta_new[v]); for j == 0
+// it starts the step (beta0 = beta_new).  One wave per vector; run by one
+// workgroup.  Alg. 6: y^(j) = exp(-i tau T_j) e_1, delta = |y^(j) - y^(j-1)|
+// / |y^(j)|, eps = min(1 + |y|, delta/(1-delta) |y|) (or 1 + |y| if
+// delta >= 1); stop when eps < tol or beta_{j-1} < |H| tol.
+template <int NV, int W = kWaves>
+__device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepCtl* ctl, int m_max, double tol,
+                              double norm_inf) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int v = wv; v < NV; v += W) {
+    VecState& S = st[v];
+    const double b = beta_new[v];
+    if (j == 0) {
+      if (lane == 0) {
+        S.beta0 = b;
+        S.scale[0] = b > 0.0 ? 1.0 / b : 0.0;
+        S.status = b > 0.0 ? 0 : 2;  // a zero vector stays zero
+        S.m = b > 0.0 ? 0 : 1;
+        S.eps = 0.0;
+        S.y[0] = 1.0;
+        S.y[1] = 0.0;
+      }
+      continue;
+    }
+    if (S.status != 0) continue;
+    double yr, yi;
+    // beta[j-1] is not part of T_j; store it after the exponential
+    wave_small_expm(j, S.alpha, S.beta, S.tau, lane, yr, yi);
+    const double pr = (lane < j - 1) ? S.y[2 * lane] : 0.0;
+    const double pi = (lane < j - 1) ? S.y[2 * lane + 1] : 0.0;
+    const double d2 = wave_sum((yr - pr) * (yr - pr) + (yi - pi) * (yi - pi));
+    const double y2 = wave_sum(yr * yr + yi * yi);
+    const double ny = sqrt(y2);
+    const double delta = sqrt(d2) / ny;
+    const double eps = (delta < 1.0) ? fmin(1.0 + ny, delta / (1.0 - delta) * ny) : 1.0 + ny;
+    if (lane < j) {
+      S.y[2 * lane] = yr;
+      S.y[2 * lane + 1] = yi;
+    }
+    if (lane == 0) {
+      S.beta[j - 1] = b;
+      S.eps = eps;
+      S.m = j;
+      int status = 0;
+      if (b < norm_inf * tol) status = 2;
+      else if (eps < tol) status = 1;
+      else if (j >= m_max) status = 3;
+      S.status = status;
+      S.scale[j] = (status == 0 && b > 0.0) ? 1.0 / b : 0.0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int done = 1, maxed = 0;
+    for (int v = 0; v < NV; ++v) {
+      done &= (st[v].status != 0);
+      maxed |= (st[v].status == 3);
+    }
+    ctl->all_done = done;
+    ctl->any_maxed = maxed;
+    ctl->iter = j;
+  }
+}
+
+// ---------------------------------------------------------------------------
+}  // namespace dev
+}  // namespace hub
