@@ -98,19 +98,7 @@ hub_status upload(hub_basis h, T** dst, const std::vector<T>& src) {
   return HUB_OK;
 }
 
-int pick_rows(const hub_basis h, int prec) {
-  const char* env = std::getenv(prec == 0 ? "HUB_ROWS_C128" : "HUB_ROWS_C64");
-  if (env) {
-    const int r = std::atoi(env);
-    if (r >= 1 && r <= 4) return r;
-  }
-  // largest row count that keeps >= 3 workgroups per CU (256 CUs) and <= 64 KB LDS
-  int best = 1;
-  for (int r = 2; r <= 4; r *= 2) {
-    if (hub::apply_grid(h->D, r) >= 768 && hub::apply_lds_bytes(h->D, prec, 1, r) <= 64 * 1024) best = r;
-  }
-  return best;
-}
+int pick_rows(const hub_basis, int) { return 1; }  // one tile row per apply workgroup
 
 hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t blockbuf_bytes) {
   const size_t need = slot_bytes * static_cast<size_t>(nslots);
@@ -128,9 +116,11 @@ hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t b
     HUB_HIP(hipMalloc(&h->blockbuf, blockbuf_bytes));
     h->blockbuf_bytes = blockbuf_bytes;
   }
-  // partial sums: apply grid * (1 + kObsQ) * nv doubles at most
-  const size_t pb = std::max<size_t>(static_cast<size_t>(h->D.dim_up) * (1 + kObsQ) * kMaxNV,
-                                     static_cast<size_t>(2048) * 2 * 64) * sizeof(double);
+  // partial sums of an apply: grid * (1 + kObsQ) * nv doubles at most
+  size_t pb = static_cast<size_t>(2048) * 2 * 64 * sizeof(double);
+  for (int pr = 0; pr < 2; ++pr)
+    for (int nv = 1; nv <= kMaxNV; nv *= 2)
+      pb = std::max(pb, static_cast<size_t>(hub::apply_grid(h->D, pr, nv)) * (1 + kObsQ) * nv * sizeof(double));
   if (pb > h->partials_bytes) {
     if (h->partials) HUB_HIP(hipFree(h->partials));
     h->partials = nullptr;
@@ -298,7 +288,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   L.prev_partials = h->partials_e;
   L.prev_nblk = hub::elem_grid(dim * nv);
   L.stream = stream;
-  const int agrid = hub::apply_grid(h->D, rows);
+  const int agrid = hub::apply_grid(h->D, pi, nv);
 
   // The decision for Krylov dimension m is taken by the first workgroup of
   // the m-th apply; iterations are enqueued speculatively up to the previous

@@ -22,7 +22,7 @@ namespace dev {
 // uniform over the workgroup), in independent batches of eight, each with a
 // uniform signed class coefficient.
 struct KArgs {
-  int dim_up, dim_dn, nc, j, nslots, m_max;
+  int dim_up, dim_dn, nc, j, nslots, m_max, chunks;
   double tol, norm_inf, U;
   const uint32_t* up_bits;
   const uint32_t* dn_bits;
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   constexpr bool kO = (MODE == M_LANCZOS_OBS || MODE == M_OBS);
   constexpr bool kW = (MODE != M_OBS);
   constexpr int kNQ = 1 + 3 + 2 * kMaxClasses;
-  constexpr int kUB = 8;  // up hops gathered in the first batch
+  constexpr int kUB = 4;  // up hops gathered before the staging barrier (more costs registers)
   __shared__ double red[kWavesA * kMaxNV];
   __shared__ double sh_beta[kMaxNV];
   __shared__ V sh_slot[NV > 1 ? 64 * NV : 1];
@@ -125,7 +125,13 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   V* __restrict__ y = static_cast<V*>(p.y);
   const int rowlen = p.dim_dn * NV;       // complex elements of one tile row
   const int half = (p.dim_dn + 1) * NV;   // one staged copy incl. the zero slot
-  const int a = xcd_remap(blockIdx.x, gridDim.x);
+  // workgroup = (row a, column chunk); the chunks of one row are consecutive
+  // logical blocks, so they run on one XCD and re-read the staged row from L2
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int a = lb / p.chunks;
+  const int cw = (rowlen + p.chunks - 1) / p.chunks;
+  const int qbeg = (lb % p.chunks) * cw;
+  const int qend = min(rowlen, qbeg + cw);
   const int hb = p.up_ptr[a], hcnt = p.up_ptr[a + 1] - hb;
   const uint32_t ua = p.up_bits[a];
   const double ea = p.eps_up ? p.eps_up[a] : 0.0;
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   // Global loads of this thread's first column (table entries, the first
   // batch of up-hop sources, the previous Lanczos vector) are issued before
   // the row is staged, so their latency overlaps the staging.
-  int q = tid;
+  int q = qbeg + tid;
   uint2 ev[kQ2];
   uint32_t eu[kUB];
   V tu[kUB];
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     for (int k = 0; k < kUB; ++k) tu[k] = (k < hcnt) ? x[(size_t)(eu[k] & 0xFFFFu) * rowlen + qq] : V{0, 0};
     if (kL && p.j > 0) pv = static_cast<const V*>(p.xprev)[(size_t)a * rowlen + qq];
   };
-  if (q < rowlen) load_column(q);
+  if (q < qend) load_column(q);
 
   // stage +x, -x (zero slot at column dim_dn of each copy)
   {
@@ -185,7 +191,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     q_pi[c] = 0.0;
   }
 
-  while (q < rowlen) {
+  while (q < qend) {
     const int b = q / NV;
     const uint32_t db = p.dn_bits[b];
     const double eb = p.eps_dn ? p.eps_dn[b] : 0.0;
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     }
     if (kW) y[idx] = out;
     q += kBlockA;
-    if (q < rowlen) load_column(q);
+    if (q < qend) load_column(q);
   }
 
   // workgroup partials: [alpha] [diag, docc, n2, (Re, Im) <x|K_c|x> ...]
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
       }
     }
   }
-  block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)a * nq * NV);
+  block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)lb * nq * NV);
 }
 
 template <typename R, int NV, int MODE, int MAXS, int BLK>
@@ -284,6 +290,7 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.j = L.j;
   p.nslots = db.nslots;
   p.m_max = L.m_max;
+  p.chunks = apply_chunks(db, L.prec, L.nv);
   p.tol = L.tol;
   p.norm_inf = L.norm_inf;
   p.U = db.U;

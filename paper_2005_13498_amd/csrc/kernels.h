@@ -85,7 +85,8 @@ struct ApplyLaunch {
 
 // Each launcher returns the hipError_t of its launch.
 hipError_t launch_apply(const ApplyLaunch& L, int* grid_out = nullptr);
-int apply_grid(const DevBasis& db, int rows);
+int apply_grid(const DevBasis& db, int prec, int nv);    // workgroups of one apply launch
+int apply_chunks(const DevBasis& db, int prec, int nv);  // column chunks per tile row
 int apply_nq(int mode, bool obs, int nc);
 size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows);
 int elem_grid(int64_t n);  // grid of the elementwise kernels (update, combine, norms)
