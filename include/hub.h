@@ -198,6 +198,44 @@ hub_status hub_propagate(hub_basis basis, const hub_pulse *pulses, double t_star
 hub_status hub_ground_state(hub_basis basis, double A, const hub_krylov_opts *opts,
                             void *v_out, double *E0, double *gap, void *stream);
 
+/* Creation (dagger = 1) or annihilation (dagger = 0) operator c_{site,spin}
+ * (spin 0 = up, 1 = down) from the sector of `from` to the sector of `to`
+ * (Eq. (creation-annihilation)): y_k = c x_k for nvec vectors (device, ABI
+ * layout; x in from's sector, y in to's).  Signs follow the spin-separated
+ * operator order of the basis (an up operator passes the up creators of lower
+ * sites; a down operator also passes all up creators).  Errors: HUB_E_SECTOR
+ * when `to` is not the operator's target sector, HUB_E_INVALID.  Synchronises
+ * `stream`. */
+hub_status hub_apply_cop(hub_basis from, hub_basis to, int32_t site, int32_t spin, int32_t dagger,
+                         hub_prec prec, int32_t nvec, const void *x, void *y, void *stream);
+
+/* out[2k] + i out[2k+1] = <x_k | y_k> (conjugate on x) for nvec pairs of
+ * device vectors of the basis's sector.  out: host [2 * nvec].  Fixed-order
+ * (reproducible) reduction.  Synchronises `stream`. */
+hub_status hub_dot(hub_basis basis, hub_prec prec, int32_t nvec, const void *x, const void *y, double *out,
+                   void *stream);
+
+/* Diagonal two-time Green's functions (Eq. (Glg), Sec. 3.7).  Member k applies
+ * op_k = c (dagger 0) or c^dag (dagger 1) on (site, spin) to psi(t'_k),
+ * t'_k = t_start + start_step * dt, propagates the result in op_k's sector with
+ * the midpoint Krylov stepper on the same time grid as psi, and records
+ *     o_k(s) = < op_k psi(t'_k + s dt) | phi_k(t'_k + s dt) >,  s = 0..n_rel,
+ * so that G^<(t', t'+s) = i o(s) for c and G^>(t'+s, t') = -i o(s) for c^dag.
+ * targets: host array of n_targets basis handles covering the members'
+ * sectors (matched by particle numbers); members sharing a sector are
+ * propagated together.  psi_inout: device vector of `basis` in precision
+ * `prec`, advanced in place to t_start + (max start_step + n_rel) dt.
+ * overlaps: host [n_members][n_rel + 1][2].  Synchronises `stream`. */
+typedef struct {
+  int32_t site, spin, dagger, start_step;
+} hub_greens_member;
+
+hub_status hub_greens_diag(hub_basis basis, int32_t n_targets, const hub_basis *targets,
+                           const hub_pulse *pulse, double t_start, double dt, int32_t n_rel,
+                           const hub_krylov_opts *opts, hub_prec prec, int32_t n_members,
+                           const hub_greens_member *members, void *psi_inout, double *overlaps,
+                           void *stream);
+
 /* Value of the pulse's A(t) (host arithmetic, as used by hub_propagate). */
 hub_status hub_pulse_A(const hub_pulse *pulse, double t, double *A);
 

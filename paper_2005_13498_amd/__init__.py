@@ -37,7 +37,7 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_basis_classes", "hub_basis_hops",
            "hub_apply_H", "hub_observables", "hub_krylov_expm_step", "hub_propagate",
            "hub_ground_state", "hub_pulse_A", "hub_last_error", "hub_profile_enable",
-           "hub_profile_read")
+           "hub_profile_read", "hub_apply_cop", "hub_dot", "hub_greens_diag")
 
 
 class HubError(RuntimeError):
@@ -66,6 +66,11 @@ class hub_krylov_opts(ctypes.Structure):
 class hub_step_info(ctypes.Structure):
     _fields_ = [("m_used", ctypes.c_int32), ("substeps", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("breakdown", ctypes.c_int32), ("err_est", ctypes.c_double), ("beta_last", ctypes.c_double)]
+
+
+class hub_greens_member(ctypes.Structure):
+    _fields_ = [("site", ctypes.c_int32), ("spin", ctypes.c_int32), ("dagger", ctypes.c_int32),
+                ("start_step", ctypes.c_int32)]
 
 
 class hub_obs(ctypes.Structure):
@@ -103,6 +108,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_last_error": ([], ctypes.c_char_p),
         "hub_profile_enable": ([vp, i32], i32),
         "hub_profile_read": ([vp, P(i64), P(dbl), P(dbl)], i32),
+        "hub_apply_cop": ([vp, vp, i32, i32, i32, i32, i32, vp, vp, vp], i32),
+        "hub_dot": ([vp, i32, i32, vp, vp, P(dbl), vp], i32),
+        "hub_greens_diag": ([vp, i32, P(vp), P(hub_pulse), dbl, dbl, i32, P(hub_krylov_opts), i32, i32,
+                             P(hub_greens_member), vp, P(dbl), vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -317,6 +326,36 @@ def hub_profile_read(h):
     n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
     _check(load_library().hub_profile_read(ctypes.c_void_p(h), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)))
     return n.value, ms.value, b.value
+
+
+def hub_apply_cop(h_from, h_to, site: int, spin: int, dagger: bool, x, y, nvec: int = 1, stream=None) -> None:
+    """y = c_{site,spin} x (dagger False) or c^dag x, from h_from's sector to h_to's."""
+    _check(load_library().hub_apply_cop(ctypes.c_void_p(h_from), ctypes.c_void_p(h_to), int(site), int(spin),
+                                        1 if dagger else 0, _prec_of(x), int(nvec), _dptr(x), _dptr(y),
+                                        _stream_ptr(stream)))
+
+
+def hub_dot(h, x, y, nvec: int = 1, stream=None) -> np.ndarray:
+    """<x_k|y_k> for nvec pairs (complex array)."""
+    out = np.zeros(2 * nvec)
+    _check(load_library().hub_dot(ctypes.c_void_p(h), _prec_of(x), int(nvec), _dptr(x), _dptr(y),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream)))
+    return out[0::2] + 1j * out[1::2]
+
+
+def hub_greens_diag(h, targets, pulse, t_start: float, dt: float, n_rel: int, opts, members, psi, stream=None):
+    """Overlaps o[k, s] (complex) of the members (site, spin, dagger, start_step)."""
+    nt = len(targets)
+    tarr = (ctypes.c_void_p * nt)(*[ctypes.c_void_p(t) for t in targets])
+    nm = len(members)
+    marr = (hub_greens_member * nm)(*[hub_greens_member(*[int(v) for v in m]) for m in members])
+    out = np.zeros(nm * (n_rel + 1) * 2)
+    p = make_pulse(pulse)
+    _check(load_library().hub_greens_diag(ctypes.c_void_p(h), nt, tarr, ctypes.byref(p), float(t_start), float(dt),
+                                          int(n_rel), ctypes.byref(opts), _prec_of(psi), nm, marr, _dptr(psi),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream)))
+    o = out.reshape(nm, n_rel + 1, 2)
+    return o[..., 0] + 1j * o[..., 1]
 
 
 class Basis:

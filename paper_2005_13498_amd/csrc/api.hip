@@ -784,6 +784,242 @@ hub_status hub_propagate(hub_basis h, const hub_pulse* pulses, double t_start, d
 }
 
 // ---------------------------------------------------------------------------
+// Creation / annihilation operators between sectors and overlaps (Sec. 2.5,
+// Sec. 3.7).  Spin-separated order: an up operator on site i passes the up
+// creators of sites < i; a down operator also passes all n_up up creators.
+namespace {
+
+struct OpMap {
+  std::vector<int32_t> map;
+  std::vector<int8_t> sgn;
+  bool down = false;
+};
+
+hub_status build_op_map(hub_basis from, hub_basis to, int site, int spin, int dagger, OpMap& M) {
+  if (!from || !to) return fail(HUB_E_INVALID, "null basis handle");
+  if (spin != 0 && spin != 1) return fail(HUB_E_INVALID, "spin must be 0 or 1");
+  const int ns = from->B.lat.n_sites;
+  if (site < 0 || site >= ns) return fail(HUB_E_INVALID, "site out of range");
+  if (to->B.lat.n_sites != ns) return fail(HUB_E_SECTOR, "bases belong to lattices of different size");
+  const int d = dagger ? 1 : -1;
+  const int nu = from->B.n_up + (spin == 0 ? d : 0), nd = from->B.n_dn + (spin == 1 ? d : 0);
+  if (to->B.n_up != nu || to->B.n_dn != nd) return fail(HUB_E_SECTOR, "target basis is not the operator's sector");
+  const hub::SpinTable& Tt = spin == 0 ? to->B.up : to->B.dn;
+  M.down = spin == 1;
+  M.map.assign(Tt.dim, -1);
+  M.sgn.assign(Tt.dim, 0);
+  const uint32_t bit = 1u << site;
+  for (int r = 0; r < Tt.dim; ++r) {
+    const uint32_t t = Tt.states[r];
+    uint32_t src;
+    if (dagger) {
+      if (!(t & bit)) continue;
+      src = t ^ bit;
+    } else {
+      if (t & bit) continue;
+      src = t | bit;
+    }
+    int sign = (__builtin_popcount(src & (bit - 1u)) & 1) ? -1 : 1;
+    if (spin == 1 && (from->B.n_up & 1)) sign = -sign;
+    M.map[r] = static_cast<int32_t>(hub::rank_of(src, ns));
+    M.sgn[r] = static_cast<int8_t>(sign);
+  }
+  return HUB_OK;
+}
+
+struct DevOpMap {
+  int32_t* map = nullptr;
+  int8_t* sgn = nullptr;
+  bool down = false;
+  void release() {
+    if (map) (void)hipFree(map);
+    if (sgn) (void)hipFree(sgn);
+    map = nullptr;
+    sgn = nullptr;
+  }
+};
+
+hub_status upload_op(hub_basis h, const OpMap& M, DevOpMap& D) {
+  D.down = M.down;
+  HUB_HIP(hipMalloc(reinterpret_cast<void**>(&D.map), M.map.size() * sizeof(int32_t)));
+  HUB_HIP(hipMalloc(reinterpret_cast<void**>(&D.sgn), M.sgn.size()));
+  HUB_HIP(hipMemcpy(D.map, M.map.data(), M.map.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HUB_HIP(hipMemcpy(D.sgn, M.sgn.data(), M.sgn.size(), hipMemcpyHostToDevice));
+  (void)h;
+  return HUB_OK;
+}
+
+}  // namespace
+
+hub_status hub_apply_cop(hub_basis from, hub_basis to, int32_t site, int32_t spin, int32_t dagger, hub_prec prec,
+                         int32_t nvec, const void* x, void* y, void* stream) {
+  hub_status s = check_common(from, prec, nvec);
+  if (s != HUB_OK) return s;
+  if (!to || to->device != from->device) return fail(HUB_E_INVALID, "target basis on another device");
+  if (!x || !y || x == y) return fail(HUB_E_INVALID, "x and y must be distinct device buffers");
+  OpMap M;
+  if ((s = build_op_map(from, to, site, spin, dagger, M)) != HUB_OK) return s;
+  DevOpMap D;
+  if ((s = upload_op(from, M, D)) != HUB_OK) {
+    D.release();
+    return s;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = hub::launch_cop(prec == HUB_C128 ? 0 : 1, to->D.dim, to->D.dim_dn, from->D.dim_dn,
+                                       from->D.dim, nvec, D.down, D.map, D.sgn, x, y, st);
+  const hipError_t e2 = hipStreamSynchronize(st);
+  D.release();
+  if (e != hipSuccess || e2 != hipSuccess) return fail(HUB_E_DEVICE, "operator kernel failed");
+  return HUB_OK;
+}
+
+hub_status hub_dot(hub_basis h, hub_prec prec, int32_t nvec, const void* x, const void* y, double* out,
+                   void* stream) {
+  hub_status s = check_common(h, prec, nvec);
+  if (s != HUB_OK) return s;
+  if (!x || !y || !out) return fail(HUB_E_INVALID, "null argument");
+  s = ensure_workspace(h, 16, 1, 0);
+  if (s != HUB_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* dout = nullptr;
+  HUB_HIP(hipMalloc(reinterpret_cast<void**>(&dout), 2 * nvec * sizeof(double)));
+  hipError_t e = hub::launch_dots(prec == HUB_C128 ? 0 : 1, h->D.dim, nvec, x, y, dout, h->partials_e, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 2 * nvec * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return fail(HUB_E_DEVICE, std::string("dot: ") + hipGetErrorString(e));
+  return HUB_OK;
+}
+
+hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targets, const hub_pulse* pulse,
+                           double t_start, double dt, int32_t n_rel, const hub_krylov_opts* opts, hub_prec prec,
+                           int32_t n_members, const hub_greens_member* members, void* psi_inout, double* overlaps,
+                           void* stream) {
+  hub_status s = check_common(h, prec, 1);
+  if (s != HUB_OK) return s;
+  if (!targets || !pulse || !opts || !members || !psi_inout || !overlaps || n_targets < 1 || n_members < 1 ||
+      n_rel < 0)
+    return fail(HUB_E_INVALID, "null or empty argument");
+  if ((s = check_opts(*opts)) != HUB_OK) return s;
+  if ((s = check_pulse(*pulse)) != HUB_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const size_t es = elem_bytes(prec);
+  // target basis of every member, members grouped by target and sorted by start
+  std::vector<int> tb(n_members, -1);
+  int max_start = 0;
+  for (int k = 0; k < n_members; ++k) {
+    const hub_greens_member& m = members[k];
+    if (m.start_step < 0) return fail(HUB_E_INVALID, "negative start step");
+    max_start = std::max(max_start, static_cast<int>(m.start_step));
+    const int d = m.dagger ? 1 : -1;
+    const int nu = h->B.n_up + (m.spin == 0 ? d : 0), nd = h->B.n_dn + (m.spin == 1 ? d : 0);
+    for (int g = 0; g < n_targets; ++g)
+      if (targets[g] && targets[g]->B.n_up == nu && targets[g]->B.n_dn == nd && targets[g]->device == h->device) {
+        tb[k] = g;
+        break;
+      }
+    if (tb[k] < 0) return fail(HUB_E_SECTOR, "no target basis for a member's sector");
+  }
+  std::vector<std::vector<int>> grp(n_targets);
+  for (int k = 0; k < n_members; ++k) grp[tb[k]].push_back(k);
+  for (auto& v : grp)
+    std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return members[a].start_step < members[b].start_step; });
+  // device buffers: member vectors per group, one scratch vector, op maps, overlaps
+  std::vector<void*> gbuf(n_targets, nullptr);
+  std::vector<DevOpMap> ops(n_members);
+  void* tmp = nullptr;
+  double* dover = nullptr;
+  auto cleanup = [&](hub_status r) {
+    for (void* p : gbuf)
+      if (p) (void)hipFree(p);
+    for (auto& o : ops) o.release();
+    if (tmp) (void)hipFree(tmp);
+    if (dover) (void)hipFree(dover);
+    return r;
+  };
+  int64_t maxdim = 0;
+  for (int g = 0; g < n_targets; ++g) {
+    if (grp[g].empty()) continue;
+    maxdim = std::max(maxdim, targets[g]->D.dim);
+    if (hipMalloc(&gbuf[g], grp[g].size() * targets[g]->D.dim * es) != hipSuccess)
+      return cleanup(fail(HUB_E_NOMEM, "member buffers"));
+  }
+  if (hipMalloc(&tmp, maxdim * es) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&dover), static_cast<size_t>(n_members) * (n_rel + 1) * 2 * sizeof(double)) !=
+          hipSuccess)
+    return cleanup(fail(HUB_E_NOMEM, "scratch buffers"));
+  for (int k = 0; k < n_members; ++k) {
+    OpMap M;
+    if ((s = build_op_map(h, targets[tb[k]], members[k].site, members[k].spin, members[k].dagger, M)) != HUB_OK)
+      return cleanup(s);
+    if ((s = upload_op(h, M, ops[k])) != HUB_OK) return cleanup(s);
+  }
+  if ((s = ensure_workspace(h, 16, 1, 0)) != HUB_OK) return cleanup(s);
+  auto slot_of = [&](int k) -> char* {
+    const auto& v = grp[tb[k]];
+    const size_t pos = static_cast<size_t>(std::find(v.begin(), v.end(), k) - v.begin());
+    return static_cast<char*>(gbuf[tb[k]]) + pos * targets[tb[k]]->D.dim * es;
+  };
+  auto op_psi = [&](int k, void* dst) -> hipError_t {
+    hub_basis T = targets[tb[k]];
+    return hub::launch_cop(pi, T->D.dim, T->D.dim_dn, h->D.dim_dn, h->D.dim, 1, ops[k].down, ops[k].map,
+                           ops[k].sgn, psi_inout, dst, st);
+  };
+  const int n_total = max_start + n_rel;
+  hub_krylov_opts o1 = *opts;
+  for (int n = 0; n <= n_total; ++n) {
+    for (int k = 0; k < n_members; ++k) {
+      const int sidx = n - members[k].start_step;
+      if (sidx == 0) {
+        if (op_psi(k, slot_of(k)) != hipSuccess) return cleanup(fail(HUB_E_DEVICE, "operator kernel"));
+      }
+      if (sidx >= 0 && sidx <= n_rel) {
+        hub_basis T = targets[tb[k]];
+        if (op_psi(k, tmp) != hipSuccess ||
+            hub::launch_dots(pi, T->D.dim, 1, tmp, slot_of(k),
+                             dover + (static_cast<size_t>(k) * (n_rel + 1) + sidx) * 2, T->partials_e ? T->partials_e
+                                                                                                : h->partials_e,
+                             st) != hipSuccess)
+          return cleanup(fail(HUB_E_DEVICE, "overlap kernels"));
+      }
+    }
+    if (n == n_total) break;
+    const double amid = pulse_value(*pulse, t_start + n * dt + 0.5 * dt);
+    // psi one step
+    {
+      std::vector<std::vector<double>> am(1, std::vector<double>(1, amid));
+      if ((s = run_all(h, prec, 1, psi_inout, 1, am, nullptr, 0.0, dt, o1, nullptr, nullptr, stream)) != HUB_OK)
+        return cleanup(s);
+    }
+    // active members of every target sector one step (contiguous, batched)
+    for (int g = 0; g < n_targets; ++g) {
+      const auto& v = grp[g];
+      int lo = -1, hi = -1;
+      for (size_t q = 0; q < v.size(); ++q) {
+        const int sidx = n - members[v[q]].start_step;
+        if (sidx >= 0 && sidx < n_rel) {
+          if (lo < 0) lo = static_cast<int>(q);
+          hi = static_cast<int>(q) + 1;
+        }
+      }
+      if (lo < 0) continue;
+      hub_basis T = targets[g];
+      if ((s = ensure_workspace(T, 16, 1, 0)) != HUB_OK) return cleanup(s);
+      std::vector<std::vector<double>> am(hi - lo, std::vector<double>(1, amid));
+      char* base = static_cast<char*>(gbuf[g]) + static_cast<size_t>(lo) * T->D.dim * es;
+      if ((s = run_all(T, prec, hi - lo, base, 1, am, nullptr, 0.0, dt, o1, nullptr, nullptr, stream)) != HUB_OK)
+        return cleanup(s);
+    }
+  }
+  if (hipMemcpyAsync(overlaps, dover, static_cast<size_t>(n_members) * (n_rel + 1) * 2 * sizeof(double),
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return cleanup(fail(HUB_E_DEVICE, "overlap copy"));
+  return cleanup(HUB_OK);
+}
+
+// ---------------------------------------------------------------------------
 // Ground state: restarted Lanczos with full reorthogonalisation (classical
 // Gram-Schmidt applied twice), complex double; Ritz pairs from the
 // tridiagonal by Jacobi rotations on the host.

@@ -127,6 +127,16 @@ hipError_t launch_site_docc(int prec, const DevBasis& db, const void* x, double*
 hipError_t launch_interleave(int prec, int nv, int64_t n, const void* src, void* dst, bool to_block,
                              hipStream_t s);
 
+// Creation/annihilation operator between sectors: y_k = op x_k for nvec
+// vectors (ABI layout).  map/sgn: per target row (up operator) or column
+// (down operator): source index (-1: none) and sign.
+hipError_t launch_cop(int prec, int64_t n_t, int dim_dn_t, int dim_dn_s, int64_t n_s, int nvec, bool down,
+                      const int32_t* map, const int8_t* sgn, const void* x, void* y, hipStream_t s);
+
+// out[2k], out[2k+1] = <x_k | y_k> for nvec pairs (device output, fixed order).
+hipError_t launch_dots(int prec, int64_t n, int nvec, const void* x, const void* y, double* out, double* partials,
+                       hipStream_t s);
+
 // BLAS-1 helpers for the ground-state Lanczos (complex double, one vector).
 hipError_t launch_multidot(int64_t n, const double2* const* vecs, int k, const double2* w, double2* out,
                            double* partials, hipStream_t s);

@@ -213,6 +213,53 @@ __global__ __launch_bounds__(kBlock) void k_site_docc(int dim_up, int dim_dn, in
   block_partials<1>(acc, n_sites, red, partials + (size_t)blockIdx.x * n_sites);
 }
 
+// y = sign * x at the mapped source element: a creation or annihilation
+// operator between two sectors.  For an up operator the map acts on tile rows
+// (map[a'] = source row, -1 = no source), for a down operator on columns.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cop(int64_t n_t, int dim_dn_t, int dim_dn_s, int64_t n_s, int nvec,
+                                                 int down, const int32_t* map, const int8_t* sgn,
+                                                 const typename CT<R>::T* x, typename CT<R>::T* y) {
+  using V = typename CT<R>::T;
+  const int64_t total = n_t * nvec;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const int64_t k = i / n_t, e = i % n_t;
+    const int a = static_cast<int>(e / dim_dn_t), b = static_cast<int>(e % dim_dn_t);
+    const int r = down ? b : a;
+    const int src = map[r];
+    V out = V{0, 0};
+    if (src >= 0) {
+      const int64_t se = down ? (int64_t)a * dim_dn_s + src : (int64_t)src * dim_dn_s + b;
+      const V v = x[k * n_s + se];
+      const R f = static_cast<R>(sgn[r]);
+      out = V{f * v.x, f * v.y};
+    }
+    y[i] = out;
+  }
+}
+
+// <x_k | y_k> partials for nvec vector pairs (ABI layout), [grid][2 * nvec].
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_dots(int64_t n, int nvec, const typename CT<R>::T* x,
+                                                  const typename CT<R>::T* y, double* partials) {
+  __shared__ double red[kWaves];
+  for (int k = 0; k < nvec; ++k) {
+    double re = 0.0, im = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+      const auto a = x[k * n + i];
+      const auto b = y[k * n + i];
+      re += (double)a.x * b.x + (double)a.y * b.y;
+      im += (double)a.x * b.y - (double)a.y * b.x;
+    }
+    re = block_sum(re, red);
+    im = block_sum(im, red);
+    if (threadIdx.x == 0) {
+      partials[(size_t)blockIdx.x * 2 * nvec + 2 * k] = re;
+      partials[(size_t)blockIdx.x * 2 * nvec + 2 * k + 1] = im;
+    }
+  }
+}
+
 // ------------------------------- BLAS-1 ------------------------------------
 __global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, const double2* const* vecs, int kv,
                                                      const double2* w, double* partials) {
@@ -449,6 +496,32 @@ hipError_t launch_site_docc(int prec, const DevBasis& db, const void* x, double*
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize(partials, grid, db.n_sites, out, 0, s);
+}
+
+hipError_t launch_cop(int prec, int64_t n_t, int dim_dn_t, int dim_dn_s, int64_t n_s, int nvec, bool down,
+                      const int32_t* map, const int8_t* sgn, const void* x, void* y, hipStream_t s) {
+  const int grid = elem_grid(n_t * nvec) * 4;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_cop<double>, dim3(grid), dim3(kBlock), 0, s, n_t, dim_dn_t, dim_dn_s, n_s, nvec,
+                       down ? 1 : 0, map, sgn, static_cast<const double2*>(x), static_cast<double2*>(y));
+  else
+    hipLaunchKernelGGL(k_cop<float>, dim3(grid), dim3(kBlock), 0, s, n_t, dim_dn_t, dim_dn_s, n_s, nvec,
+                       down ? 1 : 0, map, sgn, static_cast<const float2*>(x), static_cast<float2*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(int prec, int64_t n, int nvec, const void* x, const void* y, double* out, double* partials,
+                       hipStream_t s) {
+  const int grid = elem_grid(n);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_dots<double>, dim3(grid), dim3(kBlock), 0, s, n, nvec, static_cast<const double2*>(x),
+                       static_cast<const double2*>(y), partials);
+  else
+    hipLaunchKernelGGL(k_dots<float>, dim3(grid), dim3(kBlock), 0, s, n, nvec, static_cast<const float2*>(x),
+                       static_cast<const float2*>(y), partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(partials, grid, 2 * nvec, out, 0, s);
 }
 
 hipError_t launch_multidot(int64_t n, const double2* const* vecs, int k, const double2* w, double2* out,

@@ -1,0 +1,104 @@
+"""Creation/annihilation operators, overlaps and diagonal Green's functions
+(Eq. (Glg)) of the HIP path against the CPU oracle."""
+import numpy as np
+import pytest
+
+import paper_2005_13498_amd as hub
+from synth import ring, cluster_2d, PulseParams, random_state, workloads
+from oracle import HubbardOracle, to_canonical, ladder_matrix, pulse_A
+from oracle.fock import UP, DOWN, mode_index
+from oracle.greens import greens_diag
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(x, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV).to(dtype)
+
+
+@pytest.mark.parametrize("site,spin,dagger", [(0, 0, False), (3, 0, True), (2, 1, False), (5, 1, True),
+                                              (4, 0, False), (1, 1, True)])
+def test_apply_cop_matches_ladder_operator(site, spin, dagger):
+    lat = cluster_2d(3, 2)
+    nu, nd = 3, 2
+    d = 1 if dagger else -1
+    tu, td = (nu + d, nd) if spin == 0 else (nu, nd + d)
+    hs, ht = HubbardOracle(lat, 4.0, nu, nd), HubbardOracle(lat, 4.0, tu, td)
+    Bs, Bt = hub.Basis(lat, 4.0, nu, nd), hub.Basis(lat, 4.0, tu, td)
+    xs = random_state(hs.dim, seed=5, nvec=2)
+    Op = ladder_matrix(hs.states, ht.states, mode_index(site, spin), dagger)
+    ref = np.stack([to_canonical(Op @ v, ht.states, 6) for v in xs])
+    x = _dev(np.concatenate([to_canonical(v, hs.states, 6) for v in xs]))
+    y = torch.empty(2 * Bt.dim, dtype=torch.complex128, device=DEV)
+    hub.hub_apply_cop(Bs.handle, Bt.handle, site, spin, dagger, x, y, nvec=2)
+    assert np.allclose(y.cpu().numpy().reshape(2, -1), ref, atol=1e-15)
+    Bs.close()
+    Bt.close()
+
+
+def test_apply_cop_wrong_sector_rejected():
+    lat = ring(6)
+    Bs, Bt = hub.Basis(lat, 4.0, 3, 3), hub.Basis(lat, 4.0, 3, 2)
+    x = torch.zeros(Bs.dim, dtype=torch.complex128, device=DEV)
+    y = torch.zeros(Bt.dim, dtype=torch.complex128, device=DEV)
+    with pytest.raises(hub.HubError) as e:
+        hub.hub_apply_cop(Bs.handle, Bt.handle, 0, 0, False, x, y)   # c_up needs (2, 3)
+    assert e.value.status == hub.HUB_E_SECTOR
+    Bs.close()
+    Bt.close()
+
+
+def test_dot_batched():
+    B = hub.Basis(ring(6), 4.0, 3, 2)
+    a = random_state(B.dim, seed=1, nvec=3)
+    b = random_state(B.dim, seed=2, nvec=3)
+    got = hub.hub_dot(B.handle, _dev(a.ravel()), _dev(b.ravel()), nvec=3)
+    assert np.allclose(got, [np.vdot(a[k], b[k]) for k in range(3)], atol=1e-15)
+    B.close()
+
+
+def _greens_case(lat, U, nu, nd, members, n_rel, dt, pulse, prec, tol, seed=9):
+    ham = HubbardOracle(lat, U, nu, nd)
+    psi0 = random_state(ham.dim, seed=seed)[0]
+    B = hub.Basis(lat, U, nu, nd)
+    sectors = sorted({((nu + (1 if m[2] else -1), nd) if m[1] == 0 else (nu, nd + (1 if m[2] else -1)))
+                      for m in members})
+    T = [hub.Basis(lat, U, *sec) for sec in sectors]
+    dtype = torch.complex128 if prec == hub.HUB_C128 else torch.complex64
+    psi = _dev(to_canonical(psi0, ham.states, lat.n_sites), dtype)
+    got = hub.hub_greens_diag(B.handle, [t.handle for t in T], pulse, 0.0, dt, n_rel,
+                              hub.make_opts(tol=tol, m_max=30), members, psi)
+    oh = {sec: HubbardOracle(lat, U, *sec) for sec in sectors}
+    for k, (site, spin, dagger, start) in enumerate(members):
+        sec = (nu + (1 if dagger else -1), nd) if spin == 0 else (nu, nd + (1 if dagger else -1))
+        ref = greens_diag(ham, psi0, pulse, 0.0, dt, start, n_rel, site, spin, bool(dagger), ham_target=oh[sec])
+        yield k, got[k], ref
+    B.close()
+    for t in T:
+        t.close()
+
+
+def test_greens_diag_c128_matches_oracle():
+    members = [(0, 0, 0, 0), (2, 1, 1, 3), (3, 0, 0, 2), (1, 0, 1, 0), (4, 1, 0, 1), (5, 1, 0, 2)]
+    p = PulseParams(0, 0.6, 6.0, 0.2, 0.2)
+    for k, got, ref in _greens_case(ring(6), 4.0, 3, 3, members, 12, 0.05, p, hub.HUB_C128, 1e-13):
+        assert np.max(np.abs(got - ref)) < 1e-10, (k, np.max(np.abs(got - ref)))
+
+
+def test_greens_diag_c64_within_1e5():
+    members = [(0, 0, 0, 0), (2, 1, 1, 3), (3, 0, 1, 2), (4, 1, 0, 1)]
+    p = PulseParams(0, 0.6, 6.0, 0.2, 0.2)
+    for k, got, ref in _greens_case(ring(8), 8.0, 4, 4, members, 20, 0.02, p, hub.HUB_C64, 1e-8):
+        assert np.max(np.abs(got - ref)) < 1e-5, (k, np.max(np.abs(got - ref)))
+
+
+def test_greens_ring10_workload_sampled():
+    """10-site ring, U = 8, 5/5 (dim 63,504), members in the (4,5), (6,5),
+    (5,4), (5,6) sectors (dim 52,920) with staggered starts, complex64 apply
+    with FP64 Lanczos scalars; first 15 relative steps against the oracle."""
+    w = workloads()["ring10_greens"]
+    members = [(0, 0, 0, 0), (3, 0, 1, 5), (6, 1, 0, 10), (9, 1, 1, 0)]
+    for k, got, ref in _greens_case(w.lattice, w.U, 5, 5, members, 15, w.dt, w.pulse, hub.HUB_C64, 1e-8):
+        assert np.max(np.abs(got - ref)) < 1e-5, (k, np.max(np.abs(got - ref)))

@@ -516,3 +516,62 @@ def test_onsite_energy_enters_with_plus_sign():
     ev = np.sort(np.linalg.eigvalsh(h2.H(0.0).toarray()))
     ref = sorted(eps[i] + eps[j] + (3.0 if i == j else 0.0) for i in range(3) for j in range(3))
     assert np.allclose(ev, ref)
+
+
+# --------------------------------------------------------------------------
+# Green's functions (Eq. (Glg))
+
+def test_greens_equal_time_sum_rule():
+    """G^>(t,t) - G^<(t,t) = -i <{c, c^dag}> = -i for a normalised state."""
+    from oracle.greens import greens_diag
+    lat = ring(6)
+    h = HubbardOracle(lat, 4.0, 3, 3)
+    psi = random_state(h.dim, seed=31)[0]
+    p = PulseParams(0, 0.5, 6.0, 0.1, 0.2)
+    for site, spin in ((0, UP), (3, DOWN)):
+        ol = greens_diag(h, psi, p, 0.0, 0.05, 2, 0, site, spin, dagger=False)
+        og = greens_diag(h, psi, p, 0.0, 0.05, 2, 0, site, spin, dagger=True)
+        assert (-1j * og[0]) - (1j * ol[0]) == pytest.approx(-1j, abs=1e-13)
+
+
+def test_greens_equilibrium_matches_lehmann():
+    """A = 0 from the ground state: the propagated overlap equals the Lehmann
+    sum over the eigenstates of the N-1 (N+1) sector, up to the midpoint
+    stepper being exact for time-independent H."""
+    from oracle.greens import greens_diag, lehmann_overlap
+    lat = ring(6)
+    h = HubbardOracle(lat, 4.0, 3, 3)
+    E0, _, g = ground_state(h, 0.0)
+    p = PulseParams(0, 0.0, 1.0, 0.0, 1.0)
+    for dagger, tgt in ((False, (2, 3)), (True, (4, 3))):
+        ht = HubbardOracle(lat, 4.0, *tgt)
+        o = greens_diag(h, g, p, 0.0, 0.1, 0, 15, 0, UP, dagger, ham_target=ht)
+        ref = lehmann_overlap(h, g, E0, ht, 0, UP, dagger, 0.1 * np.arange(16))
+        assert np.allclose(o, ref, atol=1e-12)
+    # half filling: G^<_ii(t,t) = i/2 on the ring
+    o = greens_diag(h, g, p, 0.0, 0.1, 0, 0, 2, DOWN, False)
+    assert 1j * o[0] == pytest.approx(0.5j, abs=1e-12)
+
+
+def test_greens_free_fermion_closed_form_with_pulse():
+    """U = 0: G^<_ii(t, t') = i sum_occupied Phi_k,i(t) conj(Phi_k,i(t')) with
+    the orbitals propagated by the same midpoint steps."""
+    from oracle.greens import greens_diag
+    lat = ring(6)
+    h = HubbardOracle(lat, 0.0, 2, 3)
+    p = PulseParams(0, 0.7, 5.0, 0.2, 0.25)
+    rng = np.random.default_rng(4)
+    phis = [np.linalg.qr(rng.standard_normal((6, 2)) + 1j * rng.standard_normal((6, 2)))[0],
+            np.linalg.qr(rng.standard_normal((6, 3)) + 1j * rng.standard_normal((6, 3)))[0]]
+    psi0 = ff.slater_vector(phis[0], phis[1], h)
+    dt, start, nrel, site = 0.05, 3, 10, 4
+    for spin in (UP, DOWN):
+        o = greens_diag(h, psi0, p, 0.0, dt, start, nrel, site, spin, False)
+        ph = [q.copy() for q in phis]
+        hist = []
+        for n in range(start + nrel + 1):
+            hist.append(ph[spin][site, :].copy())
+            ph = ff.step(lat, ph, n * dt, dt, p)
+        ref = [np.sum(hist[start + s] * np.conj(hist[start])) for s in range(nrel + 1)]
+        # o(s) = <c psi(t'+s)| U c psi(t')> = <c^dag(t'+s) c(t')> = sum_k Phi(t') conj(Phi(t'+s))
+        assert np.allclose(o, np.conj(ref), atol=1e-12)
