@@ -29,6 +29,104 @@ if ROOT not in sys.path:
 
 METRIC = "H·v HBM GB/s + midpoint steps/s at 12 sites: mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+DOMINANT_KERNEL = "k_apply<double, 1, 1, "  # Lanczos-mode H*v, complex128, one vector
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_apply_lanczos_c128_cluster3x4_counters.txt")
+KERNEL_SOURCES = ("paper_2005_13498_amd/csrc/apply_impl.h", "paper_2005_13498_amd/csrc/kernels_common.h",
+                  "paper_2005_13498_amd/csrc/apply_c128.hip")
+COPY_BYTES = 256 << 20  # calibration copy: bytes read (and written) per launch
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None if there is none or the kernel sources changed since."""
+    try:
+        kv = {}
+        with open(COUNTERS_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _rows(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -> None:
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the dominant kernel and of
+    the calibration copy, scaled by the copy's known bytes, written as text."""
+    def per_kernel(d, counter):
+        vals = {}
+        for r in _rows(_find(d, "counter_collection.csv")):
+            if r.get("Counter_Name") != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    lines = [f"# HBM traffic of the Lanczos-mode H*v (complex128, 12-site 3x4, dim 853776)",
+             f"# command: {command}",
+             "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by what it reads for a",
+             f"# copy of {COPY_BYTES} bytes (torch elementwise neg, bench.py --copy-calibration)."]
+    res = {}
+    for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        v = per_kernel(d, counter)
+        dom = [k for k in v if DOMINANT_KERNEL in k]
+        cp = [k for k in v if "neg_kernel" in k]
+        if not dom or not cp:
+            raise SystemExit(f"{counter}: dominant kernel or copy kernel missing: {sorted(v)[:8]}")
+        import statistics
+        kib = statistics.mean(v[dom[0]])
+        cpk = max(statistics.mean(v[k]) for k in cp)
+        factor = COPY_BYTES / (cpk * 1024.0)
+        res[name] = kib * 1024.0 * factor
+        lines += [f"{counter}_kernel: {dom[0]}", f"{counter}_dispatches: {len(v[dom[0]])}",
+                  f"{counter}_kib_per_dispatch: {kib:.1f}", f"{counter}_copy_kib_per_dispatch: {cpk:.1f}",
+                  f"{counter}_copy_scale: {factor:.4f}"]
+    lines += [f"hbm_fetch_bytes_per_launch: {res['fetch']:.0f}", f"hbm_write_bytes_per_launch: {res['write']:.0f}",
+              f"hbm_bytes_per_launch: {res['fetch'] + res['write']:.0f}",
+              f"algorithmic_bytes_per_launch: {2 * 853776 * 16}",
+              f"kernel_source_sha256_16: {kernel_source_hash()}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_stats(trace_dir: str, out: str, command: str, top: int = 12) -> None:
+    """Top kernels of a --kernel-trace --stats run as text."""
+    rows = _rows(_find(trace_dir, "kernel_stats.csv"))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}",
+             f"{'calls':>8} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
+    for r in rows[:top]:
+        lines.append(f"{int(r['Calls']):>8} {float(r['AverageNs']) / 1e3:>10.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}  {r['Name'][:150]}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(seconds: float) -> dict:
@@ -74,6 +172,49 @@ def cpu_baseline(seconds: float) -> dict:
                       f"{float(np.mean(ms)):.2f}, {hv} H*v in {el:.1f} s, 1 thread)"}
 
 
+def batched_variants(hub, B, v0, w, steps: int) -> dict:
+    """Mixed precision and batching at 12 sites: the same ground state under
+    8 pulse amplitudes (the seeded A0 draws), propagated as one interleaved
+    block in complex64 (FP64 Lanczos scalars) and in complex128; member-steps/s
+    of both, the block apply's GB/s, and the complex64 errors in d(t), E(t)
+    against the complex128 block (max over members and sample times)."""
+    import numpy as np
+    import torch
+    from synth import PulseParams
+
+    pulses = [PulseParams(0, a, w.pulse.omega, w.pulse.t0, w.pulse.sigma) for a in w.extra["A0_batch"]]
+    nv = len(pulses)
+    opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+    res = {}
+    obs = {}
+    for name, dtype, prec_bytes in (("c64_block8", torch.complex64, 8), ("c128_block8", torch.complex128, 16)):
+        v = v0.to(dtype).repeat(nv).contiguous()
+        hub.hub_propagate(B.handle, pulses, 0.0, w.dt, 5, opts, v, want_obs=False)  # warm-up
+        v = v0.to(dtype).repeat(nv).contiguous()
+        hub.hub_profile_enable(B.handle, True)
+        hub.hub_profile_read(B.handle)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, o, log = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, steps, opts, v)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        launches, kms, bpl = hub.hub_profile_read(B.handle)
+        hub.hub_profile_enable(B.handle, False)
+        us = kms / max(launches, 1) * 1e3
+        res[name] = {"member_steps_per_s": nv * steps / el, "ms_per_step": el / steps * 1e3,
+                     "hv_avg_launch_us": us, "hv_gbps": bpl / (us * 1e-6) / 1e9 if launches else 0.0,
+                     "hv_bytes_per_launch": bpl, "mean_krylov_m": float(np.mean(log[:, :, 0]))}
+        obs[name] = o
+        print(f"[bench] {name}: {nv * steps / el:.0f} member-steps/s, H*v {us:.1f} us", file=sys.stderr, flush=True)
+    d64, d128 = obs["c64_block8"][:, :, 3], obs["c128_block8"][:, :, 3]
+    e64, e128 = obs["c64_block8"][:, :, 2], obs["c128_block8"][:, :, 2]
+    res["c64_vs_c128"] = {"max_abs_docc_err": float(np.max(np.abs(d64 - d128))),
+                          "max_abs_energy_per_site_err": float(np.max(np.abs(e64 - e128))),
+                          "max_abs_norm_drift": float(np.max(np.abs(obs["c64_block8"][:, :, 1] - 1.0)))}
+    res["speedup_c64_block8_vs_plain_c128"] = None  # filled by the caller
+    return res
+
+
 def run_cpu_baseline_child(seconds: float) -> dict:
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -94,11 +235,23 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run a plain copy of known size (counter scaling)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("TRACE_DIR", "OUT"))
+    ap.add_argument("--command", default="", help="profiling command recorded in a summary")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline(args.cpu_seconds)))
+        return 0
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, command=args.command)
+        return 0
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats, command=args.command)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -121,6 +274,7 @@ def main() -> int:
     A0 = hub.hub_pulse_A(w.pulse, 0.0)
     st, e0, gap = hub.hub_ground_state(B.handle, A0, v, hub.make_opts(tol=1e-12, m_max=100))
     print(f"[bench] ground state E0={e0:.12f} gap={gap:.4f}", file=sys.stderr, flush=True)
+    v0 = v.clone()
     opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
     stream = torch.cuda.current_stream()
 
@@ -167,10 +321,21 @@ def main() -> int:
                    "A0": w.pulse.A0, "omega": w.pulse.omega, "t0": w.pulse.t0, "sigma": w.pulse.sigma,
                    "mean_krylov_m": mean_m, "hv_launches": launches},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_apply (matrix-free H*v, Lanczos epilogue)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_apply<double,1,M_LANCZOS> (matrix-free H*v with the Lanczos epilogue)",
                      "bytes_per_launch": bytes_per, "avg_launch_us": avg_us},
     }
+    if args.copy_calibration:
+        a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.neg(a, out=b)  # plain elementwise kernel: reads and writes COPY_BYTES
+        torch.cuda.synchronize()
+        del a, b
+    if not args.no_variants:
+        var = batched_variants(hub, B, v0, w, args.steps)
+        var["speedup_c64_block8_vs_plain_c128"] = var["c64_block8"]["member_steps_per_s"] / steps_per_s
+        out["variants"] = var
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = run_cpu_baseline_child(args.cpu_seconds)

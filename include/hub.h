@@ -244,8 +244,9 @@ const char *hub_last_error(void);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing of the matrix-free apply (for roofline reporting).  While
- * enabled, the library brackets every H*v launch with HIP events on the
- * launch stream.  hub_profile_read returns the number of timed launches, the
+ * enabled, the library brackets with HIP events on the launch stream every
+ * hub_apply_H launch and every Lanczos H*v launch of a propagation except the
+ * first of each step that records observables (a different kernel).  hub_profile_read returns the number of timed launches, the
  * summed kernel time in ms, and the algorithmic bytes of one launch
  * (2 * nvec * dim * complex size: read x once, write y once) of the last
  * timed launch, then resets the counters.  Synchronises the device. */

@@ -181,9 +181,13 @@ hub_status check_common(hub_basis h, hub_prec prec, int32_t nvec) {
   return HUB_OK;
 }
 
+// Events bracket plain applies (hub_apply_H) and Lanczos-mode applies that do
+// not also accumulate observables, so a propagation's recorded average is
+// that of one kernel.
 hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->prof) {
+  const bool timed = h->prof && (L.mode == hub::kPlain || (L.mode == hub::kLanczos && !L.obs));
+  if (timed) {
     if (!h->ev_free.empty()) {
       e0 = h->ev_free.back().first;
       e1 = h->ev_free.back().second;
@@ -195,7 +199,7 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L) {
     HUB_HIP(hipEventRecord(e0, L.stream));
   }
   HUB_HIP(hub::launch_apply(L));
-  if (h->prof) {
+  if (timed) {
     HUB_HIP(hipEventRecord(e1, L.stream));
     h->ev_used.push_back({e0, e1});
     h->prof_bytes = 2.0 * L.nv * static_cast<double>(h->D.dim) * (L.prec == 0 ? 16.0 : 8.0);
@@ -203,10 +207,12 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L) {
   return HUB_OK;
 }
 
-// Group sizes for nvec vectors: powers of two up to 8 whose staged row fits in LDS.
+// Group sizes for nvec vectors: powers of two up to 8 whose staged row keeps
+// at least three apply workgroups per CU (<= 48 KB of the 160 KB LDS), or one
+// vector per group.
 std::vector<int> groups_for(hub_basis h, int nvec, int prec) {
   int gmax = kMaxNV;
-  while (gmax > 1 && hub::apply_lds_bytes(h->D, prec, gmax, 1) > 160 * 1024) gmax /= 2;
+  while (gmax > 1 && hub::apply_lds_bytes(h->D, prec, gmax, 1) > 48 * 1024) gmax /= 2;
   std::vector<int> g;
   int left = nvec;
   while (left > 0) {
@@ -292,7 +298,8 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
 
   // The decision for Krylov dimension m is taken by the first workgroup of
   // the m-th apply; iterations are enqueued speculatively up to the previous
-  // step's m plus one, later kernels exit at once when the step is decided.
+  // step's m (a step that needs more waits for one host round trip per extra
+  // iteration; kernels past the decision exit at once).
   int m_pred = o.m_hint > 0 ? std::min(o.m_hint, o.m_max) : std::min(8, o.m_max);
   bool first = true;
   *not_converged = false;
@@ -344,8 +351,8 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
                                    stream));
       if (maxed) break;
     }
-    // next step's speculative depth: the deepest this step needed, plus one
-    m_pred = std::min(o.m_max, m_step_max + 1);
+    // next step's speculative depth: the deepest this step needed
+    m_pred = std::max(1, std::min(o.m_max, m_step_max));
     *steps_done = n + 1;
     if (maxed) {  // stop at the first step where a vector hit m_max
       *not_converged = true;

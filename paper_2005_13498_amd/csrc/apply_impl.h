@@ -63,24 +63,31 @@ __device__ __forceinline__ void add_class(double (&pr)[kMaxClasses], double (&pi
 // observables pass use 256 (more workgroups per CU, more registers per thread).
 constexpr int kRowsLong = 2048;
 
-// Per-quantity workgroup reduction with a small LDS buffer (W waves, NV
-// interleaved vectors): out[q * NV + v] = sum over the workgroup's threads of
-// vector v.  Fixed order.
-template <int NV, int W>
-__device__ void block_partials_seq(const double* vals, int nq, double* lds, double* out) {
+// Per-quantity workgroup reduction (W waves, NV interleaved vectors):
+// out[q * NV + v] = sum over the workgroup's threads of vector v, for q < nq.
+// Each wave reduces every quantity with shuffles (static indices keep vals in
+// registers), leaves its sums in lds[(w * nq + q) * NV + v] (lds holds at
+// least W * nq * NV doubles), and after one
+// barrier the first nq * NV threads add the W wave sums in a fixed order.
+template <int NV, int W, int NQ>
+__device__ __forceinline__ void block_partials_seq(const double (&vals)[NQ], int nq, double* lds, double* out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int q = 0; q < nq; ++q) {
-    double v = vals[q];
 #pragma unroll
-    for (int off = 32; off >= NV; off >>= 1) v += __shfl_xor(v, off);
-    __syncthreads();
-    if (lane < NV) lds[w * NV + lane] = v;
-    __syncthreads();
-    if (threadIdx.x < NV) {
-      double s = 0.0;
-      for (int k = 0; k < W; ++k) s += lds[k * NV + threadIdx.x];
-      out[q * NV + threadIdx.x] = s;
+  for (int q = 0; q < NQ; ++q) {
+    if (q < nq) {
+      double v = vals[q];
+#pragma unroll
+      for (int off = 32; off >= NV; off >>= 1) v += __shfl_xor(v, off);
+      if (lane < NV) lds[(w * nq + q) * NV + lane] = v;
     }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < nq * NV) {
+    const int q = t / NV, v = t % NV;
+    double s = 0.0;
+    for (int k = 0; k < W; ++k) s += lds[(k * nq + q) * NV + v];
+    out[q * NV + v] = s;
   }
 }
 
@@ -92,9 +99,9 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   constexpr bool kL = (MODE == M_LANCZOS || MODE == M_LANCZOS_OBS);
   constexpr bool kO = (MODE == M_LANCZOS_OBS || MODE == M_OBS);
   constexpr bool kW = (MODE != M_OBS);
-  constexpr int kNQ = 1 + 3 + 2 * kMaxClasses;
+  constexpr int kNQ = 1 + 3 + 2 * kMaxClasses;  // alpha, diag, docc, n2, classes
   constexpr int kUB = 4;  // up hops gathered before the staging barrier (more costs registers)
-  __shared__ double red[kWavesA * kMaxNV];
+  __shared__ double red[kWavesA * NV * (kO ? kNQ : 1) + kWavesA];
   __shared__ double sh_beta[kMaxNV];
   __shared__ V sh_slot[NV > 1 ? 64 * NV : 1];
   __shared__ V sh_up[NV > 1 ? 2 * kMaxClasses * NV : 1];
@@ -262,19 +269,17 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   const int nqO = kO ? 3 + 2 * nc : 0;
   const int nq = nqL + nqO;
   if (nq == 0) return;
+  // fixed positions (class c at nqL + 3 + 2c) keep the array in registers
   double vals[kNQ];
-  int k = 0;
-  if (kL) vals[k++] = q_alpha;
+  if (kL) vals[0] = q_alpha;
   if (kO) {
-    vals[k++] = q_diag;
-    vals[k++] = q_docc;
-    vals[k++] = q_n2;
+    vals[nqL + 0] = q_diag;
+    vals[nqL + 1] = q_docc;
+    vals[nqL + 2] = q_n2;
 #pragma unroll
     for (int cc = 0; cc < kMaxClasses; ++cc) {
-      if (cc < nc) {
-        vals[k++] = q_pr[cc];
-        vals[k++] = q_pi[cc];
-      }
+      vals[nqL + 3 + 2 * cc] = q_pr[cc];
+      vals[nqL + 4 + 2 * cc] = q_pi[cc];
     }
   }
   block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)lb * nq * NV);
@@ -360,12 +365,16 @@ hipError_t apply_s(const ApplyLaunch& L, int grid, size_t lds) {
 
 template <typename R, int NV>
 hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds) {
-  const bool longrow = NV == 1 && L.db->dim_dn >= kRowsLong;
-  if (L.mode == kPlain)
-    return longrow ? apply_s<R, NV, M_PLAIN, 1024>(L, grid, lds) : apply_s<R, NV, M_PLAIN, 256>(L, grid, lds);
+  if constexpr (NV == 1) {
+    if (L.db->dim_dn >= kRowsLong) {
+      if (L.mode == kPlain) return apply_s<R, 1, M_PLAIN, 1024>(L, grid, lds);
+      if (L.mode != kObsOnly && !L.obs) return apply_s<R, 1, M_LANCZOS, 1024>(L, grid, lds);
+    }
+  }
+  if (L.mode == kPlain) return apply_s<R, NV, M_PLAIN, 256>(L, grid, lds);
   if (L.mode == kObsOnly) return apply_s<R, NV, M_OBS, 256>(L, grid, lds);
   if (L.obs) return apply_s<R, NV, M_LANCZOS_OBS, 256>(L, grid, lds);
-  return longrow ? apply_s<R, NV, M_LANCZOS, 1024>(L, grid, lds) : apply_s<R, NV, M_LANCZOS, 256>(L, grid, lds);
+  return apply_s<R, NV, M_LANCZOS, 256>(L, grid, lds);
 }
 
 template <typename R>
