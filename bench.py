@@ -215,6 +215,49 @@ def batched_variants(hub, B, v0, w, steps: int) -> dict:
     return res
 
 
+def controller_variant(hub, B, w, v0, v_start, t_start: float, steps: int, v_plain, obs_plain, plain_steps_per_s):
+    """Learned controller at 12 sites: trained on adaptive logs of four other
+    seeded amplitudes (A0 draws 2..5, 1000 steps from the ground state,
+    untimed), then the timed
+    workload again from the same start vector with the controlled schedule.
+    Reports steps/s, the schedule counters, and that vector and observables
+    are bit-identical to the plain run."""
+    import numpy as np
+    import torch
+    from synth import PulseParams
+    from paper_2005_13498_amd import controller as ctl
+
+    opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+    chunk, margin = 16, 1
+    t0 = time.perf_counter()
+    pulses = [PulseParams(0, a, w.pulse.omega, w.pulse.t0, w.pulse.sigma) for a in w.extra["A0_batch"][1:5]]
+    X, Y = ctl.collect_rows(B, v0, pulses, 0.0, w.dt, 1000, opts, chunk=chunk)
+    params, hist = ctl.train(X, Y, steps=600, lr=3e-3, seed=0)
+    t_train = time.perf_counter() - t0
+    hub.hub_controller_load(B.handle, params)
+    hub.hub_controller_enable(B.handle, True, chunk, margin)
+    v = v_start.clone()
+    hub.hub_propagate(B.handle, [w.pulse], t_start, w.dt, 10, opts, v.clone())  # warm-up of the schedule
+    hub.hub_controller_read_stats(B.handle)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, obs, log = hub.hub_propagate(B.handle, [w.pulse], t_start, w.dt, steps, opts, v)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    stats = hub.hub_controller_read_stats(B.handle)
+    hub.hub_controller_enable(B.handle, False)
+    same = bool(torch.equal(v, v_plain)) and bool(np.array_equal(obs, obs_plain))
+    print(f"[bench] controller: {steps / el:.0f} steps/s, fallbacks {stats['fallbacks']}, "
+          f"bit-identical {same}", file=sys.stderr, flush=True)
+    return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3,
+            "speedup_vs_adaptive": steps / el / plain_steps_per_s, "bit_identical_to_adaptive": same,
+            "chunk": chunk, "margin": margin, "fallbacks": stats["fallbacks"], "chunks": stats["chunks"],
+            "lanczos_launches_per_step": stats["lanczos_launches"] / max(1, stats["steps"]),
+            "krylov_m_per_step": stats["iterations"] / max(1, stats["steps"]),
+            "train_rows": int(len(X)), "train_loss_first_last": [hist[0][1], hist[-1][1]],
+            "train_seconds_untimed": t_train}
+
+
 def run_cpu_baseline_child(seconds: float) -> dict:
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -285,6 +328,7 @@ def main() -> int:
         t_start += args.warmup * w.dt
     torch.cuda.synchronize()
 
+    v_start = v.clone()
     # timed region: exactly K midpoint steps
     hub.hub_profile_enable(B.handle, True)
     hub.hub_profile_read(B.handle)  # reset counters
@@ -334,6 +378,7 @@ def main() -> int:
         del a, b
     if not args.no_variants:
         var = batched_variants(hub, B, v0, w, args.steps)
+        var["controller"] = controller_variant(hub, B, w, v0, v_start, t_start, args.steps, v, obs, steps_per_s)
         var["speedup_c64_block8_vs_plain_c128"] = var["c64_block8"]["member_steps_per_s"] / steps_per_s
         out["variants"] = var
     if not args.no_cpu_baseline:

@@ -243,6 +243,83 @@ hub_status hub_pulse_A(const hub_pulse *pulse, double t, double *A);
 const char *hub_last_error(void);
 
 /* ------------------------------------------------------------------------ */
+/* Learned Krylov controller.  Not in the paper: a schedule optimisation on
+ * top of Alg. 6 that never changes results.  A small FP32 MLP
+ *     x (8) -> 64 -> GELU -> 64 -> GELU -> 2,   GELU(z) = z (1 + erf(z/sqrt2)) / 2
+ * predicts, for each step of a chunk of upcoming midpoint steps, o[0] =
+ * log2 of the Krylov dimension m the adaptive step will use and o[1] = log2
+ * of the substep count (trained but not used by the scheduler: in this
+ * library one substep is always the cheapest choice).  Features of the row
+ * for step n, whose history ends at step h <= n - 1 (the last step finished
+ * when the chunk was planned):
+ *     x[0] = A(t_mid_n)            x[1] = A'(t_mid_n) / 10
+ *     x[2] = tau |H|_inf           (tau = dt / substeps; |H|_inf as in Alg. 6)
+ *     x[3..6] = log10(eps_{h-k}) / 10, k = 0..3   (a-posteriori estimate of
+ *               step h-k, floored at 1e-40; log10(tol)/10 before step 0)
+ *     x[7] = m_h / 10              (m_hint / 10, or 0.8, before step 0)
+ * Parameters (HUB_MLP_NPARAM floats, row-major, output unit first):
+ *     W1[64][8], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
+ * When enabled on a handle, hub_propagate plans `chunk` steps at a time: one
+ * MLP launch predicts m for each, each step gets ceil(2^o[0]) + margin + 1
+ * Lanczos launches (capped by m_max + 1) without host synchronisation, and
+ * the adaptive test of Alg. 6 still decides every step on the device.  A
+ * step that is not decided within its launches is abandoned unchanged (the
+ * rest of the chunk does nothing) and re-run with the adaptive schedule.
+ * Results are therefore bit-identical to the adaptive schedule. */
+#define HUB_MLP_IN 8
+#define HUB_MLP_HID 64
+#define HUB_MLP_OUT 2
+#define HUB_MLP_NPARAM (HUB_MLP_HID * HUB_MLP_IN + HUB_MLP_HID + HUB_MLP_HID * HUB_MLP_HID + HUB_MLP_HID + \
+                        HUB_MLP_OUT * HUB_MLP_HID + HUB_MLP_OUT)
+
+/* out[r][2] = MLP(feats[r][8]) for r < n_rows.  params, feats, out: device
+ * pointers on `device`.  Asynchronous on stream. */
+hub_status hub_mlp_forward(int32_t device, const float *params, int32_t n_rows, const float *feats,
+                           float *out, void *stream);
+
+/* Device workspace bytes hub_mlp_train_step needs for n_rows rows. */
+int64_t hub_mlp_workspace_bytes(int32_t n_rows);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step
+ * count t >= 1, learning rate lr) on the mean squared error
+ *     L = (1/n_rows) sum_r sum_o (out[r][o] - targets[r][o])^2.
+ * params, adam_m, adam_v (HUB_MLP_NPARAM floats each, updated in place),
+ * feats [n_rows][8], targets [n_rows][2], loss (1 float: L before the
+ * update) and workspace (hub_mlp_workspace_bytes) are device pointers.
+ * Gradient partial sums are reduced in a fixed order (deterministic).
+ * Asynchronous on stream. */
+hub_status hub_mlp_train_step(int32_t device, float *params, float *adam_m, float *adam_v, int32_t t,
+                              float lr, int32_t n_rows, const float *feats, const float *targets,
+                              float *loss, void *workspace, void *stream);
+
+/* Training rows from a finished run of one vector (host arrays): for each
+ * step n in [0, n_steps), feats[n] as above with history end
+ * h = n - 1 - (n mod chunk) (the planning point of n's chunk when chunks
+ * start at multiples of `chunk`), and targets[n] = (log2 m_n, 0).  log is
+ * that vector's hub_step_info of the run (n_steps entries, stride 1). */
+hub_status hub_controller_features(const hub_pulse *pulse, double t_start, double dt, int32_t n_steps,
+                                   double norm_inf, const hub_krylov_opts *opts, const hub_step_info *log,
+                                   int32_t chunk, float *feats, float *targets);
+
+/* Copy HUB_MLP_NPARAM host floats into the handle's controller. */
+hub_status hub_controller_load(hub_basis basis, const float *params, int32_t n_params);
+
+/* Enable (on = 1, after a load) or disable the controlled schedule of
+ * hub_propagate; chunk in [1, 256] steps, margin in [0, 16] iterations. */
+hub_status hub_controller_enable(hub_basis basis, int32_t on, int32_t chunk, int32_t margin);
+
+typedef struct {
+  int64_t steps;          /* steps finished under the controlled schedule     */
+  int64_t chunks;         /* chunks planned (one MLP launch, one sync each)   */
+  int64_t fallbacks;      /* steps re-run with the adaptive schedule          */
+  int64_t lanczos_launches; /* H*v launches enqueued by controlled chunks     */
+  int64_t iterations;     /* Krylov iterations those steps needed (sum of m over steps and vectors) */
+} hub_controller_stats;
+
+/* Counters since the last read (then reset). */
+hub_status hub_controller_read_stats(hub_basis basis, hub_controller_stats *out);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing of the matrix-free apply (for roofline reporting).  While
  * enabled, the library brackets with HIP events on the launch stream every
  * hub_apply_H launch and every Lanczos H*v launch of a propagation except the

@@ -37,7 +37,13 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_basis_classes", "hub_basis_hops",
            "hub_apply_H", "hub_observables", "hub_krylov_expm_step", "hub_propagate",
            "hub_ground_state", "hub_pulse_A", "hub_last_error", "hub_profile_enable",
-           "hub_profile_read", "hub_apply_cop", "hub_dot", "hub_greens_diag")
+           "hub_profile_read", "hub_apply_cop", "hub_dot", "hub_greens_diag",
+           "hub_mlp_forward", "hub_mlp_workspace_bytes", "hub_mlp_train_step", "hub_controller_features",
+           "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats")
+
+# Controller MLP sizes (HUB_MLP_* in hub.h).
+MLP_IN, MLP_HID, MLP_OUT = 8, 64, 2
+MLP_NPARAM = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
 
 
 class HubError(RuntimeError):
@@ -71,6 +77,11 @@ class hub_step_info(ctypes.Structure):
 class hub_greens_member(ctypes.Structure):
     _fields_ = [("site", ctypes.c_int32), ("spin", ctypes.c_int32), ("dagger", ctypes.c_int32),
                 ("start_step", ctypes.c_int32)]
+
+
+class hub_controller_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("chunks", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
+                ("lanczos_launches", ctypes.c_int64), ("iterations", ctypes.c_int64)]
 
 
 class hub_obs(ctypes.Structure):
@@ -112,6 +123,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_dot": ([vp, i32, i32, vp, vp, P(dbl), vp], i32),
         "hub_greens_diag": ([vp, i32, P(vp), P(hub_pulse), dbl, dbl, i32, P(hub_krylov_opts), i32, i32,
                              P(hub_greens_member), vp, P(dbl), vp], i32),
+        "hub_mlp_forward": ([i32, vp, i32, vp, vp, vp], i32),
+        "hub_mlp_workspace_bytes": ([i32], i64),
+        "hub_mlp_train_step": ([i32, vp, vp, vp, i32, ctypes.c_float, i32, vp, vp, vp, vp, vp], i32),
+        "hub_controller_features": ([P(hub_pulse), dbl, dbl, i32, dbl, P(hub_krylov_opts), P(hub_step_info), i32,
+                                     P(ctypes.c_float), P(ctypes.c_float)], i32),
+        "hub_controller_load": ([vp, P(ctypes.c_float), i32], i32),
+        "hub_controller_enable": ([vp, i32, i32, i32], i32),
+        "hub_controller_read_stats": ([vp, P(hub_controller_stats)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -356,6 +375,65 @@ def hub_greens_diag(h, targets, pulse, t_start: float, dt: float, n_rel: int, op
                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream)))
     o = out.reshape(nm, n_rel + 1, 2)
     return o[..., 0] + 1j * o[..., 1]
+
+
+def _device_of(t) -> int:
+    return t.device.index if t.device.index is not None else 0
+
+
+def hub_mlp_forward(params, feats, out, stream=None) -> None:
+    """out[r, :2] = MLP(feats[r, :8]); float32 device tensors."""
+    _check(load_library().hub_mlp_forward(_device_of(params), _dptr(params), int(feats.shape[0]), _dptr(feats),
+                                          _dptr(out), _stream_ptr(stream)))
+
+
+def hub_mlp_workspace_bytes(n_rows: int) -> int:
+    return int(load_library().hub_mlp_workspace_bytes(int(n_rows)))
+
+
+def hub_mlp_train_step(params, adam_m, adam_v, t: int, lr: float, feats, targets, loss, workspace,
+                       stream=None) -> None:
+    """One Adam step on the mean squared error (all float32 device tensors)."""
+    _check(load_library().hub_mlp_train_step(_device_of(params), _dptr(params), _dptr(adam_m), _dptr(adam_v),
+                                             int(t), float(lr), int(feats.shape[0]), _dptr(feats), _dptr(targets),
+                                             _dptr(loss), _dptr(workspace), _stream_ptr(stream)))
+
+
+def hub_controller_features(pulse, t_start: float, dt: float, norm_inf: float, opts, log_rows, chunk: int):
+    """Training rows (feats [n, 8], targets [n, 2]) from one vector's step log.
+
+    log_rows: array [n_steps, 6] as returned in hub_propagate's log for one
+    vector (m_used, substeps, converged, breakdown, err_est, beta_last)."""
+    lr = np.asarray(log_rows)
+    n = lr.shape[0]
+    info = (hub_step_info * max(1, n))()
+    for k in range(n):
+        info[k] = hub_step_info(int(lr[k, 0]), int(lr[k, 1]), int(lr[k, 2]), int(lr[k, 3]), float(lr[k, 4]),
+                                float(lr[k, 5]))
+    feats = np.zeros((max(1, n), MLP_IN), dtype=np.float32)
+    targ = np.zeros((max(1, n), MLP_OUT), dtype=np.float32)
+    p = make_pulse(pulse)
+    Pf = ctypes.POINTER(ctypes.c_float)
+    _check(load_library().hub_controller_features(ctypes.byref(p), float(t_start), float(dt), n, float(norm_inf),
+                                                  ctypes.byref(opts), info, int(chunk), feats.ctypes.data_as(Pf),
+                                                  targ.ctypes.data_as(Pf)))
+    return feats[:n], targ[:n]
+
+
+def hub_controller_load(h, params) -> None:
+    arr = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+    _check(load_library().hub_controller_load(ctypes.c_void_p(h), arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                              int(arr.size)))
+
+
+def hub_controller_enable(h, on: bool, chunk: int = 16, margin: int = 1) -> None:
+    _check(load_library().hub_controller_enable(ctypes.c_void_p(h), 1 if on else 0, int(chunk), int(margin)))
+
+
+def hub_controller_read_stats(h) -> dict:
+    s = hub_controller_stats()
+    _check(load_library().hub_controller_read_stats(ctypes.c_void_p(h), ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in hub_controller_stats._fields_}
 
 
 class Basis:

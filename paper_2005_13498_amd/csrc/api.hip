@@ -19,6 +19,7 @@
 #include "basis.h"
 #include "host_eig.h"
 #include "kernels.h"
+#include "mlp.h"
 
 using hub::CombineLog;
 using hub::DevBasis;
@@ -48,6 +49,8 @@ hub_status fail(hub_status s, const std::string& msg) {
 
 size_t elem_bytes(hub_prec p) { return p == HUB_C128 ? 16 : 8; }
 
+constexpr int kCtrlMaxChunk = 256;
+
 }  // namespace
 
 struct hub_basis_s {
@@ -70,6 +73,15 @@ struct hub_basis_s {
   size_t partials_e_bytes = 0;
   double* scal = nullptr;         // device scalars [kMMax*2 + 16]
   int rows_c128 = 1, rows_c64 = 1;
+  // learned Krylov controller
+  bool ctrl_on = false, ctrl_loaded = false;
+  int ctrl_chunk = 16, ctrl_margin = 1;
+  float* ctrl_params = nullptr;  // device [HUB_MLP_NPARAM]
+  float* ctrl_feat = nullptr;    // device [kCtrlMaxChunk * kMaxNV][HUB_MLP_IN]
+  float* ctrl_out = nullptr;     // device [kCtrlMaxChunk * kMaxNV][HUB_MLP_OUT]
+  float* ctrl_hfeat = nullptr;   // pinned host copies of the two
+  float* ctrl_hout = nullptr;
+  hub_controller_stats cstats{};
   // profiling of the apply kernel
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
@@ -155,6 +167,38 @@ double pulse_value(const hub_pulse& p, double t) {
   return p.A0 * (std::cos(p.omega * s) - p.b) * env;
 }
 
+// dA/dt of pulse_value.
+double pulse_deriv(const hub_pulse& p, double t) {
+  const double s = t - p.t0;
+  const double is2 = 1.0 / (p.sigma * p.sigma);
+  const double env = std::exp(-0.5 * s * s * is2);
+  if (p.kind == 0) return p.A0 * env * (p.omega * std::cos(p.omega * s) - s * is2 * std::sin(p.omega * s));
+  return p.A0 * env * (-p.omega * std::sin(p.omega * s) - s * is2 * (std::cos(p.omega * s) - p.b));
+}
+
+// Controller features of one (step, vector) row: pulse at the step's
+// midpoint, tau |H|_inf, the a-posteriori estimates of the last four finished
+// steps (newest first, NaN where there is none) and the last finished step's
+// Krylov dimension (-1 if none).
+void ctrl_features(double A, double dA, double tau_norm, const double* eps_hist, int m_last, double tol, int m_hint,
+                   float* x) {
+  x[0] = static_cast<float>(A);
+  x[1] = static_cast<float>(dA / 10.0);
+  x[2] = static_cast<float>(tau_norm);
+  for (int k = 0; k < 4; ++k) {
+    const double e = eps_hist[k];
+    const double l = std::isnan(e) ? std::log10(tol) : std::log10(std::max(e, 1e-40));
+    x[3 + k] = static_cast<float>(l / 10.0);
+  }
+  const int m = m_last >= 0 ? m_last : (m_hint > 0 ? m_hint : 8);
+  x[7] = static_cast<float>(m / 10.0);
+}
+
+// Pulse values the controller needs, per (step, vector) of a group.
+struct CtrlInputs {
+  std::vector<double> A_mid, dA_mid;  // [n * nv + v]
+};
+
 hub_status check_pulse(const hub_pulse& p) {
   if (p.kind != 0 && p.kind != 1) return fail(HUB_E_INVALID, "pulse kind must be 0 or 1");
   if (!(p.sigma > 0.0) || !std::isfinite(p.A0) || !std::isfinite(p.omega) || !std::isfinite(p.t0) ||
@@ -233,9 +277,9 @@ struct StepReport {
 // the ABI layout at `user` (vector k at user + k*dim).  coef_mid[n][v][2*nc].
 hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps,
                      const std::vector<double>& coef_mid, double dt, const hub_krylov_opts& o,
-                     bool want_obs, const std::vector<double>* coef_final, std::vector<double>* obs_out,
+                     bool want_obs, const std::vector<double>* coef_obs, std::vector<double>* obs_out,
                      std::vector<StepReport>* reports, hipStream_t stream, bool* not_converged,
-                     int* steps_done) {
+                     int* steps_done, const CtrlInputs* ctrl) {
   const size_t es = elem_bytes(prec);
   const int64_t dim = h->D.dim;
   const size_t vbytes = static_cast<size_t>(dim) * nv * es;
@@ -296,41 +340,51 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   L.stream = stream;
   const int agrid = hub::apply_grid(h->D, pi, nv);
 
-  // The decision for Krylov dimension m is taken by the first workgroup of
-  // the m-th apply; iterations are enqueued speculatively up to the previous
-  // step's m (a step that needs more waits for one host round trip per extra
-  // iteration; kernels past the decision exit at once).
+  const int S = o.substeps;
+  CombineLog* dlog_c = static_cast<CombineLog*>(dlog);
+  // one Lanczos iteration j of substep `sub` of step n (apply, then update)
+  auto enqueue_iter = [&](int n, int sub, int jj) -> hub_status {
+    hub::ApplyLaunch A = L;
+    A.mode = hub::kLanczos;
+    A.obs = want_obs && sub == 0 && jj == 0;
+    A.coef_obs = A.obs ? coef_obs->data() + static_cast<size_t>(n) * nv * 2 * nc : nullptr;
+    A.x = ptrs[jj];
+    A.y = jj < o.m_max ? ptrs[jj + 1] : nullptr;
+    A.xprev = jj > 0 ? ptrs[jj - 1] : nullptr;
+    A.coef = coef_mid.data() + static_cast<size_t>(n) * nv * 2 * nc;
+    A.j = jj;
+    hub_status r = launch_apply_timed(h, A);
+    if (r != HUB_OK) return r;
+    if (jj < o.m_max)
+      HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
+                                 hub::apply_nq(hub::kLanczos, A.obs, nc), h->partials_e, stream));
+    return HUB_OK;
+  };
+  auto finish_sub = [&](int n, int sub) -> hub_status {
+    HUB_HIP(hub::launch_combine(pi, nv, dim, h->slot_ptrs, h->st, h->ctl, h->partials_e, stream));
+    HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, dlog_c + (static_cast<size_t>(n) * S + sub) * nv,
+                                 (want_obs && sub == 0) ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr,
+                                 kObsQ, stream));
+    return HUB_OK;
+  };
+
+  // Adaptive schedule.  The decision for Krylov dimension m is taken by the
+  // first workgroup of the m-th apply; iterations are enqueued speculatively
+  // up to the previous step's m (a step that needs more waits for one host
+  // round trip per extra iteration; kernels past the decision exit at once).
   int m_pred = o.m_hint > 0 ? std::min(o.m_hint, o.m_max) : std::min(8, o.m_max);
-  bool first = true;
+  bool first = true;  // the next step_begin computes |v| itself
   *not_converged = false;
   *steps_done = 0;
-  for (int n = 0; n < n_steps; ++n) {
-    const double* cf = coef_mid.data() + static_cast<size_t>(n) * nv * 2 * nc;
+  auto adaptive_step = [&](int n, int sub0, bool* maxed) -> hub_status {
     int m_step_max = 0;
-    bool maxed = false;
-    for (int sub = 0; sub < o.substeps; ++sub) {
+    *maxed = false;
+    for (int sub = sub0; sub < S; ++sub) {
       HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, first, h->partials_e, stream));
       first = false;
-      const bool obs_here = want_obs && sub == 0;
-      auto enqueue_iter = [&](int jj) -> hub_status {
-        hub::ApplyLaunch A = L;
-        A.mode = hub::kLanczos;
-        A.obs = obs_here && jj == 0;
-        A.x = ptrs[jj];
-        A.y = jj < o.m_max ? ptrs[jj + 1] : nullptr;
-        A.xprev = jj > 0 ? ptrs[jj - 1] : nullptr;
-        A.coef = cf;
-        A.j = jj;
-        hub_status r = launch_apply_timed(h, A);
-        if (r != HUB_OK) return r;
-        if (jj < o.m_max)
-          HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
-                                     hub::apply_nq(hub::kLanczos, A.obs, nc), h->partials_e, stream));
-        return HUB_OK;
-      };
       int j = 0;
       for (; j <= m_pred && j <= o.m_max; ++j) {
-        hub_status r = enqueue_iter(j);
+        hub_status r = enqueue_iter(n, sub, j);
         if (r != HUB_OK) return r;
       }
       while (true) {
@@ -338,35 +392,197 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         HUB_HIP(hipStreamSynchronize(stream));
         if (h->h_ctl->all_done) break;
         if (j > o.m_max) return fail(HUB_E_DEVICE, "Krylov loop ended without a decision");
-        hub_status r = enqueue_iter(j);
+        hub_status r = enqueue_iter(n, sub, j);
         if (r != HUB_OK) return r;
         ++j;
       }
       m_step_max = std::max(m_step_max, static_cast<int>(h->h_ctl->iter));
-      maxed = h->h_ctl->any_maxed != 0;
-      HUB_HIP(hub::launch_combine(pi, nv, dim, h->slot_ptrs, h->st, h->partials_e, stream));
-      CombineLog* lg = static_cast<CombineLog*>(dlog) + (static_cast<size_t>(n) * o.substeps + sub) * nv;
-      HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, lg,
-                                   obs_here ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr, kObsQ,
-                                   stream));
-      if (maxed) break;
+      *maxed = h->h_ctl->any_maxed != 0;
+      hub_status r = finish_sub(n, sub);
+      if (r != HUB_OK) return r;
+      if (*maxed) break;
     }
     // next step's speculative depth: the deepest this step needed
     m_pred = std::max(1, std::min(o.m_max, m_step_max));
-    *steps_done = n + 1;
-    if (maxed) {  // stop at the first step where a vector hit m_max
-      *not_converged = true;
-      break;
+    return HUB_OK;
+  };
+
+  const bool controlled = h->ctrl_on && ctrl != nullptr && n_steps > 0;
+  if (!controlled) {
+    for (int n = 0; n < n_steps; ++n) {
+      bool maxed = false;
+      hub_status r = adaptive_step(n, 0, &maxed);
+      if (r != HUB_OK) return r;
+      *steps_done = n + 1;
+      if (maxed) {  // stop at the first step where a vector hit m_max
+        *not_converged = true;
+        break;
+      }
+    }
+  } else {
+    // Controlled schedule: plan `chunk` steps with one MLP launch, enqueue
+    // them without host synchronisation, then check on the device counters
+    // how many finished; an undecided step is re-run adaptively.
+    std::vector<CombineLog> hlog(static_cast<size_t>(n_steps) * S * nv);
+    std::vector<int> L_of(h->ctrl_chunk);
+    auto step_hist = [&](int n, int v, double* eps, int* m) {  // step n's log of vector v
+      double e = 0.0;
+      int mm = 0;
+      for (int sub = 0; sub < S; ++sub) {
+        const CombineLog& c = hlog[(static_cast<size_t>(n) * S + sub) * nv + v];
+        e = std::max(e, c.eps);
+        mm = std::max(mm, static_cast<int>(c.m));
+      }
+      *eps = e;
+      *m = mm;
+    };
+    auto fetch_logs = [&](int n_from, int n_to) -> hub_status {  // enqueue only
+      if (n_to <= n_from) return HUB_OK;
+      const size_t off = static_cast<size_t>(n_from) * S * nv;
+      const size_t cnt = static_cast<size_t>(n_to - n_from) * S * nv;
+      HUB_HIP(hipMemcpyAsync(hlog.data() + off, dlog_c + off, cnt * sizeof(CombineLog), hipMemcpyDeviceToHost,
+                             stream));
+      return HUB_OK;
+    };
+    int n = 0;
+    while (n < n_steps) {
+      const int K = std::min(h->ctrl_chunk, n_steps - n);
+      // plan: features of every (step, vector) row, history up to step n-1
+      float* hf = h->ctrl_hfeat;
+      for (int k = 0; k < K; ++k)
+        for (int v = 0; v < nv; ++v) {
+          double eh[4];
+          for (int q = 0; q < 4; ++q) {
+            const int hs = n - 1 - q;
+            int mm = 0;
+            if (hs >= 0) step_hist(hs, v, &eh[q], &mm);
+            else eh[q] = NAN;
+          }
+          double e0 = 0.0;
+          int m_last = -1;
+          if (n >= 1) step_hist(n - 1, v, &e0, &m_last);
+          const size_t r = static_cast<size_t>(n + k) * nv + v;
+          ctrl_features((*ctrl).A_mid[r], (*ctrl).dA_mid[r], tau * h->B.norm_inf, eh, m_last, o.tol, o.m_hint,
+                        hf + (static_cast<size_t>(k) * nv + v) * HUB_MLP_IN);
+        }
+      const int rows = K * nv;
+      HUB_HIP(hipMemcpyAsync(h->ctrl_feat, hf, static_cast<size_t>(rows) * HUB_MLP_IN * sizeof(float),
+                             hipMemcpyHostToDevice, stream));
+      HUB_HIP(hub::launch_mlp_forward(h->ctrl_params, rows, h->ctrl_feat, h->ctrl_out, stream));
+      HUB_HIP(hipMemcpyAsync(h->ctrl_hout, h->ctrl_out, static_cast<size_t>(rows) * HUB_MLP_OUT * sizeof(float),
+                             hipMemcpyDeviceToHost, stream));
+      StepCtl c0 = *h->h_ctl;
+      c0.abort = 0;
+      c0.steps_done = 0;
+      c0.all_done = 0;
+      c0.any_maxed = 0;
+      c0.iter = 0;
+      *h->h_ctl = c0;
+      HUB_HIP(hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
+      HUB_HIP(hipStreamSynchronize(stream));
+      for (int k = 0; k < K; ++k) {
+        double lg = 0.0;
+        for (int v = 0; v < nv; ++v) {
+          const double ov = h->ctrl_hout[(static_cast<size_t>(k) * nv + v) * HUB_MLP_OUT];
+          lg = std::max(lg, std::isfinite(ov) ? ov : 64.0);
+        }
+        const double mpred = std::ceil(std::exp2(std::min(lg, 10.0)) - 1e-6);
+        L_of[k] = std::min(o.m_max, static_cast<int>(mpred) + h->ctrl_margin) + 1;  // launches j = 0..L-1
+      }
+      // enqueue the chunk
+      for (int k = 0; k < K; ++k)
+        for (int sub = 0; sub < S; ++sub) {
+          HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, first, h->partials_e, stream));
+          first = false;
+          for (int j = 0; j < L_of[k] && j <= o.m_max; ++j) {
+            hub_status r = enqueue_iter(n + k, sub, j);
+            if (r != HUB_OK) return r;
+          }
+          hub_status r = finish_sub(n + k, sub);
+          if (r != HUB_OK) return r;
+          h->cstats.lanczos_launches += std::min(L_of[k], o.m_max + 1);
+        }
+      HUB_HIP(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
+      { hub_status r = fetch_logs(n, n + K); if (r != HUB_OK) return r; }
+      HUB_HIP(hipStreamSynchronize(stream));
+      h->cstats.chunks += 1;
+      const int done_sub = h->h_ctl->steps_done;
+      const int complete = std::min(K, done_sub / S);
+      bool maxed = false;
+      for (int k = 0; k < complete && !maxed; ++k)
+        for (int v = 0; v < nv; ++v) {
+          double e;
+          int mm;
+          step_hist(n + k, v, &e, &mm);
+          for (int sub = 0; sub < S; ++sub)
+            maxed |= hlog[(static_cast<size_t>(n + k) * S + sub) * nv + v].status == 3;
+          h->cstats.iterations += mm;
+        }
+      h->cstats.steps += complete;
+      *steps_done = n + complete;
+      if (maxed) {  // a vector hit m_max: the device stopped after that step
+        int k = 0;
+        for (; k < complete; ++k) {
+          bool mk = false;
+          for (int sub = 0; sub < S; ++sub)
+            for (int v = 0; v < nv; ++v) mk |= hlog[(static_cast<size_t>(n + k) * S + sub) * nv + v].status == 3;
+          if (mk) break;
+        }
+        *steps_done = n + k + 1;
+        *not_converged = true;
+        break;
+      }
+      if (h->h_ctl->abort == 0) {
+        n += K;
+        continue;
+      }
+      // fallback: the first unfinished step, from its first unfinished substep
+      const int nb = n + complete;
+      StepCtl c1 = *h->h_ctl;
+      c1.abort = 0;
+      c1.all_done = 0;
+      c1.any_maxed = 0;
+      c1.iter = 0;
+      c1.steps_done = 0;
+      *h->h_ctl = c1;
+      HUB_HIP(hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
+      first = true;  // the abandoned step overwrote the |v|^2 partials
+      int mp = 0;
+      for (int v = 0; v < nv; ++v) {
+        double e;
+        int mm;
+        if (nb >= 1) step_hist(nb - 1, v, &e, &mm);
+        else mm = 0;
+        mp = std::max(mp, mm);
+      }
+      if (mp > 0) m_pred = std::min(o.m_max, mp);
+      bool mx = false;
+      hub_status r = adaptive_step(nb, done_sub % S, &mx);
+      if (r != HUB_OK) return r;
+      r = fetch_logs(nb, nb + 1);
+      if (r != HUB_OK) return r;
+      HUB_HIP(hipStreamSynchronize(stream));
+      h->cstats.fallbacks += 1;
+      *steps_done = nb + 1;
+      if (mx) {
+        *not_converged = true;
+        break;
+      }
+      n = nb + 1;
     }
   }
   // observables at the final sample time
   if (want_obs && *steps_done == n_steps) {
+    StepCtl c2 = StepCtl{};  // clear a stop flag left by the last step
+    *h->h_ctl = c2;
+    HUB_HIP(hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
     hub::ApplyLaunch A = L;
     A.mode = hub::kObsOnly;
     A.obs = true;
     A.x = slot0;
     A.y = nullptr;
-    A.coef = coef_final->data();
+    A.coef = coef_obs->data() + static_cast<size_t>(n_steps) * nv * 2 * nc;
+    A.coef_obs = A.coef;
     A.j = 0;
     HUB_HIP(hub::launch_apply(A));
     HUB_HIP(hub::launch_finalize_obs(nv, h->partials, agrid, hub::apply_nq(hub::kObsOnly, true, nc), h->st, stream));
@@ -405,11 +621,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   return HUB_OK;
 }
 
-void fill_obs(const hub::Basis& B, const double* o /* kObsQ */, const double* coef /* 2*nc */, double t,
-              hub_obs* out) {
-  const int nc = static_cast<int>(B.classes.size());
-  double e = o[0];
-  for (int c = 0; c < nc; ++c) e += coef[2 * c] * o[3 + 2 * c] - coef[2 * c + 1] * o[3 + 2 * c + 1];
+// o = [<D>, docc, |x|^2, Re <x|K(t)|x>] of one vector at sample time t.
+void fill_obs(const hub::Basis& B, const double* o /* kObsQ */, double t, hub_obs* out) {
+  const double e = o[0] + o[3];
   out->t = t;
   out->norm = std::sqrt(std::max(0.0, o[2]));
   out->energy_per_site = e / B.lat.n_sites;
@@ -533,6 +747,11 @@ void hub_basis_destroy(hub_basis h) {
   if (h->scal) (void)hipFree(h->scal);
   if (h->partials) (void)hipFree(h->partials);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  if (h->ctrl_params) (void)hipFree(h->ctrl_params);
+  if (h->ctrl_feat) (void)hipFree(h->ctrl_feat);
+  if (h->ctrl_out) (void)hipFree(h->ctrl_out);
+  if (h->ctrl_hfeat) (void)hipHostFree(h->ctrl_hfeat);
+  if (h->ctrl_hout) (void)hipHostFree(h->ctrl_hout);
   for (auto& e : h->ev_used) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -669,6 +888,7 @@ hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t 
     L.obs = true;
     L.x = static_cast<const char*>(v) + static_cast<size_t>(k) * dim * es;
     L.coef = cf.data();
+    L.coef_obs = cf.data();
     L.st = h->st;
     L.ctl = h->ctl;
     L.partials = h->partials;
@@ -680,7 +900,7 @@ hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t 
     HUB_HIP(hipMemcpyAsync(o, reinterpret_cast<char*>(h->st) + offsetof(VecState, obs), sizeof(o),
                            hipMemcpyDeviceToHost, st));
     HUB_HIP(hipStreamSynchronize(st));
-    fill_obs(h->B, o, cf.data(), 0.0, &out[k]);
+    fill_obs(h->B, o, 0.0, &out[k]);
     out[k].t = 0.0;
     if (site_docc) {
       HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, h->scal, h->partials_e, st));
@@ -696,7 +916,8 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
                           const std::vector<std::vector<double>>& A_mid /* [nvec][n_steps] */,
                           const std::vector<std::vector<double>>* A_sample /* [nvec][n_steps+1] */,
                           double t_start, double dt, const hub_krylov_opts& o, hub_obs* obs,
-                          hub_step_info* log, void* stream) {
+                          hub_step_info* log, void* stream,
+                          const std::vector<std::vector<double>>* dA_mid = nullptr /* [nvec][n_steps] */) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int pi = prec == HUB_C128 ? 0 : 1;
   const size_t es = elem_bytes(prec);
@@ -711,17 +932,31 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
       for (int v = 0; v < nv; ++v)
         coef_for(h->B, A_mid[k0 + v][n], cm.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
     const bool want_obs = obs != nullptr && A_sample != nullptr;
-    std::vector<double> cfin(static_cast<size_t>(2) * kMaxNV * kMaxClasses, 0.0);
-    if (want_obs)
-      for (int v = 0; v < nv; ++v)
-        coef_for(h->B, (*A_sample)[k0 + v][n_steps], cfin.data() + static_cast<size_t>(2) * v * nc);
+    // hop coefficients at the sample times t_start + n dt, n = 0..n_steps
+    std::vector<double> co;
+    if (want_obs) {
+      co.assign(static_cast<size_t>(n_steps + 1) * nv * 2 * nc, 0.0);
+      for (int n = 0; n <= n_steps; ++n)
+        for (int v = 0; v < nv; ++v)
+          coef_for(h->B, (*A_sample)[k0 + v][n], co.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
+    }
     std::vector<double> obs_raw;
     std::vector<StepReport> reps;
     bool ncv = false;
     int done = 0;
     char* user = static_cast<char*>(v_inout) + static_cast<size_t>(k0) * dim * es;
-    hub_status s = run_group(h, prec, nv, user, n_steps, cm, dt, o, want_obs, &cfin, &obs_raw, &reps, st, &ncv,
-                             &done);
+    CtrlInputs ci;
+    if (dA_mid) {
+      ci.A_mid.resize(static_cast<size_t>(n_steps) * nv);
+      ci.dA_mid.resize(static_cast<size_t>(n_steps) * nv);
+      for (int n = 0; n < n_steps; ++n)
+        for (int v = 0; v < nv; ++v) {
+          ci.A_mid[static_cast<size_t>(n) * nv + v] = A_mid[k0 + v][n];
+          ci.dA_mid[static_cast<size_t>(n) * nv + v] = (*dA_mid)[k0 + v][n];
+        }
+    }
+    hub_status s = run_group(h, prec, nv, user, n_steps, cm, dt, o, want_obs, &co, &obs_raw, &reps, st, &ncv,
+                             &done, dA_mid ? &ci : nullptr);
     if (s != HUB_OK) return s;
     if (log)
       for (int n = 0; n < done; ++n)
@@ -743,9 +978,7 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
             O = hub_obs{t_start + n * dt, NAN, NAN, NAN};
             continue;
           }
-          double cs[2 * kMaxClasses];
-          coef_for(h->B, (*A_sample)[k0 + v][n], cs);
-          fill_obs(h->B, obs_raw.data() + (static_cast<size_t>(n) * nv + v) * kObsQ, cs, t_start + n * dt, &O);
+          fill_obs(h->B, obs_raw.data() + (static_cast<size_t>(n) * nv + v) * kObsQ, t_start + n * dt, &O);
         }
     }
     any_nc |= ncv;
@@ -783,11 +1016,13 @@ hub_status hub_propagate(hub_basis h, const hub_pulse* pulses, double t_start, d
   for (int k = 0; k < nvec; ++k)
     if ((s = check_pulse(pulses[k])) != HUB_OK) return s;
   std::vector<std::vector<double>> am(nvec, std::vector<double>(n_steps)), as(nvec, std::vector<double>(n_steps + 1));
+  std::vector<std::vector<double>> dam(nvec, std::vector<double>(n_steps));
   for (int k = 0; k < nvec; ++k) {
     for (int n = 0; n < n_steps; ++n) am[k][n] = pulse_value(pulses[k], t_start + n * dt + 0.5 * dt);
+    for (int n = 0; n < n_steps; ++n) dam[k][n] = pulse_deriv(pulses[k], t_start + n * dt + 0.5 * dt);
     for (int n = 0; n <= n_steps; ++n) as[k][n] = pulse_value(pulses[k], t_start + n * dt);
   }
-  return run_all(h, prec, nvec, v_inout, n_steps, am, &as, t_start, dt, *opts, obs, log, stream);
+  return run_all(h, prec, nvec, v_inout, n_steps, am, &as, t_start, dt, *opts, obs, log, stream, &dam);
 }
 
 // ---------------------------------------------------------------------------
@@ -1240,6 +1475,98 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
   HUB_HIP(hipStreamSynchronize(st));
   if (gap) *gap = g;
   if (g < 1e-8 * h->B.norm_inf) return fail(HUB_E_DEGENERATE, "ground state is degenerate within 1e-8 |H|");
+  return HUB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned Krylov controller: MLP kernels and the controlled schedule.
+hub_status hub_mlp_forward(int32_t device, const float* params, int32_t n_rows, const float* feats, float* out,
+                           void* stream) {
+  if (!params || !feats || !out) return fail(HUB_E_INVALID, "null argument");
+  if (n_rows < 0) return fail(HUB_E_INVALID, "n_rows must be >= 0");
+  HUB_HIP(hipSetDevice(device));
+  HUB_HIP(hub::launch_mlp_forward(params, n_rows, feats, out, static_cast<hipStream_t>(stream)));
+  return HUB_OK;
+}
+
+int64_t hub_mlp_workspace_bytes(int32_t n_rows) { return n_rows < 1 ? 0 : hub::mlp_workspace_bytes(n_rows); }
+
+hub_status hub_mlp_train_step(int32_t device, float* params, float* adam_m, float* adam_v, int32_t t, float lr,
+                              int32_t n_rows, const float* feats, const float* targets, float* loss, void* workspace,
+                              void* stream) {
+  if (!params || !adam_m || !adam_v || !feats || !targets || !loss || !workspace)
+    return fail(HUB_E_INVALID, "null argument");
+  if (n_rows < 1) return fail(HUB_E_INVALID, "n_rows must be >= 1");
+  if (t < 1) return fail(HUB_E_INVALID, "Adam step count t must be >= 1");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(HUB_E_INVALID, "lr must be finite and > 0");
+  HUB_HIP(hipSetDevice(device));
+  HUB_HIP(hub::launch_mlp_train_step(params, adam_m, adam_v, t, lr, n_rows, feats, targets, loss, workspace,
+                                     static_cast<hipStream_t>(stream)));
+  return HUB_OK;
+}
+
+hub_status hub_controller_features(const hub_pulse* pulse, double t_start, double dt, int32_t n_steps,
+                                   double norm_inf, const hub_krylov_opts* opts, const hub_step_info* log,
+                                   int32_t chunk, float* feats, float* targets) {
+  if (!pulse || !opts || !log || !feats || !targets) return fail(HUB_E_INVALID, "null argument");
+  if (n_steps < 0 || chunk < 1) return fail(HUB_E_INVALID, "n_steps must be >= 0 and chunk >= 1");
+  hub_status s = check_pulse(*pulse);
+  if (s != HUB_OK) return s;
+  if ((s = check_opts(*opts)) != HUB_OK) return s;
+  if (!std::isfinite(dt) || !std::isfinite(t_start) || !std::isfinite(norm_inf))
+    return fail(HUB_E_INVALID, "non-finite argument");
+  const double tau = dt / opts->substeps;
+  for (int n = 0; n < n_steps; ++n) {
+    const int hs = n - 1 - (n % chunk);
+    double eh[4];
+    for (int q = 0; q < 4; ++q) eh[q] = (hs - q >= 0) ? log[hs - q].err_est : NAN;
+    const int m_last = hs >= 0 ? log[hs].m_used : -1;
+    const double tm = t_start + n * dt + 0.5 * dt;
+    ctrl_features(pulse_value(*pulse, tm), pulse_deriv(*pulse, tm), tau * norm_inf, eh, m_last, opts->tol,
+                  opts->m_hint, feats + static_cast<size_t>(n) * HUB_MLP_IN);
+    targets[static_cast<size_t>(n) * HUB_MLP_OUT] = static_cast<float>(std::log2(std::max(1, log[n].m_used)));
+    targets[static_cast<size_t>(n) * HUB_MLP_OUT + 1] = 0.0f;
+  }
+  return HUB_OK;
+}
+
+hub_status hub_controller_load(hub_basis h, const float* params, int32_t n_params) {
+  if (!h || !params) return fail(HUB_E_INVALID, "null argument");
+  if (n_params != HUB_MLP_NPARAM) return fail(HUB_E_INVALID, "n_params must be HUB_MLP_NPARAM");
+  if (h->device < 0) return fail(HUB_E_DEVICE, "host-only handle (created with device -1)");
+  for (int k = 0; k < n_params; ++k)
+    if (!std::isfinite(params[k])) return fail(HUB_E_INVALID, "non-finite controller parameter");
+  HUB_HIP(hipSetDevice(h->device));
+  const size_t rows = static_cast<size_t>(kCtrlMaxChunk) * kMaxNV;
+  if (!h->ctrl_params) {
+    HUB_HIP(hipMalloc(reinterpret_cast<void**>(&h->ctrl_params), HUB_MLP_NPARAM * sizeof(float)));
+    HUB_HIP(hipMalloc(reinterpret_cast<void**>(&h->ctrl_feat), rows * HUB_MLP_IN * sizeof(float)));
+    HUB_HIP(hipMalloc(reinterpret_cast<void**>(&h->ctrl_out), rows * HUB_MLP_OUT * sizeof(float)));
+    HUB_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->ctrl_hfeat), rows * HUB_MLP_IN * sizeof(float)));
+    HUB_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->ctrl_hout), rows * HUB_MLP_OUT * sizeof(float)));
+  }
+  HUB_HIP(hipMemcpy(h->ctrl_params, params, HUB_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  h->ctrl_loaded = true;
+  return HUB_OK;
+}
+
+hub_status hub_controller_enable(hub_basis h, int32_t on, int32_t chunk, int32_t margin) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (on && !h->ctrl_loaded) return fail(HUB_E_INVALID, "no controller parameters loaded");
+  if (on && (chunk < 1 || chunk > kCtrlMaxChunk)) return fail(HUB_E_INVALID, "chunk must be in [1, 256]");
+  if (on && (margin < 0 || margin > 16)) return fail(HUB_E_INVALID, "margin must be in [0, 16]");
+  h->ctrl_on = on != 0;
+  if (on) {
+    h->ctrl_chunk = chunk;
+    h->ctrl_margin = margin;
+  }
+  return HUB_OK;
+}
+
+hub_status hub_controller_read_stats(hub_basis h, hub_controller_stats* out) {
+  if (!h || !out) return fail(HUB_E_INVALID, "null argument");
+  *out = h->cstats;
+  h->cstats = hub_controller_stats{};
   return HUB_OK;
 }
 

@@ -12,6 +12,9 @@ namespace dev {
 //   y[a,b] = (U popc(u_a & d_b) + e_a + e_b) x[a,b]
 //          + sum over up hops a'->a:   sgn coef_c x[a',b]
 //          + sum over down hops b'->b: sgn coef_c x[a,b'].
+// The observables modes also accumulate, in FP64, the same hop sum with the
+// coefficients of the observation time (K(t_obs) x), and per workgroup the
+// diagonal energy, the double occupation, |x|^2 and Re <x|K(t_obs)|x>.
 // A workgroup owns one tile row.  The row is staged in LDS twice, as +x and
 // -x, followed by a zero slot, so a down hop is one LDS read at an index that
 // already encodes its fermion sign (pad slots read the zero).  Each thread
@@ -21,7 +24,7 @@ namespace dev {
 // read whole source rows from global memory (coalesced; the hop list is
 // uniform over the workgroup), in independent batches of eight, each with a
 // uniform signed class coefficient.
-struct KArgs {
+struct KArgs {  // passed by value as kernel arguments (at most 4 KB)
   int dim_up, dim_dn, nc, j, nslots, m_max, chunks;
   double tol, norm_inf, U;
   const uint32_t* up_bits;
@@ -35,6 +38,7 @@ struct KArgs {
   double coef[2 * kMaxNV * kMaxClasses];  // [v][c] complex
   double slot_coef[2 * 64];                // vector 0: coefficient of every down slot
   double up_coef[2 * 2 * kMaxClasses];     // vector 0: [c][sign] signed coefficient
+  double coef_obs[2 * kMaxNV * kMaxClasses];  // [v][c] complex, observation time (obs modes)
   const void* x;
   void* y;
   const void* xprev;
@@ -44,19 +48,6 @@ struct KArgs {
   const double* prev_partials;
   int prev_nblk;
 };
-
-template <typename V>
-__device__ __forceinline__ void add_class(double (&pr)[kMaxClasses], double (&pi)[kMaxClasses], int c, V x,
-                                          V s) {
-  const double re = (double)x.x * s.x + (double)x.y * s.y;  // conj(x) * s
-  const double im = (double)x.x * s.y - (double)x.y * s.x;
-#pragma unroll
-  for (int k = 0; k < kMaxClasses; ++k)
-    if (k == c) {
-      pr[k] += re;
-      pi[k] += im;
-    }
-}
 
 // Threads per apply workgroup.  Long rows of single vectors use 1024 threads
 // (fewer column passes per thread); short rows, interleaved blocks and the
@@ -99,12 +90,14 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   constexpr bool kL = (MODE == M_LANCZOS || MODE == M_LANCZOS_OBS);
   constexpr bool kO = (MODE == M_LANCZOS_OBS || MODE == M_OBS);
   constexpr bool kW = (MODE != M_OBS);
-  constexpr int kNQ = 1 + 3 + 2 * kMaxClasses;  // alpha, diag, docc, n2, classes
+  constexpr int kNQ = 1 + kObsQ;  // alpha, diag, docc, n2, Re <x|K(t_obs)|x>
   constexpr int kUB = 4;  // up hops gathered before the staging barrier (more costs registers)
   __shared__ double red[kWavesA * NV * (kO ? kNQ : 1) + kWavesA];
   __shared__ double sh_beta[kMaxNV];
   __shared__ V sh_slot[NV > 1 ? 64 * NV : 1];
   __shared__ V sh_up[NV > 1 ? 2 * kMaxClasses * NV : 1];
+  __shared__ double2 sh_oslot[kO ? 64 * NV : 1];             // observation-time coefficient per slot
+  __shared__ double2 sh_oup[kO ? 2 * kMaxClasses * NV : 1];  // and per signed up-hop class
 
   const int tid = threadIdx.x;
   const int v = tid % NV;
@@ -188,15 +181,22 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
       sh_up[t] = V{sg * static_cast<R>(p.coef[2 * (vv * nc + c)]), sg * static_cast<R>(p.coef[2 * (vv * nc + c) + 1])};
     }
   }
+  if (kO) {
+    for (int t = tid; t < 64 * NV; t += kBlockA) {
+      const int s = t / NV, vv = t % NV;
+      const int c = p.slot_class[s];
+      sh_oslot[t] = (s < p.nslots) ? make_double2(p.coef_obs[2 * (vv * nc + c)], p.coef_obs[2 * (vv * nc + c) + 1])
+                                   : make_double2(0.0, 0.0);
+    }
+    for (int t = tid; t < 2 * nc * NV; t += kBlockA) {
+      const int cs = t / NV, vv = t % NV, c = cs >> 1;
+      const double sg = (cs & 1) ? -1.0 : 1.0;
+      sh_oup[t] = make_double2(sg * p.coef_obs[2 * (vv * nc + c)], sg * p.coef_obs[2 * (vv * nc + c) + 1]);
+    }
+  }
   __syncthreads();
 
-  double q_alpha = 0.0, q_diag = 0.0, q_docc = 0.0, q_n2 = 0.0;
-  double q_pr[kMaxClasses], q_pi[kMaxClasses];
-#pragma unroll
-  for (int c = 0; c < kMaxClasses; ++c) {
-    q_pr[c] = 0.0;
-    q_pi[c] = 0.0;
-  }
+  double q_alpha = 0.0, q_diag = 0.0, q_docc = 0.0, q_n2 = 0.0, q_hop = 0.0;
 
   while (q < qend) {
     const int b = q / NV;
@@ -206,6 +206,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     const double nd = static_cast<double>(__popc(ua & db));
     const double dg = p.U * nd + ea + eb;
     V acc = V{static_cast<R>(dg) * xv.x, static_cast<R>(dg) * xv.y};
+    double2 ko = make_double2(0.0, 0.0);  // K(t_obs) x at this element (obs modes)
     if (kO) {
       const double m2 = (double)xv.x * xv.x + (double)xv.y * xv.y;
       q_diag += dg * m2;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
       if (NV == 1) cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
       else cf = sh_slot[s * NV + v];
       acc = cfma(cf, t, acc);
-      if (kO) add_class(q_pr, q_pi, p.slot_class[s], xv, t);  // the staged value carries the sign
+      if (kO) ko = cfma(sh_oslot[s * NV + v], make_double2(t.x, t.y), ko);  // staged value carries the sign
     }
     // up hops: whole source rows from global memory, uniform signed coefficients
     auto up_term = [&](uint32_t e, V t) {
@@ -232,10 +233,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
       if (NV == 1) cf = V{static_cast<R>(p.up_coef[2 * cs]), static_cast<R>(p.up_coef[2 * cs + 1])};
       else cf = sh_up[cs * NV + v];
       acc = cfma(cf, t, acc);
-      if (kO) {
-        const V ts = (e >> 31) ? V{-t.x, -t.y} : t;
-        add_class(q_pr, q_pi, static_cast<int>((e >> 16) & 0xFFu), xv, ts);
-      }
+      if (kO) ko = cfma(sh_oup[cs * NV + v], make_double2(t.x, t.y), ko);
     };
 #pragma unroll
     for (int k = 0; k < kUB; ++k)
@@ -251,6 +249,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
       for (int k = 0; k < 8; ++k)
         if (h0 + k < hcnt) up_term(e[k], t[k]);
     }
+    if (kO) q_hop += (double)xv.x * ko.x + (double)xv.y * ko.y;  // Re conj(x) K x
     const size_t idx = (size_t)a * rowlen + q;
     V out = acc;
     if (kL) {
@@ -264,23 +263,17 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     if (q < qend) load_column(q);
   }
 
-  // workgroup partials: [alpha] [diag, docc, n2, (Re, Im) <x|K_c|x> ...]
+  // workgroup partials: [alpha] [diag, docc, n2, Re <x|K(t_obs)|x>]
   constexpr int nqL = kL ? 1 : 0;
-  const int nqO = kO ? 3 + 2 * nc : 0;
-  const int nq = nqL + nqO;
+  constexpr int nq = nqL + (kO ? kObsQ : 0);
   if (nq == 0) return;
-  // fixed positions (class c at nqL + 3 + 2c) keep the array in registers
   double vals[kNQ];
   if (kL) vals[0] = q_alpha;
   if (kO) {
     vals[nqL + 0] = q_diag;
     vals[nqL + 1] = q_docc;
     vals[nqL + 2] = q_n2;
-#pragma unroll
-    for (int cc = 0; cc < kMaxClasses; ++cc) {
-      vals[nqL + 3 + 2 * cc] = q_pr[cc];
-      vals[nqL + 4 + 2 * cc] = q_pi[cc];
-    }
+    vals[nqL + 3] = q_hop;
   }
   block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)lb * nq * NV);
 }
@@ -308,6 +301,7 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.dn_tab = db.dn_tab;
   for (int s = 0; s < 64; ++s) p.slot_class[s] = db.slot_class[s];
   for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef[k] = L.coef ? L.coef[k] : 0.0;
+  for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef_obs[k] = L.coef_obs ? L.coef_obs[k] : 0.0;
   for (int s = 0; s < 64; ++s) {
     const int c = db.slot_class[s];
     p.slot_coef[2 * s] = (s < db.nslots && L.coef) ? L.coef[2 * c] : 0.0;

@@ -10,7 +10,7 @@
 namespace hub {
 
 constexpr int kMMax = 60;                       // largest Krylov dimension (one wavefront)
-constexpr int kObsQ = 3 + 2 * kMaxClasses;      // <D>, docc, |x|^2, (Re, Im) <x|K_c|x>
+constexpr int kObsQ = 4;  // <D>, docc, |x|^2, Re <x|K(t_obs)|x> (all unnormalised)
 constexpr int kMaxNV = 8;                       // vectors per interleaved block
 constexpr int kBlock = 256;                     // threads per workgroup
 
@@ -34,6 +34,8 @@ struct StepCtl {
   int32_t iter;              // Lanczos iterations completed in this step
   int32_t m_max;
   int32_t any_maxed;         // some vector reached m_max in this step
+  int32_t abort;             // a step ended undecided: later kernels do nothing
+  int32_t steps_done;        // (sub)steps logged since the host last cleared it
   double tol;
   double norm_inf;
 };
@@ -72,6 +74,7 @@ struct ApplyLaunch {
   void* y;
   const void* xprev;     // Lanczos: u_{j-1} (null at j = 0)
   const double* coef;    // host [nv][nc] complex pairs (copied into the launch arguments)
+  const double* coef_obs;  // host [nv][nc] hop coefficients at the observation time (obs modes)
   VecState* st;          // device [nv] (Lanczos/obs)
   StepCtl* ctl;
   int j;                 // Lanczos iteration (0-based); the Krylov decision for m = j is taken here
@@ -98,9 +101,10 @@ hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, V
                          hipStream_t s);
 
 // v = beta0 sum_k y_k s_k u_k over the m_v vectors of each vector v (in place
-// into slot 0), and |v|^2 partials [elem_grid][nv].
+// into slot 0), and |v|^2 partials [elem_grid][nv].  If some vector is still
+// undecided the step is abandoned: ctl->abort is set and slot 0 is kept.
 hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
-                          double* partials, hipStream_t s);
+                          StepCtl* ctl, double* partials, hipStream_t s);
 
 // |v|^2 partials of the step input (if norm), tau of every vector, cleared control block.
 hipError_t launch_step_begin(int prec, int nv, int64_t n, const void* v, VecState* st, StepCtl* ctl, double tau,

@@ -60,12 +60,24 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, typename CT<R>::T*
 // next step's first apply.
 template <typename R, int NV>
 __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, void* const* slots, const VecState* st,
-                                                    double* partials) {
+                                                    StepCtl* ctl, double* partials) {
   using V = typename CT<R>::T;
   __shared__ double red[kWaves * kMaxNV];
   __shared__ double cr[kMaxNV][kMMax], ci[kMaxNV][kMMax];
   __shared__ int mv[kMaxNV];
   const int tid = threadIdx.x;
+  // A step whose launches ended before every vector was decided is abandoned
+  // with slot 0 unchanged; the flag makes the rest of the enqueued work idle.
+  if (ctl->abort) return;
+  bool undecided = false;
+  for (int v = 0; v < NV; ++v) undecided |= (st[v].status == 0);
+  if (undecided) {
+    if (blockIdx.x == 0 && tid == 0) {
+      ctl->abort = 1;
+      ctl->all_done = 1;
+    }
+    return;
+  }
   for (int t = tid; t < NV * kMMax; t += kBlock) {
     const int vv = t / kMMax, k = t % kMMax;
     const VecState& S = st[vv];
@@ -101,6 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_step_begin(int64_t n, const typename
                                                        StepCtl* ctl, double tau, int norm, double* partials) {
   using V = typename CT<R>::T;
   __shared__ double red[kWaves * kMaxNV];
+  if (ctl->abort) return;
   const int tid = threadIdx.x;
   double n2 = 0.0;
   if (norm) {
@@ -119,9 +132,11 @@ __global__ __launch_bounds__(kBlock) void k_step_begin(int64_t n, const typename
   }
 }
 
-// Records the finished step (into log) and clears the control block.
+// Records the finished step (into log) and clears the control block; does
+// nothing after an abandoned step.
 template <int NV>
 __global__ void k_step_log(const VecState* st, StepCtl* ctl, CombineLog* log, double* obs_log, int nobs) {
+  if (ctl->abort) return;
   const int v = threadIdx.x;
   if (v < NV) {
     const VecState& S = st[v];
@@ -139,6 +154,13 @@ __global__ void k_step_log(const VecState* st, StepCtl* ctl, CombineLog* log, do
     ctl->all_done = 0;
     ctl->any_maxed = 0;
     ctl->iter = 0;
+    ctl->steps_done += 1;
+    int maxed = 0;
+    for (int w = 0; w < NV; ++w) maxed |= (st[w].status == 3);
+    if (maxed && log) {  // a vector hit m_max: later enqueued steps do nothing
+      ctl->abort = 2;
+      ctl->all_done = 1;
+    }
   }
 }
 
@@ -388,7 +410,8 @@ int apply_grid(const DevBasis& db, int prec, int nv) { return db.dim_up * apply_
 int apply_nq(int mode, bool obs, int nc) {
   const bool kL = mode == kLanczos;
   const bool kO = mode == kObsOnly || (kL && obs);
-  return (kL ? 1 : 0) + (kO ? 3 + 2 * nc : 0);
+  (void)nc;
+  return (kL ? 1 : 0) + (kO ? kObsQ : 0);
 }
 
 size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows) {
@@ -430,14 +453,14 @@ hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, V
 }
 
 hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
-                          double* partials, hipStream_t s) {
+                          StepCtl* ctl, double* partials, hipStream_t s) {
   const int grid = elem_grid(n * nv);
   if (prec == 0) {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_combine<double, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
-                                         st, partials));
+                                         st, ctl, partials));
   } else {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_combine<float, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
-                                         st, partials));
+                                         st, ctl, partials));
   }
   return hipGetLastError();
 }

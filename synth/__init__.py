@@ -7,9 +7,9 @@ time stepping), so the CPU oracle and the HIP path can both draw from it
 without sharing any computation.
 """
 from .lattices import Lattice, ring, chain, cluster_2d, two_site
-from .workloads import PulseParams, Workload, workloads, random_state, draw_amplitudes
+from .workloads import PulseParams, Workload, workloads, random_state, draw_amplitudes, controller_draws
 
 __all__ = [
     "Lattice", "ring", "chain", "cluster_2d", "two_site",
-    "PulseParams", "Workload", "workloads", "random_state", "draw_amplitudes",
+    "PulseParams", "Workload", "workloads", "random_state", "draw_amplitudes", "controller_draws",
 ]

@@ -55,6 +55,19 @@ def draw_amplitudes(n: int, low: float = 0.2, high: float = 1.0, seed: int = SEE
     return np.random.default_rng(seed).uniform(low, high, size=n)
 
 
+def controller_draws(n: int, seed: int = SEED + 1):
+    """Seeded (U, A0, omega) triples for controller training runs:
+    U ~ U[4, 12], A0 ~ U[0.2, 1.2], omega ~ U[U/2, 2U], drawn in that order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        U = float(rng.uniform(4.0, 12.0))
+        A0 = float(rng.uniform(0.2, 1.2))
+        om = float(rng.uniform(0.5 * U, 2.0 * U))
+        out.append((U, A0, om))
+    return out
+
+
 def random_state(dim: int, seed: int = 1, nvec: int = 1) -> np.ndarray:
     """Complex standard-normal vectors, each normalised to 1; shape (nvec, dim)."""
     rng = np.random.default_rng(seed)
@@ -85,5 +98,9 @@ def workloads() -> Dict[str, Workload]:
         "ring14_block": Workload("ring14_block", ring(14), 8.0, 7, 7, ring_pulse,
                                  dt=0.01, n_steps=200, tol=1e-10, m_max=30,
                                  extra={"A0_batch": tuple(0.1 * k for k in range(1, 9))}),
+        # controller training logs: 10-site ring runs under seeded (U, A0, omega)
+        "controller": Workload("controller", ring(10), 8.0, 5, 5, ring_pulse,
+                               dt=0.01, n_steps=400, tol=1e-8, m_max=30,
+                               extra={"draws": tuple(controller_draws(16))}),
     }
     return out

@@ -1,0 +1,155 @@
+"""Learned Krylov controller on the GPU, through the C ABI.
+
+* MLP forward, gradient (read back from Adam's first moment) and Adam update
+  against the FP64 oracle (oracle/mlp.py), FP32 tolerances;
+* training on adaptive-run logs lowers the loss and predicts m;
+* the controlled schedule gives bit-identical vectors, observables and step
+  logs to the adaptive schedule, whatever the predictions (always too small:
+  every step falls back; always large; trained), for single vectors, blocks
+  and complex64, and stops at the same step when m_max is hit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2005_13498_amd as hub
+from paper_2005_13498_amd import controller as ctl
+from oracle import mlp
+from synth import workloads, PulseParams, ring
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def test_mlp_forward_matches_oracle():
+    rng = np.random.default_rng(11)
+    theta = rng.normal(scale=0.3, size=mlp.N_PARAM)
+    X = rng.normal(size=(1000, 8))
+    out = torch.zeros((1000, 2), dtype=torch.float32, device=DEV)
+    hub.hub_mlp_forward(_dev(theta), _dev(X), out)
+    ref, _ = mlp.forward(theta.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= 2e-5 * (1 + np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n_rows", [1, 37, 3000])
+def test_mlp_gradient_and_adam_match_oracle(n_rows):
+    rng = np.random.default_rng(12 + n_rows)
+    theta = (rng.normal(scale=0.3, size=mlp.N_PARAM)).astype(np.float32).astype(np.float64)
+    X = rng.normal(size=(n_rows, 8)).astype(np.float32).astype(np.float64)
+    Y = rng.normal(size=(n_rows, 2)).astype(np.float32).astype(np.float64)
+    P, m, v = _dev(theta), torch.zeros(mlp.N_PARAM, device=DEV), torch.zeros(mlp.N_PARAM, device=DEV)
+    loss = torch.zeros(1, device=DEV)
+    ws = torch.empty(hub.hub_mlp_workspace_bytes(n_rows) // 4 + 1, device=DEV)
+    lr = 1e-3
+    hub.hub_mlp_train_step(P, m, v, 1, lr, _dev(X), _dev(Y), loss, ws)
+    L_ref, g_ref = mlp.loss_and_grad(theta, X, Y)
+    assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
+    g_gpu = m.cpu().numpy().astype(np.float64) / 0.1     # first moment after one step = 0.1 g
+    assert np.max(np.abs(g_gpu - g_ref)) <= 1e-4 * np.max(np.abs(g_ref))
+    th_ref, m_ref, v_ref = mlp.adam_step(theta, np.zeros_like(theta), np.zeros_like(theta), 1, lr, g_ref)
+    big = np.abs(g_ref) > 1e-3 * np.max(np.abs(g_ref))
+    d = np.abs(P.cpu().numpy().astype(np.float64) - th_ref)
+    assert np.max(d[big]) <= 1e-3 * lr + 1e-6
+    assert np.max(d) <= 2 * lr + 1e-6
+    # five more steps on the same data: the loss follows the oracle's trajectory
+    th, mo, vo = th_ref, m_ref, v_ref
+    for t in range(2, 7):
+        hub.hub_mlp_train_step(P, m, v, t, lr, _dev(X), _dev(Y), loss, ws)
+        L_ref, g = mlp.loss_and_grad(th, X, Y)
+        assert abs(loss.item() - L_ref) <= 1e-4 * L_ref
+        th, mo, vo = mlp.adam_step(th, mo, vo, t, lr, g)
+
+
+@pytest.fixture(scope="module")
+def ring8():
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    v0 = torch.empty(B.dim, dtype=torch.complex128, device=DEV)
+    hub.hub_ground_state(B.handle, hub.hub_pulse_A(w.pulse, 0.0), v0, hub.make_opts(tol=1e-13, m_max=100))
+    yield w, B, v0
+    B.close()
+
+
+@pytest.fixture(scope="module")
+def trained(ring8):
+    w, B, v0 = ring8
+    opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+    pulses = [PulseParams(0, a, om, 1.0, 0.3) for a, om in ((0.3, 6.0), (0.7, 9.0), (1.0, 8.0), (0.5, 12.0))]
+    X, Y = ctl.collect_rows(B, v0, pulses, 0.0, w.dt, 200, opts, chunk=8)
+    params, hist = ctl.train(X, Y, steps=800, lr=3e-3, seed=1)
+    return params, hist, X, Y
+
+
+def test_training_lowers_loss_and_predicts_m(trained):
+    params, hist, X, Y = trained
+    assert hist[-1][1] < 0.1 * hist[0][1], hist
+    out = torch.zeros((len(X), 2), device=DEV)
+    hub.hub_mlp_forward(_dev(params), _dev(X), out)
+    m_pred = np.ceil(np.exp2(out.cpu().numpy()[:, 0]) - 1e-6)
+    m_true = np.exp2(Y[:, 0])
+    assert np.mean(np.abs(m_pred - m_true) <= 1) >= 0.9
+
+
+def _run(B, pulses, w, v0, prec, opts, params=None, chunk=8, margin=1, allow_nc=False):
+    v = v0.to(prec).repeat(len(pulses)).contiguous()
+    if params is not None:
+        hub.hub_controller_load(B.handle, params)
+        hub.hub_controller_enable(B.handle, True, chunk, margin)
+    else:
+        hub.hub_controller_enable(B.handle, False)
+    hub.hub_controller_read_stats(B.handle)
+    try:
+        st, obs, log = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, w.n_steps, opts, v,
+                                         allow_not_converged=allow_nc)
+    finally:
+        hub.hub_controller_enable(B.handle, False)
+    return st, v, obs, log, hub.hub_controller_read_stats(B.handle)
+
+
+def _same(a, b):
+    assert a[0] == b[0]
+    assert torch.equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2], equal_nan=True)
+    assert np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("prec,nv", [(torch.complex128, 1), (torch.complex128, 3), (torch.complex64, 2)])
+def test_controlled_schedule_is_bit_identical(ring8, trained, prec, nv):
+    w, B, v0 = ring8
+    opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+    pulses = [w.pulse] + [PulseParams(0, 0.3 + 0.2 * k, 8.0, 1.0, 0.3) for k in range(nv - 1)]
+    ref = _run(B, pulses, w, v0, prec, opts)
+    steps = w.n_steps
+    # always too small: every step abandoned on the device and re-run adaptively
+    low = _run(B, pulses, w, v0, prec, opts, ctl.constant_params(2), margin=0)
+    _same(low, ref)
+    assert low[4]["fallbacks"] >= 0.9 * steps
+    # always m_max: never abandoned
+    high = _run(B, pulses, w, v0, prec, opts, ctl.constant_params(w.m_max), margin=0)
+    _same(high, ref)
+    # counters add up over the vector groups of the call
+    assert high[4]["fallbacks"] == 0 and high[4]["steps"] >= steps and high[4]["steps"] % steps == 0
+    # trained
+    tr = _run(B, pulses, w, v0, prec, opts, trained[0], chunk=16, margin=1)
+    _same(tr, ref)
+    s = tr[4]
+    assert s["fallbacks"] <= 0.1 * s["steps"], s
+    mean_m = float(np.mean(ref[3][:, :, 0]))
+    assert s["lanczos_launches"] <= (mean_m + 4) * s["steps"], (s, mean_m)
+
+
+def test_controlled_schedule_stops_at_m_max_like_adaptive(ring8):
+    w, B, v0 = ring8
+    opts = hub.make_opts(tol=1e-15, m_max=4)
+    pulses = [w.pulse]
+    ref = _run(B, pulses, w, v0, torch.complex128, opts, allow_nc=True)
+    assert ref[0] == hub.HUB_E_NOT_CONVERGED
+    got = _run(B, pulses, w, v0, torch.complex128, opts, ctl.constant_params(3), allow_nc=True)
+    _same(got, ref)
+    got = _run(B, pulses, w, v0, torch.complex128, opts, ctl.constant_params(30), allow_nc=True)
+    _same(got, ref)
