@@ -72,6 +72,7 @@ struct hub_basis_s {
   double* partials_e = nullptr;   // partial sums of the elementwise kernels
   size_t partials_e_bytes = 0;
   double* scal = nullptr;         // device scalars [kMMax*2 + 16]
+  double* rcoef = nullptr;        // device re-orthogonalisation coefficients [kMMax + 1][kMaxNV] complex
   int rows_c128 = 1, rows_c64 = 1;
   // learned Krylov controller
   bool ctrl_on = false, ctrl_loaded = false;
@@ -129,7 +130,8 @@ hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t b
     h->blockbuf_bytes = blockbuf_bytes;
   }
   // partial sums of an apply: grid * (1 + kObsQ) * nv doubles at most
-  size_t pb = static_cast<size_t>(2048) * 2 * 64 * sizeof(double);
+  // (also the CGS inner-product partials: elem_grid * (kMMax + 1) * 2 * nv)
+  size_t pb = static_cast<size_t>(256) * (kMMax + 1) * 2 * kMaxNV * sizeof(double);
   for (int pr = 0; pr < 2; ++pr)
     for (int nv = 1; nv <= kMaxNV; nv *= 2)
       pb = std::max(pb, static_cast<size_t>(hub::apply_grid(h->D, pr, nv)) * (1 + kObsQ) * nv * sizeof(double));
@@ -211,7 +213,7 @@ hub_status check_opts(const hub_krylov_opts& o) {
   if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(HUB_E_INVALID, "opts.tol must be > 0");
   if (o.m_max < 1 || o.m_max > kMMax) return fail(HUB_E_INVALID, "opts.m_max must be in 1..60");
   if (o.substeps < 1) return fail(HUB_E_INVALID, "opts.substeps must be >= 1");
-  if (o.reorth != 0) return fail(HUB_E_INVALID, "opts.reorth = 1 is not supported by this build");
+  if (o.reorth != 0 && o.reorth != 1) return fail(HUB_E_INVALID, "opts.reorth must be 0 or 1");
   if (o.m_hint < 0) return fail(HUB_E_INVALID, "opts.m_hint must be >= 0");
   return HUB_OK;
 }
@@ -355,9 +357,14 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.j = jj;
     hub_status r = launch_apply_timed(h, A);
     if (r != HUB_OK) return r;
-    if (jj < o.m_max)
+    if (jj < o.m_max) {
       HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
                                  hub::apply_nq(hub::kLanczos, A.obs, nc), h->partials_e, stream));
+      if (o.reorth)  // CGS2: two Gram-Schmidt passes against u_0..u_j
+        for (int pass = 0; pass < 2; ++pass)
+          HUB_HIP(hub::launch_reorth(pi, nv, dim, h->slot_ptrs, jj, h->st, h->ctl, h->partials, h->rcoef,
+                                     h->partials_e, stream));
+    }
     return HUB_OK;
   };
   auto finish_sub = [&](int n, int sub) -> hub_status {
@@ -717,6 +724,7 @@ hub_status hub_basis_create(const hub_lattice* lat, int32_t n_up, int32_t n_dn, 
       hipMalloc(reinterpret_cast<void**>(&h->st), kMaxNV * sizeof(VecState)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&h->ctl), sizeof(StepCtl)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&h->scal), (2 * kMMax + 64) * sizeof(double) * 2) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&h->rcoef), (kMMax + 1) * kMaxNV * 2 * sizeof(double)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(HUB_E_NOMEM, "workspace allocation failed"));
   if (hipMemset(h->ctl, 0, sizeof(StepCtl)) != hipSuccess ||
@@ -745,6 +753,7 @@ void hub_basis_destroy(hub_basis h) {
   if (h->ctl) (void)hipFree(h->ctl);
   if (h->partials_e) (void)hipFree(h->partials_e);
   if (h->scal) (void)hipFree(h->scal);
+  if (h->rcoef) (void)hipFree(h->rcoef);
   if (h->partials) (void)hipFree(h->partials);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->ctrl_params) (void)hipFree(h->ctrl_params);

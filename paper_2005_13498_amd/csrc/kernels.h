@@ -100,6 +100,13 @@ hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, V
                          const double* apply_partials, int apply_nblk, int apply_nq, double* partials,
                          hipStream_t s);
 
+// One CGS pass of u_{j+1} (slot j+1) against v_k = s_k u_k, k <= j, with FP64
+// coefficients: dot partials [elem_grid][j+1][2][nv] in dot_partials, the
+// coefficients [j+1][nv] complex in coef, and |u_{j+1}|^2 partials
+// [elem_grid][nv] for the next apply.  Idle after the step's decision.
+hipError_t launch_reorth(int prec, int nv, int64_t n, void* const* slots_dev, int j, const VecState* st,
+                         const StepCtl* ctl, double* dot_partials, double* coef, double* norm_partials,
+                         hipStream_t s);
 // v = beta0 sum_k y_k s_k u_k over the m_v vectors of each vector v (in place
 // into slot 0), and |v|^2 partials [elem_grid][nv].  If some vector is still
 // undecided the step is abandoned: ctl->abort is set and slot 0 is kept.

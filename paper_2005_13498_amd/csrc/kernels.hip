@@ -282,6 +282,91 @@ __global__ __launch_bounds__(kBlock) void k_dots(int64_t n, int nvec, const type
   }
 }
 
+// --------------------- CGS2 re-orthogonalisation ---------------------------
+// One classical Gram-Schmidt pass of w = u_{j+1} against the Krylov vectors
+// v_k = s_k u_k, k = 0..j (FP64 coefficients):  w <- w - sum_k v_k <v_k, w>.
+// Three kernels: partial inner products, their fixed-order reduction into
+// coefficients s_k^2 <u_k, w>, and the subtraction with |w|^2 partials.
+// All exit at once after the step's decision.
+constexpr int kReorthK = 4;  // inner products accumulated per pass over w
+
+template <typename R, int NV>
+__global__ __launch_bounds__(kBlock) void k_reorth_dot(int64_t n, void* const* slots, int j, const StepCtl* ctl,
+                                                       double* partials) {
+  using V = typename CT<R>::T;
+  __shared__ double red[kWaves * 2 * kReorthK * kMaxNV];
+  if (ctl->all_done) return;
+  const V* w = static_cast<const V*>(slots[j + 1]);
+  const int64_t total = n * NV;
+  const int tid = threadIdx.x;
+  for (int kb = 0; kb <= j; kb += kReorthK) {
+    const int kn = min(kReorthK, j + 1 - kb);
+    double acc[2 * kReorthK];
+#pragma unroll
+    for (int q = 0; q < 2 * kReorthK; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < total; i += (int64_t)gridDim.x * kBlock) {
+      const V x = w[i];
+#pragma unroll
+      for (int q = 0; q < kReorthK; ++q) {
+        if (q < kn) {
+          const V u = static_cast<const V*>(slots[kb + q])[i];
+          acc[2 * q] += (double)u.x * x.x + (double)u.y * x.y;      // conj(u) w
+          acc[2 * q + 1] += (double)u.x * x.y - (double)u.y * x.x;
+        }
+      }
+    }
+    block_partials<NV>(acc, 2 * kn, red, partials + ((size_t)blockIdx.x * (j + 1) * 2 + 2 * kb) * NV);
+  }
+}
+
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_reorth_coef(const double* partials, int nrows, int j, const VecState* st,
+                                                        const StepCtl* ctl, double* coef) {
+  __shared__ double red[kWaves];
+  if (ctl->all_done) return;
+  const int ncols = (j + 1) * 2 * NV;  // column (k * 2 + c) * NV + v
+  for (int t = 0; t < ncols; ++t) {
+    const double s = reduce_column(partials, nrows, ncols, t, red);
+    if (threadIdx.x == 0) {
+      const int v = t % NV, c = (t / NV) % 2, k = t / (2 * NV);
+      const double sc = st[v].scale[k];
+      coef[(k * NV + v) * 2 + c] = s * sc * sc;
+    }
+  }
+}
+
+template <typename R, int NV>
+__global__ __launch_bounds__(kBlock) void k_reorth_axpy(int64_t n, void* const* slots, int j, const double* coef,
+                                                        const StepCtl* ctl, double* partials) {
+  using V = typename CT<R>::T;
+  __shared__ double red[kWaves * kMaxNV];
+  __shared__ double cr[kMMax + 1][kMaxNV], ci[kMMax + 1][kMaxNV];
+  if (ctl->all_done) return;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < (j + 1) * NV; t += kBlock) {
+    cr[t / NV][t % NV] = coef[2 * t];
+    ci[t / NV][t % NV] = coef[2 * t + 1];
+  }
+  __syncthreads();
+  V* w = static_cast<V*>(slots[j + 1]);
+  const int v = tid % NV;
+  const int64_t total = n * NV;
+  double n2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const V x = w[i];
+    double ar = x.x, ai = x.y;
+    for (int k = 0; k <= j; ++k) {
+      const V u = static_cast<const V*>(slots[k])[i];
+      ar -= cr[k][v] * u.x - ci[k][v] * u.y;
+      ai -= cr[k][v] * u.y + ci[k][v] * u.x;
+    }
+    const V o = V{static_cast<R>(ar), static_cast<R>(ai)};
+    w[i] = o;
+    n2 += (double)o.x * o.x + (double)o.y * o.y;
+  }
+  block_partials<NV>(&n2, 1, red, partials + (size_t)blockIdx.x * NV);
+}
+
 // ------------------------------- BLAS-1 ------------------------------------
 __global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, const double2* const* vecs, int kv,
                                                      const double2* w, double* partials) {
@@ -435,6 +520,33 @@ hipError_t launch_apply(const ApplyLaunch& L, int* grid_out) {
     case 8: { constexpr int NVC = 8; CALL; } break;     \
     default: return hipErrorInvalidValue;               \
   }
+
+hipError_t launch_reorth(int prec, int nv, int64_t n, void* const* slots_dev, int j, const VecState* st,
+                         const StepCtl* ctl, double* dot_partials, double* coef, double* norm_partials,
+                         hipStream_t s) {
+  const int grid = elem_grid(n * nv);
+  if (prec == 0) {
+    HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_reorth_dot<double, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
+                                         j, ctl, dot_partials));
+  } else {
+    HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_reorth_dot<float, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
+                                         j, ctl, dot_partials));
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_reorth_coef<NVC>), dim3(1), dim3(kBlock), 0, s, dot_partials, grid, j, st,
+                                       ctl, coef));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (prec == 0) {
+    HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_reorth_axpy<double, NVC>), dim3(grid), dim3(kBlock), 0, s, n,
+                                         slots_dev, j, coef, ctl, norm_partials));
+  } else {
+    HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_reorth_axpy<float, NVC>), dim3(grid), dim3(kBlock), 0, s, n,
+                                         slots_dev, j, coef, ctl, norm_partials));
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, VecState* st, StepCtl* ctl, int j,
                          const double* apply_partials, int apply_nblk, int apply_nq, double* partials,
