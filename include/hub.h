@@ -320,6 +320,21 @@ typedef struct {
 hub_status hub_controller_read_stats(hub_basis basis, hub_controller_stats *out);
 
 /* ------------------------------------------------------------------------ */
+/* Choice of the H*v kernels for single vectors (plain applies and the
+ * Lanczos iterations that do not also accumulate observables).
+ *   path 0: one pass (rows staged in LDS; up hops gathered as whole rows of
+ *           x from global memory);
+ *   path 1: two passes whenever 4 columns of x for all up strings fit in LDS
+ *           (a row pass for the diagonal and the down hops, then a column
+ *           pass that stages those columns and adds the up hops);
+ *   path -1 (default): two passes when they fit and the vector is larger
+ *           than 4 MiB, one pass otherwise.
+ * Plain applies give bit-identical results on both paths; in Lanczos mode
+ * the alpha_j reduction is summed in another order (deterministic either
+ * way). */
+hub_status hub_set_apply_path(hub_basis basis, int32_t path);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing of the matrix-free apply (for roofline reporting).  While
  * enabled, the library brackets with HIP events on the launch stream every
  * hub_apply_H launch and every Lanczos H*v launch of a propagation except the

@@ -39,7 +39,8 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_ground_state", "hub_pulse_A", "hub_last_error", "hub_profile_enable",
            "hub_profile_read", "hub_apply_cop", "hub_dot", "hub_greens_diag",
            "hub_mlp_forward", "hub_mlp_workspace_bytes", "hub_mlp_train_step", "hub_controller_features",
-           "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats")
+           "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats",
+           "hub_set_apply_path")
 
 # Controller MLP sizes (HUB_MLP_* in hub.h).
 MLP_IN, MLP_HID, MLP_OUT = 8, 64, 2
@@ -131,6 +132,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_controller_load": ([vp, P(ctypes.c_float), i32], i32),
         "hub_controller_enable": ([vp, i32, i32, i32], i32),
         "hub_controller_read_stats": ([vp, P(hub_controller_stats)], i32),
+        "hub_set_apply_path": ([vp, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -434,6 +436,11 @@ def hub_controller_read_stats(h) -> dict:
     s = hub_controller_stats()
     _check(load_library().hub_controller_read_stats(ctypes.c_void_p(h), ctypes.byref(s)))
     return {k: getattr(s, k) for k, _ in hub_controller_stats._fields_}
+
+
+def hub_set_apply_path(h, path: int) -> None:
+    """-1 automatic, 0 one-pass, 1 two-pass H*v kernels for single vectors."""
+    _check(load_library().hub_set_apply_path(ctypes.c_void_p(h), int(path)))
 
 
 class Basis:

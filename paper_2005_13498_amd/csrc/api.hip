@@ -230,7 +230,7 @@ hub_status check_common(hub_basis h, hub_prec prec, int32_t nvec) {
 // Events bracket plain applies (hub_apply_H) and Lanczos-mode applies that do
 // not also accumulate observables, so a propagation's recorded average is
 // that of one kernel.
-hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L) {
+hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid = nullptr) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = h->prof && (L.mode == hub::kPlain || (L.mode == hub::kLanczos && !L.obs));
   if (timed) {
@@ -244,7 +244,7 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L) {
     }
     HUB_HIP(hipEventRecord(e0, L.stream));
   }
-  HUB_HIP(hub::launch_apply(L));
+  HUB_HIP(hub::launch_apply(L, grid));
   if (timed) {
     HUB_HIP(hipEventRecord(e1, L.stream));
     h->ev_used.push_back({e0, e1});
@@ -340,7 +340,6 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   L.prev_partials = h->partials_e;
   L.prev_nblk = hub::elem_grid(dim * nv);
   L.stream = stream;
-  const int agrid = hub::apply_grid(h->D, pi, nv);
 
   const int S = o.substeps;
   CombineLog* dlog_c = static_cast<CombineLog*>(dlog);
@@ -355,7 +354,8 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.xprev = jj > 0 ? ptrs[jj - 1] : nullptr;
     A.coef = coef_mid.data() + static_cast<size_t>(n) * nv * 2 * nc;
     A.j = jj;
-    hub_status r = launch_apply_timed(h, A);
+    int agrid = 0;  // workgroups that wrote the apply's partial sums
+    hub_status r = launch_apply_timed(h, A, &agrid);
     if (r != HUB_OK) return r;
     if (jj < o.m_max) {
       HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
@@ -591,8 +591,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.coef = coef_obs->data() + static_cast<size_t>(n_steps) * nv * 2 * nc;
     A.coef_obs = A.coef;
     A.j = 0;
-    HUB_HIP(hub::launch_apply(A));
-    HUB_HIP(hub::launch_finalize_obs(nv, h->partials, agrid, hub::apply_nq(hub::kObsOnly, true, nc), h->st, stream));
+    int ogrid = 0;
+    HUB_HIP(hub::launch_apply(A, &ogrid));
+    HUB_HIP(hub::launch_finalize_obs(nv, h->partials, ogrid, hub::apply_nq(hub::kObsOnly, true, nc), h->st, stream));
     HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, nullptr, dobs + static_cast<size_t>(n_steps) * nv * kObsQ,
                                  kObsQ, stream));
   }
@@ -719,6 +720,10 @@ hub_status hub_basis_create(const hub_lattice* lat, int32_t n_up, int32_t n_dn, 
   D.nslots = B.dn.nslots;
   D.maxs_pad = B.dn.maxs_pad;
   for (int k = 0; k < 64; ++k) D.slot_class[k] = B.dn.slot_class[k];
+  if ((s = upload(h, &D.up_tab, B.up.tabc)) != HUB_OK) return cleanup(s);
+  D.up_nslots = B.up.nslots;
+  D.up_maxs_pad = B.up.maxs_pad;
+  for (int k = 0; k < 64; ++k) D.up_slot_class[k] = B.up.slot_class[k];
 
   if (hipMalloc(reinterpret_cast<void**>(&h->slot_ptrs), (kMMax + 2) * sizeof(void*)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&h->st), kMaxNV * sizeof(VecState)) != hipSuccess ||
@@ -1576,6 +1581,13 @@ hub_status hub_controller_read_stats(hub_basis h, hub_controller_stats* out) {
   if (!h || !out) return fail(HUB_E_INVALID, "null argument");
   *out = h->cstats;
   h->cstats = hub_controller_stats{};
+  return HUB_OK;
+}
+
+hub_status hub_set_apply_path(hub_basis h, int32_t path) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (path < -1 || path > 1) return fail(HUB_E_INVALID, "path must be -1, 0 or 1");
+  h->D.two_pass = path;
   return HUB_OK;
 }
 

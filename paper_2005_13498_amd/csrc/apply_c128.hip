@@ -3,8 +3,8 @@
 
 namespace hub {
 
-hipError_t launch_apply_c128(const ApplyLaunch& L, int grid, size_t lds) {
-  return dev::apply_nv<double>(L, grid, lds);
+hipError_t launch_apply_c128(const ApplyLaunch& L, int grid, size_t lds, int* pgrid) {
+  return dev::apply_nv<double>(L, grid, lds, pgrid);
 }
 
 }  // namespace hub

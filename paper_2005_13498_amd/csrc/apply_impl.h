@@ -82,12 +82,16 @@ __device__ __forceinline__ void block_partials_seq(const double (&vals)[NQ], int
   }
 }
 
-template <typename R, int NV, int MODE, int MAXS, int BLK>
+// UPH = false: row pass of the two-pass apply (diagonal and down hops only;
+// in Lanczos mode the prologue still takes the Krylov decision, and the raw
+// partial product is written for the column pass to finish).
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH>
 __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   using V = typename CT<R>::T;
   constexpr int kBlockA = BLK;
   constexpr int kWavesA = kBlockA / 64;
   constexpr bool kL = (MODE == M_LANCZOS || MODE == M_LANCZOS_OBS);
+  constexpr bool kEpi = kL && UPH;  // Lanczos epilogue and alpha partials here
   constexpr bool kO = (MODE == M_LANCZOS_OBS || MODE == M_OBS);
   constexpr bool kW = (MODE != M_OBS);
   constexpr int kNQ = 1 + kObsQ;  // alpha, diag, docc, n2, Re <x|K(t_obs)|x>
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   const int cw = (rowlen + p.chunks - 1) / p.chunks;
   const int qbeg = (lb % p.chunks) * cw;
   const int qend = min(rowlen, qbeg + cw);
-  const int hb = p.up_ptr[a], hcnt = p.up_ptr[a + 1] - hb;
+  const int hb = p.up_ptr[a], hcnt = UPH ? p.up_ptr[a + 1] - hb : 0;
   const uint32_t ua = p.up_bits[a];
   const double ea = p.eps_up ? p.eps_up[a] : 0.0;
   const uint2* tab2 = reinterpret_cast<const uint2*>(p.dn_tab);
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     for (int k = 0; k < kUB; ++k) eu[k] = (k < hcnt) ? p.up_hops[hb + k] : 0u;
 #pragma unroll
     for (int k = 0; k < kUB; ++k) tu[k] = (k < hcnt) ? x[(size_t)(eu[k] & 0xFFFFu) * rowlen + qq] : V{0, 0};
-    if (kL && p.j > 0) pv = static_cast<const V*>(p.xprev)[(size_t)a * rowlen + qq];
+    if (kEpi && p.j > 0) pv = static_cast<const V*>(p.xprev)[(size_t)a * rowlen + qq];
   };
   if (q < qend) load_column(q);
 
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     if (kO) q_hop += (double)xv.x * ko.x + (double)xv.y * ko.y;  // Re conj(x) K x
     const size_t idx = (size_t)a * rowlen + q;
     V out = acc;
-    if (kL) {
+    if (kEpi) {
       out.x = out.x * sj - bprev * pv.x;
       out.y = out.y * sj - bprev * pv.y;
       // alpha_j = Re <s_j u_j, w>
@@ -264,11 +268,11 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   }
 
   // workgroup partials: [alpha] [diag, docc, n2, Re <x|K(t_obs)|x>]
-  constexpr int nqL = kL ? 1 : 0;
+  constexpr int nqL = kEpi ? 1 : 0;
   constexpr int nq = nqL + (kO ? kObsQ : 0);
   if (nq == 0) return;
   double vals[kNQ];
-  if (kL) vals[0] = q_alpha;
+  if (kEpi) vals[0] = q_alpha;
   if (kO) {
     vals[nqL + 0] = q_diag;
     vals[nqL + 1] = q_docc;
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)lb * nq * NV);
 }
 
-template <typename R, int NV, int MODE, int MAXS, int BLK>
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH>
 hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   const DevBasis& db = *L.db;
   KArgs p;
@@ -322,7 +326,7 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.partials = L.partials;
   p.prev_partials = L.prev_partials;
   p.prev_nblk = L.prev_nblk;
-  auto fn = k_apply<R, NV, MODE, MAXS, BLK>;
+  auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH>;
   // dynamic LDS above the 64 KB default must be opted into (CU total 160 KB)
   static int max_dyn = -1;
   if (max_dyn < 0) {
@@ -341,26 +345,186 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   return hipGetLastError();
 }
 
-template <typename R, int NV, int MODE, int BLK>
+template <typename R, int NV, int MODE, int BLK, bool UPH = true>
 hipError_t apply_s(const ApplyLaunch& L, int grid, size_t lds) {
   switch (L.db->maxs_pad) {
-    case 4: return apply_t<R, NV, MODE, 4, BLK>(L, grid, lds);
-    case 8: return apply_t<R, NV, MODE, 8, BLK>(L, grid, lds);
-    case 12: return apply_t<R, NV, MODE, 12, BLK>(L, grid, lds);
-    case 16: return apply_t<R, NV, MODE, 16, BLK>(L, grid, lds);
-    case 20: return apply_t<R, NV, MODE, 20, BLK>(L, grid, lds);
-    case 24: return apply_t<R, NV, MODE, 24, BLK>(L, grid, lds);
-    case 32: return apply_t<R, NV, MODE, 32, BLK>(L, grid, lds);
-    case 48: return apply_t<R, NV, MODE, 48, BLK>(L, grid, lds);
-    case 64: return apply_t<R, NV, MODE, 64, BLK>(L, grid, lds);
+    case 4: return apply_t<R, NV, MODE, 4, BLK, UPH>(L, grid, lds);
+    case 8: return apply_t<R, NV, MODE, 8, BLK, UPH>(L, grid, lds);
+    case 12: return apply_t<R, NV, MODE, 12, BLK, UPH>(L, grid, lds);
+    case 16: return apply_t<R, NV, MODE, 16, BLK, UPH>(L, grid, lds);
+    case 20: return apply_t<R, NV, MODE, 20, BLK, UPH>(L, grid, lds);
+    case 24: return apply_t<R, NV, MODE, 24, BLK, UPH>(L, grid, lds);
+    case 32: return apply_t<R, NV, MODE, 32, BLK, UPH>(L, grid, lds);
+    case 48: return apply_t<R, NV, MODE, 48, BLK, UPH>(L, grid, lds);
+    case 64: return apply_t<R, NV, MODE, 64, BLK, UPH>(L, grid, lds);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass of the two-pass apply (one vector).  A workgroup owns kColW
+// consecutive columns b0.. of the tile and stages them for every up string a
+// in LDS as +x, -x and a zero row (layout [copy][a][kColW]), so an up hop is
+// one LDS read at an index that carries its fermion sign, exactly like the
+// down hops of the row pass.  Each thread finishes elements (a, b): it adds
+// the up hops (padded, class-sorted slots, coefficients in SGPRs) to the row
+// pass's partial product in y and, in Lanczos mode, applies the epilogue and
+// accumulates alpha partials.  Every x element is read from memory once per
+// pass instead of once per up hop.
+struct ColArgs {
+  int dim_up, dim_dn, j, m_max;
+  const uint16_t* up_tab;   // [dim_up][MAXS]
+  double slot_coef[2 * 64]; // coefficient of every up slot (complex)
+  const void* x;
+  void* y;                  // in: row-pass partial product, out: result
+  const void* xprev;
+  const VecState* st;
+  const StepCtl* ctl;
+  double* partials;         // Lanczos: alpha partials [grid]
+};
+
+template <typename R, int MODE, int MAXS, int BLK>
+__global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
+  using V = typename CT<R>::T;
+  constexpr bool kL = MODE == M_LANCZOS;
+  constexpr int kW = BLK / 64;
+  __shared__ double red[kW];
+  R sj = 1, bprev = 0;
+  if (kL) {
+    if (p.ctl->all_done || p.j >= p.m_max) return;
+    // |u_j| as recorded by the row pass's decision (beta0 at j = 0)
+    const VecState& S = p.st[0];
+    const double bv = p.j == 0 ? S.beta0 : S.beta[p.j - 1];
+    sj = static_cast<R>(bv > 0.0 ? 1.0 / bv : 0.0);
+    if (p.j > 0) bprev = static_cast<R>(bv * S.scale[p.j - 1]);
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V* xs = reinterpret_cast<V*>(smem_raw);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int b0 = lb * kColW;
+  const V* __restrict__ x = static_cast<const V*>(p.x);
+  V* __restrict__ y = static_cast<V*>(p.y);
+  const int half = (p.dim_up + 1) * kColW;
+  for (int t = threadIdx.x; t < half; t += BLK) {
+    const int a = t / kColW, c = t % kColW;
+    V v = V{0, 0};
+    if (a < p.dim_up && b0 + c < p.dim_dn) v = x[(size_t)a * p.dim_dn + b0 + c];
+    xs[t] = v;
+    xs[half + t] = V{-v.x, -v.y};
+  }
+  __syncthreads();
+  const uint2* tab2 = reinterpret_cast<const uint2*>(p.up_tab);
+  constexpr int kQ2 = MAXS / 4;
+  double q_alpha = 0.0;
+  for (int q = threadIdx.x; q < p.dim_up * kColW; q += BLK) {
+    const int a = q / kColW, c = q % kColW;
+    if (b0 + c >= p.dim_dn) continue;
+    uint2 ev[kQ2];
+#pragma unroll
+    for (int k = 0; k < kQ2; ++k) ev[k] = tab2[(size_t)a * kQ2 + k];
+    const size_t o = (size_t)a * p.dim_dn + b0 + c;
+    V acc = y[o];
+    V pv = V{0, 0};
+    if (kL && p.j > 0) pv = static_cast<const V*>(p.xprev)[o];
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      const uint32_t w2 = (s & 3) < 2 ? ev[s >> 2].x : ev[s >> 2].y;
+      const uint32_t idx = (s & 1) ? (w2 >> 16) : (w2 & 0xFFFFu);
+      const V t = xs[idx * kColW + c];
+      const V cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
+      acc = cfma(cf, t, acc);
+    }
+    V out = acc;
+    if (kL) {
+      const V xv = xs[a * kColW + c];
+      out.x = out.x * sj - bprev * pv.x;
+      out.y = out.y * sj - bprev * pv.y;
+      q_alpha += (double)sj * ((double)xv.x * out.x + (double)xv.y * out.y);
+    }
+    y[o] = out;
+  }
+  if (kL) {
+    const double vals[1] = {q_alpha};
+    block_partials_seq<1, kW>(vals, 1, red, p.partials + lb);
+  }
+}
+
+template <typename R, int MODE, int MAXS>
+hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
+  const DevBasis& db = *L.db;
+  constexpr int BLK = 1024;
+  ColArgs p;
+  p.dim_up = db.dim_up;
+  p.dim_dn = db.dim_dn;
+  p.j = L.j;
+  p.m_max = L.m_max;
+  p.up_tab = db.up_tab;
+  for (int s = 0; s < 64; ++s) {
+    const int c = db.up_slot_class[s];
+    const bool ok = s < db.up_nslots && L.coef;
+    p.slot_coef[2 * s] = ok ? L.coef[2 * c] : 0.0;
+    p.slot_coef[2 * s + 1] = ok ? L.coef[2 * c + 1] : 0.0;
+  }
+  p.x = L.x;
+  p.y = L.y;
+  p.xprev = L.xprev;
+  p.st = L.st;
+  p.ctl = L.ctl;
+  p.partials = L.partials;
+  const int grid = colpass_grid(db);
+  const size_t lds = colpass_lds_bytes(db, sizeof(R) == 8 ? 0 : 1);
+  auto fn = k_colpass<R, MODE, MAXS, BLK>;
+  static int max_dyn = -1;
+  if (max_dyn < 0) {
+    hipFuncAttributes fa{};
+    size_t stat = 0;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(fn)) == hipSuccess) stat = fa.sharedSizeBytes;
+    const int want = 160 * 1024 - static_cast<int>(stat);
+    max_dyn = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  want) == hipSuccess
+                  ? want
+                  : 64 * 1024 - static_cast<int>(stat);
+    (void)hipGetLastError();  // a refused opt-in is not a launch error
+  }
+  if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
+  if (pgrid) *pgrid = grid;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(BLK), lds, L.stream, p);
+  return hipGetLastError();
+}
+
+template <typename R, int MODE>
+hipError_t colpass_s(const ApplyLaunch& L, int* pgrid) {
+  switch (L.db->up_maxs_pad) {
+    case 4: return colpass_t<R, MODE, 4>(L, pgrid);
+    case 8: return colpass_t<R, MODE, 8>(L, pgrid);
+    case 12: return colpass_t<R, MODE, 12>(L, pgrid);
+    case 16: return colpass_t<R, MODE, 16>(L, pgrid);
+    case 20: return colpass_t<R, MODE, 20>(L, pgrid);
+    case 24: return colpass_t<R, MODE, 24>(L, pgrid);
+    case 32: return colpass_t<R, MODE, 32>(L, pgrid);
+    case 48: return colpass_t<R, MODE, 48>(L, pgrid);
+    case 64: return colpass_t<R, MODE, 64>(L, pgrid);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename R, int NV>
-hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds) {
+hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds, int* pgrid) {
+  if (pgrid) *pgrid = grid;
   if constexpr (NV == 1) {
-    if (L.db->dim_dn >= kRowsLong) {
+    const bool longrow = L.db->dim_dn >= kRowsLong;
+    if (apply_two_pass(*L.db, L.prec, 1, L.mode, L.obs)) {
+      hipError_t e;
+      if (L.mode == kPlain) {
+        e = longrow ? apply_s<R, 1, M_PLAIN, 1024, false>(L, grid, lds)
+                    : apply_s<R, 1, M_PLAIN, 256, false>(L, grid, lds);
+        return e != hipSuccess ? e : colpass_s<R, M_PLAIN>(L, pgrid);
+      }
+      e = longrow ? apply_s<R, 1, M_LANCZOS, 1024, false>(L, grid, lds)
+                  : apply_s<R, 1, M_LANCZOS, 256, false>(L, grid, lds);
+      return e != hipSuccess ? e : colpass_s<R, M_LANCZOS>(L, pgrid);
+    }
+    if (longrow) {
       if (L.mode == kPlain) return apply_s<R, 1, M_PLAIN, 1024>(L, grid, lds);
       if (L.mode != kObsOnly && !L.obs) return apply_s<R, 1, M_LANCZOS, 1024>(L, grid, lds);
     }
@@ -372,12 +536,12 @@ hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds) {
 }
 
 template <typename R>
-hipError_t apply_nv(const ApplyLaunch& L, int grid, size_t lds) {
+hipError_t apply_nv(const ApplyLaunch& L, int grid, size_t lds, int* pgrid) {
   switch (L.nv) {
-    case 1: return apply_mode<R, 1>(L, grid, lds);
-    case 2: return apply_mode<R, 2>(L, grid, lds);
-    case 4: return apply_mode<R, 4>(L, grid, lds);
-    case 8: return apply_mode<R, 8>(L, grid, lds);
+    case 1: return apply_mode<R, 1>(L, grid, lds, pgrid);
+    case 2: return apply_mode<R, 2>(L, grid, lds, pgrid);
+    case 4: return apply_mode<R, 4>(L, grid, lds, pgrid);
+    case 8: return apply_mode<R, 8>(L, grid, lds, pgrid);
     default: return hipErrorInvalidValue;
   }
 }

@@ -54,6 +54,11 @@ struct DevBasis {
   uint16_t* dn_tab = nullptr;    // [dim_dn][maxs_pad] staged-row index src + sign * (dim_dn + 1), pad dim_dn
   uint8_t slot_class[64] = {0};  // class of every down slot (uniform over strings)
   int nslots = 0, maxs_pad = 8;
+  // the same padded, class-sorted table for the up strings (column pass)
+  uint16_t* up_tab = nullptr;    // [dim_up][up_maxs_pad] index src + sign * (dim_up + 1), pad dim_up
+  uint8_t up_slot_class[64] = {0};
+  int up_nslots = 0, up_maxs_pad = 8;
+  int two_pass = -1;             // -1 automatic, 0 never, 1 whenever it fits
   int up_max_hops = 0, dn_max_hops = 0;
 };
 
@@ -87,8 +92,16 @@ struct ApplyLaunch {
 };
 
 // Each launcher returns the hipError_t of its launch.
+// grid_out: workgroups of the kernel that wrote the launch's partial sums.
 hipError_t launch_apply(const ApplyLaunch& L, int* grid_out = nullptr);
-int apply_grid(const DevBasis& db, int prec, int nv);    // workgroups of one apply launch
+int apply_grid(const DevBasis& db, int prec, int nv);    // most workgroups any apply kernel writes partials for
+// Two-pass apply (single vectors, plain and Lanczos modes): a row pass does
+// the diagonal and the down hops, a column pass stages kColW columns of x
+// for all up strings in LDS and adds the up hops (and the Lanczos epilogue).
+constexpr int kColW = 4;
+bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs);
+int colpass_grid(const DevBasis& db);
+size_t colpass_lds_bytes(const DevBasis& db, int prec);
 int apply_chunks(const DevBasis& db, int prec, int nv);  // column chunks per tile row
 int apply_nq(int mode, bool obs, int nc);
 size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows);

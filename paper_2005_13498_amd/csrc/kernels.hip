@@ -470,8 +470,8 @@ __global__ void k_first_final(const int64_t* partials, int nrows, int64_t n, int
 }  // namespace dev
 using namespace dev;
 
-hipError_t launch_apply_c128(const ApplyLaunch& L, int grid, size_t lds);
-hipError_t launch_apply_c64(const ApplyLaunch& L, int grid, size_t lds);
+hipError_t launch_apply_c128(const ApplyLaunch& L, int grid, size_t lds, int* pgrid);
+hipError_t launch_apply_c64(const ApplyLaunch& L, int grid, size_t lds, int* pgrid);
 
 int elem_grid(int64_t n) {
   // at most 256 workgroups: each Lanczos apply workgroup sums these partials
@@ -490,7 +490,24 @@ int apply_chunks(const DevBasis& db, int prec, int nv) {
   return 1;
 }
 
-int apply_grid(const DevBasis& db, int prec, int nv) { return db.dim_up * apply_chunks(db, prec, nv); }
+int colpass_grid(const DevBasis& db) { return (db.dim_dn + kColW - 1) / kColW; }
+
+size_t colpass_lds_bytes(const DevBasis& db, int prec) {
+  return 2 * (static_cast<size_t>(db.dim_up) + 1) * kColW * (prec == 0 ? 16 : 8);  // +x, -x, zero row
+}
+
+bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
+  if (nv != 1 || obs || !(mode == kPlain || mode == kLanczos) || db.two_pass == 0 || !db.up_tab) return false;
+  if (colpass_lds_bytes(db, prec) > 150 * 1024) return false;
+  if (db.two_pass == 1) return true;
+  // automatic: when a vector is larger than one XCD's L2 the up-hop row
+  // gathers of the one-pass kernel stream from the Infinity Cache
+  return static_cast<double>(db.dim) * (prec == 0 ? 16 : 8) >= 4.0 * 1024 * 1024;
+}
+
+int apply_grid(const DevBasis& db, int prec, int nv) {
+  return std::max(db.dim_up * apply_chunks(db, prec, nv), colpass_grid(db));
+}
 
 int apply_nq(int mode, bool obs, int nc) {
   const bool kL = mode == kLanczos;
@@ -506,10 +523,12 @@ size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows) {
 }
 
 hipError_t launch_apply(const ApplyLaunch& L, int* grid_out) {
-  const int grid = apply_grid(*L.db, L.prec, L.nv);
-  if (grid_out) *grid_out = grid;
+  const int grid = L.db->dim_up * apply_chunks(*L.db, L.prec, L.nv);
+  int pgrid = grid;
   const size_t lds = apply_lds_bytes(*L.db, L.prec, L.nv, L.rows);
-  return L.prec == 0 ? launch_apply_c128(L, grid, lds) : launch_apply_c64(L, grid, lds);
+  const hipError_t e = L.prec == 0 ? launch_apply_c128(L, grid, lds, &pgrid) : launch_apply_c64(L, grid, lds, &pgrid);
+  if (grid_out) *grid_out = pgrid;
+  return e;
 }
 
 #define HUB_NV_SWITCH(nv, CALL)                         \
