@@ -335,13 +335,15 @@ hub_status hub_controller_read_stats(hub_basis basis, hub_controller_stats *out)
 hub_status hub_set_apply_path(hub_basis basis, int32_t path);
 
 /* ------------------------------------------------------------------------ */
-/* Kernel timing of the matrix-free apply (for roofline reporting).  While
- * enabled, the library brackets with HIP events on the launch stream every
- * hub_apply_H launch and every Lanczos H*v launch of a propagation except the
- * first of each step that records observables (a different kernel).  hub_profile_read returns the number of timed launches, the
- * summed kernel time in ms, and the algorithmic bytes of one launch
- * (2 * nvec * dim * complex size: read x once, write y once) of the last
- * timed launch, then resets the counters.  Synchronises the device. */
+/* Kernel timing of the matrix-free apply (for roofline reporting).  on = 0
+ * disables it; on = k >= 1 attaches HIP start/end events to the kernel
+ * dispatches of every k-th eligible H*v: hub_apply_H launches and Lanczos
+ * H*v launches of a propagation except the first of each step, which also
+ * records observables (a different kernel).  A two-pass apply is timed as
+ * the sum of its two kernels.  hub_profile_read returns the number of timed
+ * launches, their summed kernel time in ms, and the algorithmic bytes of one
+ * launch (2 * nvec * dim * complex size: read x once, write y once) of the
+ * last timed launch, then resets the counters.  Synchronises the device. */
 hub_status hub_profile_enable(hub_basis basis, int32_t on);
 hub_status hub_profile_read(hub_basis basis, int64_t *launches, double *total_ms,
                             double *bytes_per_launch);

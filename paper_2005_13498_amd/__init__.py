@@ -339,8 +339,10 @@ def hub_pulse_A(pulse, t: float) -> float:
     return A.value
 
 
-def hub_profile_enable(h, on: bool) -> None:
-    _check(load_library().hub_profile_enable(ctypes.c_void_p(h), 1 if on else 0))
+def hub_profile_enable(h, on) -> None:
+    """False/0 off; True/1 time every eligible H*v; k > 1 every k-th."""
+    k = int(on) if not isinstance(on, bool) else (1 if on else 0)
+    _check(load_library().hub_profile_enable(ctypes.c_void_p(h), k))
 
 
 def hub_profile_read(h):

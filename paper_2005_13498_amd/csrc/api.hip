@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdlib>
@@ -85,7 +86,10 @@ struct hub_basis_s {
   hub_controller_stats cstats{};
   // profiling of the apply kernel
   bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  int prof_period = 1;
+  int64_t prof_count = 0;
+  std::vector<std::array<hipEvent_t, 4>> ev_used;  // per sampled apply; unused entries null
+  std::vector<hipEvent_t> ev_free;
   double prof_bytes = 0.0;
 };
 
@@ -227,29 +231,35 @@ hub_status check_common(hub_basis h, hub_prec prec, int32_t nvec) {
   return HUB_OK;
 }
 
-// Events bracket plain applies (hub_apply_H) and Lanczos-mode applies that do
-// not also accumulate observables, so a propagation's recorded average is
-// that of one kernel.
+// Timing events ride on the dispatches of plain applies (hub_apply_H) and of
+// Lanczos-mode applies that do not also accumulate observables (every
+// prof_period-th such apply): one start/end pair per kernel, so a sampled
+// apply's time is its kernel time (row plus column pass for two passes).
 hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid = nullptr) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  const bool timed = h->prof && (L.mode == hub::kPlain || (L.mode == hub::kLanczos && !L.obs));
-  if (timed) {
+  bool timed = h->prof && (L.mode == hub::kPlain || (L.mode == hub::kLanczos && !L.obs));
+  if (timed) timed = (h->prof_count++ % h->prof_period) == 0;
+  if (!timed) {
+    HUB_HIP(hub::launch_apply(L, grid));
+    return HUB_OK;
+  }
+  const bool two = hub::apply_two_pass(h->D, L.prec, L.nv, L.mode, L.obs);
+  std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < (two ? 4 : 2); ++k) {
     if (!h->ev_free.empty()) {
-      e0 = h->ev_free.back().first;
-      e1 = h->ev_free.back().second;
+      ev[k] = h->ev_free.back();
       h->ev_free.pop_back();
     } else {
-      HUB_HIP(hipEventCreate(&e0));
-      HUB_HIP(hipEventCreate(&e1));
+      HUB_HIP(hipEventCreate(&ev[k]));
     }
-    HUB_HIP(hipEventRecord(e0, L.stream));
   }
-  HUB_HIP(hub::launch_apply(L, grid));
-  if (timed) {
-    HUB_HIP(hipEventRecord(e1, L.stream));
-    h->ev_used.push_back({e0, e1});
-    h->prof_bytes = 2.0 * L.nv * static_cast<double>(h->D.dim) * (L.prec == 0 ? 16.0 : 8.0);
-  }
+  hub::ApplyLaunch T = L;
+  T.ev_start = ev[0];
+  T.ev_stop = ev[1];
+  T.ev2_start = ev[2];
+  T.ev2_stop = ev[3];
+  HUB_HIP(hub::launch_apply(T, grid));
+  h->ev_used.push_back(ev);
+  h->prof_bytes = 2.0 * L.nv * static_cast<double>(h->D.dim) * (L.prec == 0 ? 16.0 : 8.0);
   return HUB_OK;
 }
 
@@ -766,14 +776,10 @@ void hub_basis_destroy(hub_basis h) {
   if (h->ctrl_out) (void)hipFree(h->ctrl_out);
   if (h->ctrl_hfeat) (void)hipHostFree(h->ctrl_hfeat);
   if (h->ctrl_hout) (void)hipHostFree(h->ctrl_hout);
-  for (auto& e : h->ev_used) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
-  for (auto& e : h->ev_free) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
+  for (auto& e : h->ev_used)
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  for (hipEvent_t x : h->ev_free) (void)hipEventDestroy(x);
   delete h;
 }
 
@@ -1594,7 +1600,10 @@ hub_status hub_set_apply_path(hub_basis h, int32_t path) {
 // ---------------------------------------------------------------------------
 hub_status hub_profile_enable(hub_basis h, int32_t on) {
   if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (on < 0) return fail(HUB_E_INVALID, "on must be >= 0");
   h->prof = on != 0;
+  h->prof_period = on > 0 ? on : 1;
+  h->prof_count = 0;
   return HUB_OK;
 }
 
@@ -1604,10 +1613,14 @@ hub_status hub_profile_read(hub_basis h, int64_t* launches, double* total_ms, do
   HUB_HIP(hipDeviceSynchronize());
   double tot = 0.0;
   for (auto& e : h->ev_used) {
-    float ms = 0.0f;
-    HUB_HIP(hipEventElapsedTime(&ms, e.first, e.second));
-    tot += ms;
-    h->ev_free.push_back(e);
+    for (int k = 0; k < 4; k += 2) {
+      if (!e[k]) continue;
+      float ms = 0.0f;
+      HUB_HIP(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+      tot += ms;
+    }
+    for (hipEvent_t x : e)
+      if (x) h->ev_free.push_back(x);
   }
   if (launches) *launches = static_cast<int64_t>(h->ev_used.size());
   if (total_ms) *total_ms = tot;

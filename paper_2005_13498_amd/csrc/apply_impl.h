@@ -2,6 +2,8 @@
 // apply_c128.hip and apply_c64.hip.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "kernels_common.h"
 
 namespace hub {
@@ -282,6 +284,17 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)lb * nq * NV);
 }
 
+// Launch with optional timing events attached to the dispatch.
+template <typename K, typename A>
+hipError_t launch_ev(K fn, int grid, int blk, size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A& args) {
+  if (!e0 && !e1) {
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(blk), lds, st, args);
+    return hipGetLastError();
+  }
+  void* kargs[] = {&args};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(blk), kargs, lds, st, e0, e1, 0);
+}
+
 template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH>
 hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   const DevBasis& db = *L.db;
@@ -341,8 +354,7 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
     (void)hipGetLastError();  // a refused opt-in is not a launch error
   }
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(BLK), lds, L.stream, p);
-  return hipGetLastError();
+  return launch_ev(fn, grid, BLK, lds, L.stream, L.ev_start, L.ev_stop, p);
 }
 
 template <typename R, int NV, int MODE, int BLK, bool UPH = true>
@@ -488,8 +500,7 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   }
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
   if (pgrid) *pgrid = grid;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(BLK), lds, L.stream, p);
-  return hipGetLastError();
+  return launch_ev(fn, grid, BLK, lds, L.stream, L.ev2_start, L.ev2_stop, p);
 }
 
 template <typename R, int MODE>

@@ -89,6 +89,9 @@ struct ApplyLaunch {
   const double* prev_partials;  // Lanczos: |u_j|^2 (or |v|^2) partials [prev_nblk][nv]
   int prev_nblk;
   hipStream_t stream;
+  // optional timing events attached to the dispatches: start/end of the
+  // (first) kernel, and of the column pass when the apply has two kernels
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev2_start = nullptr, ev2_stop = nullptr;
 };
 
 // Each launcher returns the hipError_t of its launch.
