@@ -135,10 +135,12 @@ hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t b
   }
   // partial sums of an apply: grid * (1 + kObsQ) * nv doubles at most
   // (also the CGS inner-product partials: elem_grid * (kMMax + 1) * 2 * nv)
-  size_t pb = static_cast<size_t>(256) * (kMMax + 1) * 2 * kMaxNV * sizeof(double);
+  size_t pb = static_cast<size_t>(1024) * (kMMax + 1) * 2 * kMaxNV * sizeof(double);
   for (int pr = 0; pr < 2; ++pr)
     for (int nv = 1; nv <= kMaxNV; nv *= 2)
       pb = std::max(pb, static_cast<size_t>(hub::apply_grid(h->D, pr, nv)) * (1 + kObsQ) * nv * sizeof(double));
+  pb = std::max(pb, (2 * static_cast<size_t>(hub::colpass_grid(h->D)) +
+                     static_cast<size_t>(h->D.dim_up) * kObsQ) * sizeof(double));
   if (pb > h->partials_bytes) {
     if (h->partials) HUB_HIP(hipFree(h->partials));
     h->partials = nullptr;
@@ -364,12 +366,17 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.xprev = jj > 0 ? ptrs[jj - 1] : nullptr;
     A.coef = coef_mid.data() + static_cast<size_t>(n) * nv * 2 * nc;
     A.j = jj;
+    // a two-pass apply with observables leaves the row pass's partials after
+    // the column pass's
+    const bool two_obs = A.obs && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
+    if (two_obs) A.row_obs = h->partials + 2 * static_cast<size_t>(hub::colpass_grid(h->D));
     int agrid = 0;  // workgroups that wrote the apply's partial sums
     hub_status r = launch_apply_timed(h, A, &agrid);
     if (r != HUB_OK) return r;
     if (jj < o.m_max) {
       HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
-                                 hub::apply_nq(hub::kLanczos, A.obs, nc), h->partials_e, stream));
+                                 two_obs ? hub::apply_nq_two_pass(true) : hub::apply_nq(hub::kLanczos, A.obs, nc),
+                                 two_obs ? A.row_obs : nullptr, h->D.dim_up, h->partials_e, stream));
       if (o.reorth)  // CGS2: two Gram-Schmidt passes against u_0..u_j
         for (int pass = 0; pass < 2; ++pass)
           HUB_HIP(hub::launch_reorth(pi, nv, dim, h->slot_ptrs, jj, h->st, h->ctl, h->partials, h->rcoef,

@@ -336,7 +336,9 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.xprev = L.xprev;
   p.st = L.st;
   p.ctl = L.ctl;
-  p.partials = L.partials;
+  // the row pass of a two-pass apply with observables has its own partials
+  constexpr bool kObsMode = (MODE == M_LANCZOS_OBS || MODE == M_OBS);
+  p.partials = (!UPH && kObsMode) ? L.row_obs : L.partials;
   p.prev_partials = L.prev_partials;
   p.prev_nblk = L.prev_nblk;
   auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH>;
@@ -387,20 +389,22 @@ struct ColArgs {
   int dim_up, dim_dn, j, m_max;
   const uint16_t* up_tab;   // [dim_up][MAXS]
   double slot_coef[2 * 64]; // coefficient of every up slot (complex)
+  double slot_coef_obs[2 * 64];  // the same at the observation time (observables mode)
   const void* x;
   void* y;                  // in: row-pass partial product, out: result
   const void* xprev;
   const VecState* st;
   const StepCtl* ctl;
-  double* partials;         // Lanczos: alpha partials [grid]
+  double* partials;         // Lanczos: [grid][alpha (, Re <x|K_up(t_obs)|x>)]
 };
 
 template <typename R, int MODE, int MAXS, int BLK>
 __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   using V = typename CT<R>::T;
-  constexpr bool kL = MODE == M_LANCZOS;
+  constexpr bool kL = MODE == M_LANCZOS || MODE == M_LANCZOS_OBS;
+  constexpr bool kO = MODE == M_LANCZOS_OBS;
   constexpr int kW = BLK / 64;
-  __shared__ double red[kW];
+  __shared__ double red[2 * kW];
   R sj = 1, bprev = 0;
   if (kL) {
     if (p.ctl->all_done || p.j >= p.m_max) return;
@@ -427,7 +431,7 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   __syncthreads();
   const uint2* tab2 = reinterpret_cast<const uint2*>(p.up_tab);
   constexpr int kQ2 = MAXS / 4;
-  double q_alpha = 0.0;
+  double q_alpha = 0.0, q_hop = 0.0;
   for (int q = threadIdx.x; q < p.dim_up * kColW; q += BLK) {
     const int a = q / kColW, c = q % kColW;
     if (b0 + c >= p.dim_dn) continue;
@@ -438,6 +442,7 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
     V acc = y[o];
     V pv = V{0, 0};
     if (kL && p.j > 0) pv = static_cast<const V*>(p.xprev)[o];
+    double2 ko = make_double2(0.0, 0.0);  // up-hop part of K(t_obs) x (observables mode)
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
       const uint32_t w2 = (s & 3) < 2 ? ev[s >> 2].x : ev[s >> 2].y;
@@ -445,17 +450,22 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
       const V t = xs[idx * kColW + c];
       const V cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
       acc = cfma(cf, t, acc);
+      if (kO) ko = cfma(make_double2(p.slot_coef_obs[2 * s], p.slot_coef_obs[2 * s + 1]), make_double2(t.x, t.y), ko);
     }
     V out = acc;
     if (kL) {
       const V xv = xs[a * kColW + c];
+      if (kO) q_hop += (double)xv.x * ko.x + (double)xv.y * ko.y;
       out.x = out.x * sj - bprev * pv.x;
       out.y = out.y * sj - bprev * pv.y;
       q_alpha += (double)sj * ((double)xv.x * out.x + (double)xv.y * out.y);
     }
     y[o] = out;
   }
-  if (kL) {
+  if (kO) {
+    const double vals[2] = {q_alpha, q_hop};
+    block_partials_seq<1, kW>(vals, 2, red, p.partials + 2 * lb);
+  } else if (kL) {
     const double vals[1] = {q_alpha};
     block_partials_seq<1, kW>(vals, 1, red, p.partials + lb);
   }
@@ -476,6 +486,9 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
     const bool ok = s < db.up_nslots && L.coef;
     p.slot_coef[2 * s] = ok ? L.coef[2 * c] : 0.0;
     p.slot_coef[2 * s + 1] = ok ? L.coef[2 * c + 1] : 0.0;
+    const bool oko = s < db.up_nslots && L.coef_obs;
+    p.slot_coef_obs[2 * s] = oko ? L.coef_obs[2 * c] : 0.0;
+    p.slot_coef_obs[2 * s + 1] = oko ? L.coef_obs[2 * c + 1] : 0.0;
   }
   p.x = L.x;
   p.y = L.y;
@@ -530,6 +543,10 @@ hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds, int* pgrid) {
         e = longrow ? apply_s<R, 1, M_PLAIN, 1024, false>(L, grid, lds)
                     : apply_s<R, 1, M_PLAIN, 256, false>(L, grid, lds);
         return e != hipSuccess ? e : colpass_s<R, M_PLAIN>(L, pgrid);
+      }
+      if (L.obs) {  // observables of the step's first vector
+        e = apply_s<R, 1, M_LANCZOS_OBS, 256, false>(L, grid, lds);
+        return e != hipSuccess ? e : colpass_s<R, M_LANCZOS_OBS>(L, pgrid);
       }
       e = longrow ? apply_s<R, 1, M_LANCZOS, 1024, false>(L, grid, lds)
                   : apply_s<R, 1, M_LANCZOS, 256, false>(L, grid, lds);

@@ -92,6 +92,9 @@ struct ApplyLaunch {
   // optional timing events attached to the dispatches: start/end of the
   // (first) kernel, and of the column pass when the apply has two kernels
   hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev2_start = nullptr, ev2_stop = nullptr;
+  // two-pass Lanczos apply with observables: the row pass's obs partials
+  // [dim_up][kObsQ][nv] go here (the column pass writes alpha and the up-hop part)
+  double* row_obs = nullptr;
 };
 
 // Each launcher returns the hipError_t of its launch.
@@ -107,14 +110,17 @@ int colpass_grid(const DevBasis& db);
 size_t colpass_lds_bytes(const DevBasis& db, int prec);
 int apply_chunks(const DevBasis& db, int prec, int nv);  // column chunks per tile row
 int apply_nq(int mode, bool obs, int nc);
+// Partial columns the column pass of a two-pass Lanczos apply writes; with
+// observables the row pass writes its kObsQ columns to ApplyLaunch.row_obs.
+int apply_nq_two_pass(bool obs);
 size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows);
 int elem_grid(int64_t n);  // grid of the elementwise kernels (update, combine, norms)
 
 // u_{j+1} = w - alpha_j s_j u_j in place; alpha_j from the apply's partials;
 // |u_{j+1}|^2 partials [elem_grid][nv].
 hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, VecState* st, StepCtl* ctl, int j,
-                         const double* apply_partials, int apply_nblk, int apply_nq, double* partials,
-                         hipStream_t s);
+                         const double* apply_partials, int apply_nblk, int apply_nq, const double* row_obs,
+                         int row_nblk, double* partials, hipStream_t s);
 
 // One CGS pass of u_{j+1} (slot j+1) against v_k = s_k u_k, k <= j, with FP64
 // coefficients: dot partials [elem_grid][j+1][2][nv] in dot_partials, the

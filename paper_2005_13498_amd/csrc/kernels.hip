@@ -22,7 +22,8 @@ template <typename R, int NV>
 __global__ __launch_bounds__(kBlock) void k_update(int64_t n, typename CT<R>::T* w,
                                                    const typename CT<R>::T* uj, VecState* st,
                                                    StepCtl* ctl, int j, const double* apply_partials,
-                                                   int apply_nblk, int apply_nq, double* partials) {
+                                                   int apply_nblk, int apply_nq, const double* row_obs,
+                                                   int row_nblk, double* partials) {
   using V = typename CT<R>::T;
   __shared__ double red[kWaves * kMaxNV];
   __shared__ double sh_alpha[kMaxNV];
@@ -36,9 +37,19 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, typename CT<R>::T*
   __syncthreads();
   if (blockIdx.x == 0) {
     if (tid < NV && st[tid].status == 0) st[tid].alpha[j] = sh_alpha[tid];
-    for (int t = NV; t < qn; ++t) {  // observables of the step's first vector
-      const double s = reduce_column(apply_partials, apply_nblk, qn, t, red);
-      if (tid == 0) st[t % NV].obs[t / NV - 1] = s;
+    if (!row_obs) {
+      for (int t = NV; t < qn; ++t) {  // observables of the step's first vector
+        const double s = reduce_column(apply_partials, apply_nblk, qn, t, red);
+        if (tid == 0) st[t % NV].obs[t / NV - 1] = s;
+      }
+    } else {
+      // two-pass apply: [diag, docc, n2, down-hop part] from the row pass,
+      // the up-hop part of <x|K(t_obs)|x> in column 1 of the column pass
+      for (int t = 0; t < kObsQ * NV; ++t) {
+        double s = reduce_column(row_obs, row_nblk, kObsQ * NV, t, red);
+        if (t / NV == kObsQ - 1) s += reduce_column(apply_partials, apply_nblk, qn, NV + t % NV, red);
+        if (tid == 0) st[t % NV].obs[t / NV] = s;
+      }
     }
   }
   const int v = tid % NV;
@@ -474,9 +485,10 @@ hipError_t launch_apply_c128(const ApplyLaunch& L, int grid, size_t lds, int* pg
 hipError_t launch_apply_c64(const ApplyLaunch& L, int grid, size_t lds, int* pgrid);
 
 int elem_grid(int64_t n) {
-  // at most 256 workgroups: each Lanczos apply workgroup sums these partials
+  // four workgroups per CU at most (16 waves) for these memory-bound passes;
+  // every Lanczos apply workgroup sums the partials they leave
   const int64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
-  return static_cast<int>(g < 1 ? 1 : (g > 256 ? 256 : g));
+  return static_cast<int>(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }
 
 int apply_chunks(const DevBasis& db, int prec, int nv) {
@@ -497,7 +509,8 @@ size_t colpass_lds_bytes(const DevBasis& db, int prec) {
 }
 
 bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
-  if (nv != 1 || obs || !(mode == kPlain || mode == kLanczos) || db.two_pass == 0 || !db.up_tab) return false;
+  if (nv != 1 || !(mode == kPlain || mode == kLanczos) || db.two_pass == 0 || !db.up_tab) return false;
+  if (obs && mode != kLanczos) return false;
   if (colpass_lds_bytes(db, prec) > 150 * 1024) return false;
   if (db.two_pass == 1) return true;
   // automatic: when a vector is larger than one XCD's L2 the up-hop row
@@ -508,6 +521,8 @@ bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
 int apply_grid(const DevBasis& db, int prec, int nv) {
   return std::max(db.dim_up * apply_chunks(db, prec, nv), colpass_grid(db));
 }
+
+int apply_nq_two_pass(bool obs) { return obs ? 2 : 1; }  // column pass: alpha [, up-hop obs part]
 
 int apply_nq(int mode, bool obs, int nc) {
   const bool kL = mode == kLanczos;
@@ -568,17 +583,17 @@ hipError_t launch_reorth(int prec, int nv, int64_t n, void* const* slots_dev, in
 }
 
 hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, VecState* st, StepCtl* ctl, int j,
-                         const double* apply_partials, int apply_nblk, int apply_nq, double* partials,
-                         hipStream_t s) {
+                         const double* apply_partials, int apply_nblk, int apply_nq, const double* row_obs,
+                         int row_nblk, double* partials, hipStream_t s) {
   const int grid = elem_grid(n * nv);
   if (prec == 0) {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_update<double, NVC>), dim3(grid), dim3(kBlock), 0, s, n,
                                          static_cast<double2*>(w), static_cast<const double2*>(uj), st, ctl, j,
-                                         apply_partials, apply_nblk, apply_nq, partials));
+                                         apply_partials, apply_nblk, apply_nq, row_obs, row_nblk, partials));
   } else {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_update<float, NVC>), dim3(grid), dim3(kBlock), 0, s, n,
                                          static_cast<float2*>(w), static_cast<const float2*>(uj), st, ctl, j,
-                                         apply_partials, apply_nblk, apply_nq, partials));
+                                         apply_partials, apply_nblk, apply_nq, row_obs, row_nblk, partials));
   }
   return hipGetLastError();
 }
