@@ -29,10 +29,13 @@ if ROOT not in sys.path:
 
 METRIC = "H·v HBM GB/s + midpoint steps/s at 12 sites: mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-DOMINANT_KERNEL = "k_apply<double, 1, 1, "  # Lanczos-mode H*v, complex128, one vector
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_apply_lanczos_c128_cluster3x4_counters.txt")
+# Lanczos-mode H*v of the 12-site complex128 vector: the two kernels of the
+# two-pass apply (row pass without up hops, column pass), 20 padded hop slots
+DOMINANT_KERNELS = ("k_apply<double, 1, 1, 20, 256, false>", "k_colpass<double, 1, 20, 1024>")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "hv_lanczos_c128_cluster3x4_counters.txt")
 KERNEL_SOURCES = ("paper_2005_13498_amd/csrc/apply_impl.h", "paper_2005_13498_amd/csrc/kernels_common.h",
-                  "paper_2005_13498_amd/csrc/apply_c128.hip")
+                  "paper_2005_13498_amd/csrc/apply_c128.hip", "paper_2005_13498_amd/csrc/kernels.h",
+                  "paper_2005_13498_amd/csrc/kernels.hip")
 COPY_BYTES = 256 << 20  # calibration copy: bytes read (and written) per launch
 PROFILE_PERIOD = 8      # HIP events on every 8th H*v (events add idle time around a dispatch)
 
@@ -78,8 +81,10 @@ def _find(d, suffix):
 
 
 def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -> None:
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the dominant kernel and of
-    the calibration copy, scaled by the copy's known bytes, written as text."""
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the H*v kernels and of the
+    calibration copy, scaled by the copy's known bytes, written as text."""
+    import statistics
+
     def per_kernel(d, counter):
         vals = {}
         for r in _rows(_find(d, "counter_collection.csv")):
@@ -88,25 +93,30 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
             vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return vals
 
-    lines = [f"# HBM traffic of the Lanczos-mode H*v (complex128, 12-site 3x4, dim 853776)",
+    lines = ["# HBM traffic of one Lanczos-mode H*v (complex128, 12-site 3x4, dim 853776):",
+             "# the row pass and the column pass of the two-pass apply, per dispatch, summed",
              f"# command: {command}",
              "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by what it reads for a",
              f"# copy of {COPY_BYTES} bytes (torch elementwise neg, bench.py --copy-calibration)."]
     res = {}
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         v = per_kernel(d, counter)
-        dom = [k for k in v if DOMINANT_KERNEL in k]
         cp = [k for k in v if "neg_kernel" in k]
-        if not dom or not cp:
-            raise SystemExit(f"{counter}: dominant kernel or copy kernel missing: {sorted(v)[:8]}")
-        import statistics
-        kib = statistics.mean(v[dom[0]])
+        if not cp:
+            raise SystemExit(f"{counter}: copy kernel missing: {sorted(v)[:8]}")
         cpk = max(statistics.mean(v[k]) for k in cp)
         factor = COPY_BYTES / (cpk * 1024.0)
+        kib = 0.0
+        for want in DOMINANT_KERNELS:
+            hit = [k for k in v if want in k]
+            if not hit:
+                raise SystemExit(f"{counter}: kernel {want} missing: {sorted(v)[:8]}")
+            m = statistics.mean(v[hit[0]])
+            kib += m
+            lines += [f"{counter}_kernel: {hit[0]}", f"{counter}_dispatches: {len(v[hit[0]])}",
+                      f"{counter}_kib_per_dispatch: {m:.1f}"]
         res[name] = kib * 1024.0 * factor
-        lines += [f"{counter}_kernel: {dom[0]}", f"{counter}_dispatches: {len(v[dom[0]])}",
-                  f"{counter}_kib_per_dispatch: {kib:.1f}", f"{counter}_copy_kib_per_dispatch: {cpk:.1f}",
-                  f"{counter}_copy_scale: {factor:.4f}"]
+        lines += [f"{counter}_copy_kib_per_dispatch: {cpk:.1f}", f"{counter}_copy_scale: {factor:.4f}"]
     lines += [f"hbm_fetch_bytes_per_launch: {res['fetch']:.0f}", f"hbm_write_bytes_per_launch: {res['write']:.0f}",
               f"hbm_bytes_per_launch: {res['fetch'] + res['write']:.0f}",
               f"algorithmic_bytes_per_launch: {2 * 853776 * 16}",
@@ -116,7 +126,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
     print("\n".join(lines))
 
 
-def summarize_stats(trace_dir: str, out: str, command: str, top: int = 12) -> None:
+def summarize_stats(trace_dir: str, out: str, command: str, top: int = 16) -> None:
     """Top kernels of a --kernel-trace --stats run as text."""
     rows = _rows(_find(trace_dir, "kernel_stats.csv"))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
