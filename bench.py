@@ -29,10 +29,12 @@ if ROOT not in sys.path:
 
 METRIC = "H·v HBM GB/s + midpoint steps/s at 12 sites: mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-# Lanczos-mode H*v of the 12-site complex128 vector: the two kernels of the
-# two-pass apply (row pass without up hops, column pass), 20 padded hop slots
-DOMINANT_KERNELS = ("k_apply<double, 1, 1, 20, 256, false>", "k_colpass<double, 1, 20, 1024>")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "hv_lanczos_c128_cluster3x4_counters.txt")
+# Fused Lanczos iteration of the 12-site complex128 vector (update of u_j +
+# two-pass H*v + epilogue): row pass without up hops that also forms u_j, and
+# the column pass; 20 padded hop slots
+DOMINANT_KERNELS = ("k_apply<double, 1, 1, 20, 256, false, true>", "k_colpass<double, 1, 20, 1024, true>")
+UNIT_BYTES = 4 * 853776 * 16  # read w_{j-1}, u_{j-1}; write u_j, y
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "lanczos_iter_c128_cluster3x4_counters.txt")
 KERNEL_SOURCES = ("paper_2005_13498_amd/csrc/apply_impl.h", "paper_2005_13498_amd/csrc/kernels_common.h",
                   "paper_2005_13498_amd/csrc/apply_c128.hip", "paper_2005_13498_amd/csrc/kernels.h",
                   "paper_2005_13498_amd/csrc/kernels.hip")
@@ -93,8 +95,9 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
             vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return vals
 
-    lines = ["# HBM traffic of one Lanczos-mode H*v (complex128, 12-site 3x4, dim 853776):",
-             "# the row pass and the column pass of the two-pass apply, per dispatch, summed",
+    lines = ["# HBM traffic of one fused Lanczos iteration (complex128, 12-site 3x4, dim 853776):",
+             "# u_j = w_{j-1} - alpha s u_{j-1} and H u_j with the Lanczos epilogue, as the row pass",
+             "# and the column pass of the two-pass apply, per dispatch, summed",
              f"# command: {command}",
              "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by what it reads for a",
              f"# copy of {COPY_BYTES} bytes (torch elementwise neg, bench.py --copy-calibration)."]
@@ -119,7 +122,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
         lines += [f"{counter}_copy_kib_per_dispatch: {cpk:.1f}", f"{counter}_copy_scale: {factor:.4f}"]
     lines += [f"hbm_fetch_bytes_per_launch: {res['fetch']:.0f}", f"hbm_write_bytes_per_launch: {res['write']:.0f}",
               f"hbm_bytes_per_launch: {res['fetch'] + res['write']:.0f}",
-              f"algorithmic_bytes_per_launch: {2 * 853776 * 16}",
+              f"algorithmic_bytes_per_launch: {UNIT_BYTES}",
               f"kernel_source_sha256_16: {kernel_source_hash()}"]
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -377,10 +380,11 @@ def main() -> int:
                    "mean_krylov_m": mean_m},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "Lanczos-mode H*v, complex128: k_apply row pass + k_colpass (up hops, Lanczos epilogue)",
+                     "kernel": "fused Lanczos iteration, complex128: k_apply row pass (forms u_j, diagonal, down hops) "
+                               "+ k_colpass (up hops, Lanczos epilogue, Krylov decision)",
                      "bytes_per_launch": bytes_per, "avg_launch_us": avg_us,
                      "timed_launches": launches, "event_sampling": f"every {PROFILE_PERIOD}th H*v",
-                     "kernels": "two-pass: k_apply row pass + k_colpass (sum of both kernel times)"},
+                     "kernels": "sum of both kernel times; bytes = 4 N s (read w_{j-1}, u_{j-1}; write u_j, y)"},
     }
     if args.copy_calibration:
         a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)

@@ -339,11 +339,15 @@ hub_status hub_set_apply_path(hub_basis basis, int32_t path);
  * disables it; on = k >= 1 attaches HIP start/end events to the kernel
  * dispatches of every k-th eligible H*v: hub_apply_H launches and Lanczos
  * H*v launches of a propagation except the first of each step, which also
- * records observables (a different kernel).  A two-pass apply is timed as
- * the sum of its two kernels.  hub_profile_read returns the number of timed
- * launches, their summed kernel time in ms, and the algorithmic bytes of one
- * launch (2 * nvec * dim * complex size: read x once, write y once) of the
- * last timed launch, then resets the counters.  Synchronises the device. */
+ * records observables (a different kernel).  When a propagation runs the
+ * two-pass kernels without re-orthogonalisation, iterations j >= 2 fuse the
+ * Lanczos update into the row pass, and only those fused iterations are
+ * timed.  A two-pass apply is timed as the sum of its two kernels.
+ * hub_profile_read returns the number of timed launches, their summed kernel
+ * time in ms, and the algorithmic bytes of one timed launch (H*v: 2 * nvec *
+ * dim * complex size, read x once and write y once; fused iteration: 4 *
+ * nvec * dim * complex size, read w_{j-1} and u_{j-1}, write u_j and y), then
+ * resets the counters.  Synchronises the device. */
 hub_status hub_profile_enable(hub_basis basis, int32_t on);
 hub_status hub_profile_read(hub_basis basis, int64_t *launches, double *total_ms,
                             double *bytes_per_launch);

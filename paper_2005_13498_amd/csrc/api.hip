@@ -139,8 +139,9 @@ hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t b
   for (int pr = 0; pr < 2; ++pr)
     for (int nv = 1; nv <= kMaxNV; nv *= 2)
       pb = std::max(pb, static_cast<size_t>(hub::apply_grid(h->D, pr, nv)) * (1 + kObsQ) * nv * sizeof(double));
+  // two-pass regions: column-pass partials, row-pass obs partials, row norms
   pb = std::max(pb, (2 * static_cast<size_t>(hub::colpass_grid(h->D)) +
-                     static_cast<size_t>(h->D.dim_up) * kObsQ) * sizeof(double));
+                     static_cast<size_t>(h->D.dim_up) * (kObsQ + 1)) * sizeof(double));
   if (pb > h->partials_bytes) {
     if (h->partials) HUB_HIP(hipFree(h->partials));
     h->partials = nullptr;
@@ -237,8 +238,9 @@ hub_status check_common(hub_basis h, hub_prec prec, int32_t nvec) {
 // Lanczos-mode applies that do not also accumulate observables (every
 // prof_period-th such apply): one start/end pair per kernel, so a sampled
 // apply's time is its kernel time (row plus column pass for two passes).
-hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid = nullptr) {
-  bool timed = h->prof && (L.mode == hub::kPlain || (L.mode == hub::kLanczos && !L.obs));
+hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid = nullptr, bool fusing = false) {
+  // with fused iterations in the loop, only those (the dominant kernels) are timed
+  bool timed = h->prof && (L.mode == hub::kPlain || (L.mode == hub::kLanczos && !L.obs && (!fusing || L.fuse)));
   if (timed) timed = (h->prof_count++ % h->prof_period) == 0;
   if (!timed) {
     HUB_HIP(hub::launch_apply(L, grid));
@@ -261,7 +263,9 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid 
   T.ev2_stop = ev[3];
   HUB_HIP(hub::launch_apply(T, grid));
   h->ev_used.push_back(ev);
-  h->prof_bytes = 2.0 * L.nv * static_cast<double>(h->D.dim) * (L.prec == 0 ? 16.0 : 8.0);
+  // algorithmic bytes: H*v reads x, writes y; a fused iteration also reads
+  // w_{j-1} and u_{j-1} and writes u_j instead of reading x
+  h->prof_bytes = (L.fuse ? 4.0 : 2.0) * L.nv * static_cast<double>(h->D.dim) * (L.prec == 0 ? 16.0 : 8.0);
   return HUB_OK;
 }
 
@@ -369,11 +373,23 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     // a two-pass apply with observables leaves the row pass's partials after
     // the column pass's
     const bool two_obs = A.obs && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
-    if (two_obs) A.row_obs = h->partials + 2 * static_cast<size_t>(hub::colpass_grid(h->D));
+    const size_t cg2 = 2 * static_cast<size_t>(hub::colpass_grid(h->D));
+    if (two_obs) A.row_obs = h->partials + cg2;
+    // From the third iteration on, the two-pass row pass also finishes the
+    // previous update (u_j = w_{j-1} - alpha s u_{j-1}) and the column pass
+    // takes the decision, so no separate update kernel runs in between.
+    const bool fusable = !o.reorth && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, false);
+    A.fuse = fusable && jj >= 2;
+    if (A.fuse) {
+      A.alpha_partials = h->partials;
+      A.alpha_nblk = hub::colpass_grid(h->D);
+      A.norm_partials = h->partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ;
+    }
     int agrid = 0;  // workgroups that wrote the apply's partial sums
-    hub_status r = launch_apply_timed(h, A, &agrid);
+    hub_status r = launch_apply_timed(h, A, &agrid, fusable);
     if (r != HUB_OK) return r;
-    if (jj < o.m_max) {
+    const bool next_fused = fusable && jj + 1 >= 2;
+    if (jj < o.m_max && !next_fused) {
       HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
                                  two_obs ? hub::apply_nq_two_pass(true) : hub::apply_nq(hub::kLanczos, A.obs, nc),
                                  two_obs ? A.row_obs : nullptr, h->D.dim_up, h->partials_e, stream));

@@ -49,6 +49,9 @@ struct KArgs {  // passed by value as kernel arguments (at most 4 KB)
   double* partials;
   const double* prev_partials;
   int prev_nblk;
+  const double* alpha_partials;    // fused: the previous column pass's alpha partials
+  int alpha_nblk;
+  double* norm_out;                // fused: |u_j|^2 partial of every row
 };
 
 // Threads per apply workgroup.  Long rows of single vectors use 1024 threads
@@ -87,7 +90,7 @@ __device__ __forceinline__ void block_partials_seq(const double (&vals)[NQ], int
 // UPH = false: row pass of the two-pass apply (diagonal and down hops only;
 // in Lanczos mode the prologue still takes the Krylov decision, and the raw
 // partial product is written for the column pass to finish).
-template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH>
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE>
 __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   using V = typename CT<R>::T;
   constexpr int kBlockA = BLK;
@@ -110,19 +113,35 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   const int nc = p.nc;
 
   R sj = 1, bprev = 0;
-  if (kL) {
+  static_assert(!FUSE || (NV == 1 && MODE == M_LANCZOS && !UPH), "fused update: single-vector row pass");
+  R c_upd = 0;  // fused update: alpha_{j-1} s_{j-1}
+  if (FUSE) {
+    // Row pass of a fused iteration: finish u_j = w_{j-1} - alpha_{j-1} s_{j-1}
+    // u_{j-1} while staging; its norm, and so the Krylov decision for m = j,
+    // are taken by the column pass.
     if (p.ctl->all_done) return;
-    // norm of the vector just completed (|u_j|, j >= 1) or of the step input
-    for (int t = 0; t < NV; ++t) {
-      const double s = reduce_column<kWavesA>(p.prev_partials, p.prev_nblk, NV, t, red);
-      if (tid == 0) sh_beta[t] = sqrt(s);
+    const double al = reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, 1, 0, red);
+    if (blockIdx.x == 0 && tid == 0 && p.st[0].status == 0) p.st[0].alpha[p.j - 1] = al;
+    c_upd = static_cast<R>(al * p.st[0].scale[p.j - 1]);
+  } else if (kL) {
+    if (p.ctl->all_done) return;
+    // norm of the vector just completed (|u_j|, j >= 1) or of the step input;
+    // a row pass needs it only in the workgroup that takes the decision (the
+    // column pass reads the recorded value)
+    if (UPH || blockIdx.x == 0) {
+      for (int t = 0; t < NV; ++t) {
+        const double s = reduce_column<kWavesA>(p.prev_partials, p.prev_nblk, NV, t, red);
+        if (tid == 0) sh_beta[t] = sqrt(s);
+      }
+      __syncthreads();
+      if (blockIdx.x == 0) krylov_decide<NV, kWavesA>(p.j, sh_beta, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
     }
-    __syncthreads();
-    if (blockIdx.x == 0) krylov_decide<NV, kWavesA>(p.j, sh_beta, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
     if (p.j >= p.m_max) return;  // only the decision was needed
-    const double bv = sh_beta[v];
-    sj = static_cast<R>(bv > 0.0 ? 1.0 / bv : 0.0);
-    if (p.j > 0) bprev = static_cast<R>(bv * p.st[v].scale[p.j - 1]);
+    if (UPH) {
+      const double bv = sh_beta[v];
+      sj = static_cast<R>(bv > 0.0 ? 1.0 / bv : 0.0);
+      if (p.j > 0) bprev = static_cast<R>(bv * p.st[v].scale[p.j - 1]);
+    }
   }
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -165,7 +184,28 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   if (q < qend) load_column(q);
 
   // stage +x, -x (zero slot at column dim_dn of each copy)
-  {
+  if (FUSE) {
+    // x holds w_{j-1}: form the row of u_j in place, stage it, sum |u_j|^2
+    V* wr = static_cast<V*>(const_cast<void*>(p.x)) + (size_t)a * rowlen;
+    const V* ur = static_cast<const V*>(p.xprev) + (size_t)a * rowlen;
+    double n2 = 0.0;
+    for (int t = tid; t < half; t += kBlockA) {
+      V val = V{0, 0};
+      if (t < rowlen) {
+        const V u = ur[t];
+        val = wr[t];
+        val.x -= c_upd * u.x;
+        val.y -= c_upd * u.y;
+        wr[t] = val;
+        n2 += (double)val.x * val.x + (double)val.y * val.y;
+      }
+      xs[t] = val;
+      xs[half + t] = V{-val.x, -val.y};
+    }
+    const double rs = block_sum<kWavesA>(n2, red);
+    if (tid == 0) p.norm_out[lb] = rs;
+    if (!p.y) return;  // j = m_max: only the norm was needed
+  } else {
     const V* src = x + (size_t)a * rowlen;
     for (int t = tid; t < half; t += kBlockA) {
       const V val = (t < rowlen) ? src[t] : V{0, 0};
@@ -295,7 +335,7 @@ hipError_t launch_ev(K fn, int grid, int blk, size_t lds, hipStream_t st, hipEve
   return hipExtLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(blk), kargs, lds, st, e0, e1, 0);
 }
 
-template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH>
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE>
 hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   const DevBasis& db = *L.db;
   KArgs p;
@@ -341,7 +381,10 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.partials = (!UPH && kObsMode) ? L.row_obs : L.partials;
   p.prev_partials = L.prev_partials;
   p.prev_nblk = L.prev_nblk;
-  auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH>;
+  p.alpha_partials = L.alpha_partials;
+  p.alpha_nblk = L.alpha_nblk;
+  p.norm_out = L.norm_partials;
+  auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH, FUSE>;
   // dynamic LDS above the 64 KB default must be opted into (CU total 160 KB)
   static int max_dyn = -1;
   if (max_dyn < 0) {
@@ -359,18 +402,18 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   return launch_ev(fn, grid, BLK, lds, L.stream, L.ev_start, L.ev_stop, p);
 }
 
-template <typename R, int NV, int MODE, int BLK, bool UPH = true>
+template <typename R, int NV, int MODE, int BLK, bool UPH = true, bool FUSE = false>
 hipError_t apply_s(const ApplyLaunch& L, int grid, size_t lds) {
   switch (L.db->maxs_pad) {
-    case 4: return apply_t<R, NV, MODE, 4, BLK, UPH>(L, grid, lds);
-    case 8: return apply_t<R, NV, MODE, 8, BLK, UPH>(L, grid, lds);
-    case 12: return apply_t<R, NV, MODE, 12, BLK, UPH>(L, grid, lds);
-    case 16: return apply_t<R, NV, MODE, 16, BLK, UPH>(L, grid, lds);
-    case 20: return apply_t<R, NV, MODE, 20, BLK, UPH>(L, grid, lds);
-    case 24: return apply_t<R, NV, MODE, 24, BLK, UPH>(L, grid, lds);
-    case 32: return apply_t<R, NV, MODE, 32, BLK, UPH>(L, grid, lds);
-    case 48: return apply_t<R, NV, MODE, 48, BLK, UPH>(L, grid, lds);
-    case 64: return apply_t<R, NV, MODE, 64, BLK, UPH>(L, grid, lds);
+    case 4: return apply_t<R, NV, MODE, 4, BLK, UPH, FUSE>(L, grid, lds);
+    case 8: return apply_t<R, NV, MODE, 8, BLK, UPH, FUSE>(L, grid, lds);
+    case 12: return apply_t<R, NV, MODE, 12, BLK, UPH, FUSE>(L, grid, lds);
+    case 16: return apply_t<R, NV, MODE, 16, BLK, UPH, FUSE>(L, grid, lds);
+    case 20: return apply_t<R, NV, MODE, 20, BLK, UPH, FUSE>(L, grid, lds);
+    case 24: return apply_t<R, NV, MODE, 24, BLK, UPH, FUSE>(L, grid, lds);
+    case 32: return apply_t<R, NV, MODE, 32, BLK, UPH, FUSE>(L, grid, lds);
+    case 48: return apply_t<R, NV, MODE, 48, BLK, UPH, FUSE>(L, grid, lds);
+    case 64: return apply_t<R, NV, MODE, 64, BLK, UPH, FUSE>(L, grid, lds);
     default: return hipErrorInvalidValue;
   }
 }
@@ -387,36 +430,57 @@ hipError_t apply_s(const ApplyLaunch& L, int grid, size_t lds) {
 // pass instead of once per up hop.
 struct ColArgs {
   int dim_up, dim_dn, j, m_max;
+  const double* norm_partials;  // fused: |u_j|^2 per row [dim_up]
+  double tol, norm_inf;
   const uint16_t* up_tab;   // [dim_up][MAXS]
   double slot_coef[2 * 64]; // coefficient of every up slot (complex)
   double slot_coef_obs[2 * 64];  // the same at the observation time (observables mode)
   const void* x;
   void* y;                  // in: row-pass partial product, out: result
   const void* xprev;
-  const VecState* st;
-  const StepCtl* ctl;
+  VecState* st;
+  StepCtl* ctl;
   double* partials;         // Lanczos: [grid][alpha (, Re <x|K_up(t_obs)|x>)]
 };
 
-template <typename R, int MODE, int MAXS, int BLK>
+// FUSE: the row pass formed u_j; reduce its norm here and take the decision.
+template <typename R, int MODE, int MAXS, int BLK, bool FUSE>
 __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   using V = typename CT<R>::T;
   constexpr bool kL = MODE == M_LANCZOS || MODE == M_LANCZOS_OBS;
   constexpr bool kO = MODE == M_LANCZOS_OBS;
   constexpr int kW = BLK / 64;
   __shared__ double red[2 * kW];
+  __shared__ double sh_b[1];
   R sj = 1, bprev = 0;
   if (kL) {
-    if (p.ctl->all_done || p.j >= p.m_max) return;
-    // |u_j| as recorded by the row pass's decision (beta0 at j = 0)
-    const VecState& S = p.st[0];
-    const double bv = p.j == 0 ? S.beta0 : S.beta[p.j - 1];
+    if (p.ctl->all_done) return;
+    double bv;
+    if (FUSE) {
+      // |u_j| from the row pass's partials.  An extra last workgroup takes
+      // the decision for m = j alongside the column blocks (a single round of
+      // workgroups: the decision would otherwise add to the kernel's time).
+      const double s2 = reduce_column<kW>(p.norm_partials, p.dim_up, 1, 0, red);
+      bv = sqrt(s2);
+      if (blockIdx.x == gridDim.x - 1) {
+        if (threadIdx.x == 0) sh_b[0] = bv;
+        __syncthreads();
+        krylov_decide<1, kW>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+        return;
+      }
+    } else {
+      // |u_j| as recorded by the row pass's decision (beta0 at j = 0)
+      const VecState& S = p.st[0];
+      bv = p.j == 0 ? S.beta0 : S.beta[p.j - 1];
+    }
+    if (p.j >= p.m_max) return;
     sj = static_cast<R>(bv > 0.0 ? 1.0 / bv : 0.0);
-    if (p.j > 0) bprev = static_cast<R>(bv * S.scale[p.j - 1]);
+    if (p.j > 0) bprev = static_cast<R>(bv * p.st[0].scale[p.j - 1]);
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* xs = reinterpret_cast<V*>(smem_raw);
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int nwork = FUSE ? gridDim.x - 1 : gridDim.x;  // column blocks
+  const int lb = xcd_remap(blockIdx.x, nwork);
   const int b0 = lb * kColW;
   const V* __restrict__ x = static_cast<const V*>(p.x);
   V* __restrict__ y = static_cast<V*>(p.y);
@@ -471,7 +535,7 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   }
 }
 
-template <typename R, int MODE, int MAXS>
+template <typename R, int MODE, int MAXS, bool FUSE>
 hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   const DevBasis& db = *L.db;
   constexpr int BLK = 1024;
@@ -480,6 +544,9 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   p.dim_dn = db.dim_dn;
   p.j = L.j;
   p.m_max = L.m_max;
+  p.norm_partials = L.norm_partials;
+  p.tol = L.tol;
+  p.norm_inf = L.norm_inf;
   p.up_tab = db.up_tab;
   for (int s = 0; s < 64; ++s) {
     const int c = db.up_slot_class[s];
@@ -498,7 +565,7 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   p.partials = L.partials;
   const int grid = colpass_grid(db);
   const size_t lds = colpass_lds_bytes(db, sizeof(R) == 8 ? 0 : 1);
-  auto fn = k_colpass<R, MODE, MAXS, BLK>;
+  auto fn = k_colpass<R, MODE, MAXS, BLK, FUSE>;
   static int max_dyn = -1;
   if (max_dyn < 0) {
     hipFuncAttributes fa{};
@@ -513,21 +580,22 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   }
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
   if (pgrid) *pgrid = grid;
-  return launch_ev(fn, grid, BLK, lds, L.stream, L.ev2_start, L.ev2_stop, p);
+  // fused: one more workgroup for the Krylov decision
+  return launch_ev(fn, FUSE ? grid + 1 : grid, BLK, lds, L.stream, L.ev2_start, L.ev2_stop, p);
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, bool FUSE = false>
 hipError_t colpass_s(const ApplyLaunch& L, int* pgrid) {
   switch (L.db->up_maxs_pad) {
-    case 4: return colpass_t<R, MODE, 4>(L, pgrid);
-    case 8: return colpass_t<R, MODE, 8>(L, pgrid);
-    case 12: return colpass_t<R, MODE, 12>(L, pgrid);
-    case 16: return colpass_t<R, MODE, 16>(L, pgrid);
-    case 20: return colpass_t<R, MODE, 20>(L, pgrid);
-    case 24: return colpass_t<R, MODE, 24>(L, pgrid);
-    case 32: return colpass_t<R, MODE, 32>(L, pgrid);
-    case 48: return colpass_t<R, MODE, 48>(L, pgrid);
-    case 64: return colpass_t<R, MODE, 64>(L, pgrid);
+    case 4: return colpass_t<R, MODE, 4, FUSE>(L, pgrid);
+    case 8: return colpass_t<R, MODE, 8, FUSE>(L, pgrid);
+    case 12: return colpass_t<R, MODE, 12, FUSE>(L, pgrid);
+    case 16: return colpass_t<R, MODE, 16, FUSE>(L, pgrid);
+    case 20: return colpass_t<R, MODE, 20, FUSE>(L, pgrid);
+    case 24: return colpass_t<R, MODE, 24, FUSE>(L, pgrid);
+    case 32: return colpass_t<R, MODE, 32, FUSE>(L, pgrid);
+    case 48: return colpass_t<R, MODE, 48, FUSE>(L, pgrid);
+    case 64: return colpass_t<R, MODE, 64, FUSE>(L, pgrid);
     default: return hipErrorInvalidValue;
   }
 }
@@ -547,6 +615,11 @@ hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds, int* pgrid) {
       if (L.obs) {  // observables of the step's first vector
         e = apply_s<R, 1, M_LANCZOS_OBS, 256, false>(L, grid, lds);
         return e != hipSuccess ? e : colpass_s<R, M_LANCZOS_OBS>(L, pgrid);
+      }
+      if (L.fuse) {
+        e = longrow ? apply_s<R, 1, M_LANCZOS, 1024, false, true>(L, grid, lds)
+                    : apply_s<R, 1, M_LANCZOS, 256, false, true>(L, grid, lds);
+        return e != hipSuccess ? e : colpass_s<R, M_LANCZOS, true>(L, pgrid);
       }
       e = longrow ? apply_s<R, 1, M_LANCZOS, 1024, false>(L, grid, lds)
                   : apply_s<R, 1, M_LANCZOS, 256, false>(L, grid, lds);

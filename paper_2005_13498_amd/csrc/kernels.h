@@ -95,6 +95,13 @@ struct ApplyLaunch {
   // two-pass Lanczos apply with observables: the row pass's obs partials
   // [dim_up][kObsQ][nv] go here (the column pass writes alpha and the up-hop part)
   double* row_obs = nullptr;
+  // two-pass Lanczos iteration j >= 2 with the update of u_j fused into the
+  // row pass: alpha_{j-1} from the previous column pass's partials, |u_j|^2
+  // partials [dim_up] to norm_partials, the Krylov decision in the column pass
+  bool fuse = false;
+  const double* alpha_partials = nullptr;
+  int alpha_nblk = 0;
+  double* norm_partials = nullptr;
 };
 
 // Each launcher returns the hipError_t of its launch.

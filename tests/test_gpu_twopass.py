@@ -140,3 +140,26 @@ def test_cluster3x4_two_pass_steps(dtype, tol):
         assert torch.equal(ys[0], ys[1])
     finally:
         B.close()
+
+
+@pytest.mark.parametrize("m_max", [2, 3, 5])
+def test_two_pass_stops_at_m_max_like_one_pass(m_max):
+    """The decision-only launch at j = m_max (fused from j = 2 on) stops the
+    step exactly as the one-pass kernels do."""
+    lat = ring(8)
+    B = hub.Basis(lat, 8.0, 4, 4, device=0)
+    try:
+        x0 = _to_dev(random_state(B.dim, seed=44)[0])
+        res = {}
+        for path in (0, 1):
+            hub.hub_set_apply_path(B.handle, path)
+            x = x0.clone()
+            st, info = hub.hub_krylov_expm_step(B.handle, [0.3], 0.2, hub.make_opts(tol=1e-15, m_max=m_max), x,
+                                                allow_not_converged=True)
+            res[path] = (st, info, x.cpu().numpy())
+        assert res[0][0] == res[1][0] == hub.HUB_E_NOT_CONVERGED
+        assert res[0][1][0, 0] == res[1][1][0, 0] == m_max
+        assert _rel(res[1][2], res[0][2]) < 1e-12
+    finally:
+        B.close()
+
