@@ -375,20 +375,25 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     const bool two_obs = A.obs && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
     const size_t cg2 = 2 * static_cast<size_t>(hub::colpass_grid(h->D));
     if (two_obs) A.row_obs = h->partials + cg2;
-    // From the third iteration on, the two-pass row pass also finishes the
+    // From the second iteration on, the two-pass row pass also finishes the
     // previous update (u_j = w_{j-1} - alpha s u_{j-1}) and the column pass
-    // takes the decision, so no separate update kernel runs in between.
+    // takes the decision, so no separate update kernel runs in between
+    // (at j = 1 the row pass also finalizes the first apply's observables).
     const bool fusable = !o.reorth && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, false);
-    A.fuse = fusable && jj >= 2;
+    A.fuse = fusable && jj >= 1;
     if (A.fuse) {
+      const bool after_obs = jj == 1 && want_obs && sub == 0 &&
+                             hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
       A.alpha_partials = h->partials;
       A.alpha_nblk = hub::colpass_grid(h->D);
+      A.alpha_stride = after_obs ? hub::apply_nq_two_pass(true) : 1;
+      A.obs_row = after_obs ? h->partials + cg2 : nullptr;
       A.norm_partials = h->partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ;
     }
     int agrid = 0;  // workgroups that wrote the apply's partial sums
     hub_status r = launch_apply_timed(h, A, &agrid, fusable);
     if (r != HUB_OK) return r;
-    const bool next_fused = fusable && jj + 1 >= 2;
+    const bool next_fused = fusable;  // every later iteration finishes this update itself
     if (jj < o.m_max && !next_fused) {
       HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
                                  two_obs ? hub::apply_nq_two_pass(true) : hub::apply_nq(hub::kLanczos, A.obs, nc),

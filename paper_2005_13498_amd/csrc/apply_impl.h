@@ -50,7 +50,9 @@ struct KArgs {  // passed by value as kernel arguments (at most 4 KB)
   const double* prev_partials;
   int prev_nblk;
   const double* alpha_partials;    // fused: the previous column pass's alpha partials
-  int alpha_nblk;
+  int alpha_nblk, alpha_stride;
+  const double* obs_row;           // fused j = 1: observables partials of the step's first apply
+  int dim_up_rows;
   double* norm_out;                // fused: |u_j|^2 partial of every row
 };
 
@@ -120,8 +122,17 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     // u_{j-1} while staging; its norm, and so the Krylov decision for m = j,
     // are taken by the column pass.
     if (p.ctl->all_done) return;
-    const double al = reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, 1, 0, red);
+    const double al = reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, p.alpha_stride, 0, red);
     if (blockIdx.x == 0 && tid == 0 && p.st[0].status == 0) p.st[0].alpha[p.j - 1] = al;
+    if (blockIdx.x == 0 && p.obs_row) {
+      // observables of the step's first vector: [diag, docc, n2, down-hop
+      // part] from its row pass plus the up-hop part from its column pass
+      for (int t = 0; t < kObsQ; ++t) {
+        double s2 = reduce_column<kWavesA>(p.obs_row, p.dim_up_rows, kObsQ, t, red);
+        if (t == kObsQ - 1) s2 += reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, p.alpha_stride, 1, red);
+        if (tid == 0) p.st[0].obs[t] = s2;
+      }
+    }
     c_upd = static_cast<R>(al * p.st[0].scale[p.j - 1]);
   } else if (kL) {
     if (p.ctl->all_done) return;
@@ -383,6 +394,9 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.prev_nblk = L.prev_nblk;
   p.alpha_partials = L.alpha_partials;
   p.alpha_nblk = L.alpha_nblk;
+  p.alpha_stride = L.alpha_stride;
+  p.obs_row = L.obs_row;
+  p.dim_up_rows = db.dim_up;
   p.norm_out = L.norm_partials;
   auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH, FUSE>;
   // dynamic LDS above the 64 KB default must be opted into (CU total 160 KB)

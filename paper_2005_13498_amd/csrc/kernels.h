@@ -101,6 +101,8 @@ struct ApplyLaunch {
   bool fuse = false;
   const double* alpha_partials = nullptr;
   int alpha_nblk = 0;
+  int alpha_stride = 1;             // columns of alpha_partials (2 after an observables apply)
+  const double* obs_row = nullptr;  // fused j = 1 after an observables apply: its row-pass obs partials
   double* norm_partials = nullptr;
 };
 
