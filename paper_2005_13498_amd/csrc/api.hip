@@ -271,10 +271,13 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid 
 
 // Group sizes for nvec vectors: powers of two up to 8 whose staged row keeps
 // at least three apply workgroups per CU (<= 48 KB of the 160 KB LDS), or one
-// vector per group.
+// vector per group; single vectors where the two-pass kernels apply.
 std::vector<int> groups_for(hub_basis h, int nvec, int prec) {
   int gmax = kMaxNV;
   while (gmax > 1 && hub::apply_lds_bytes(h->D, prec, gmax, 1) > 48 * 1024) gmax /= 2;
+  // single vectors run the two-pass kernels with fused updates, which beat
+  // interleaved one-pass blocks whenever they apply
+  if (hub::apply_two_pass(h->D, prec, 1, hub::kLanczos, false)) gmax = 1;
   std::vector<int> g;
   int left = nvec;
   while (left > 0) {
