@@ -236,6 +236,21 @@ hub_status hub_greens_diag(hub_basis basis, int32_t n_targets, const hub_basis *
                            const hub_greens_member *members, void *psi_inout, double *overlaps,
                            void *stream);
 
+/* Broadened spectral functions, Eq. (A_noneq_broad), from the overlaps of
+ * hub_greens_diag on the stepper grid s_k = k dt, k < n_s:
+ *     A(nu) = (1/pi) Re sum_k w_k e^{-eps s_k} e^{i nu s_k} z_k,
+ * w_k the trapezoidal weights of [0, (n_s - 1) dt], z = conj(o) for a removal
+ * member (lesser[m] = 1, o from c: A<(nu, t'), the lesser function G<(t'+s,
+ * t') = -conj G<(t', t'+s) transformed) and z = o for an addition member
+ * (lesser[m] = 0, o from c^dag: A>(nu, t')).  In equilibrium this is the
+ * Lorentzian Lehmann form of Eq. (spectralplot) divided by pi, removal peaks
+ * at E0 - E_phi and addition peaks at E_phi - E0.  overlaps [n_members][n_s]
+ * complex (double pairs), nu [n_nu] and out [n_members][n_nu] are device
+ * pointers on `device`; lesser [n_members] is a host array.  Asynchronous. */
+hub_status hub_spectral(int32_t device, int32_t n_members, int32_t n_s, const double *overlaps,
+                        const int32_t *lesser, double dt, double eps, int32_t n_nu, const double *nu,
+                        double *out, void *stream);
+
 /* Value of the pulse's A(t) (host arithmetic, as used by hub_propagate). */
 hub_status hub_pulse_A(const hub_pulse *pulse, double t, double *A);
 

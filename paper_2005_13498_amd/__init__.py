@@ -40,7 +40,7 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_profile_read", "hub_apply_cop", "hub_dot", "hub_greens_diag",
            "hub_mlp_forward", "hub_mlp_workspace_bytes", "hub_mlp_train_step", "hub_controller_features",
            "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats",
-           "hub_set_apply_path")
+           "hub_set_apply_path", "hub_spectral")
 
 # Controller MLP sizes (HUB_MLP_* in hub.h).
 MLP_IN, MLP_HID, MLP_OUT = 8, 64, 2
@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_controller_enable": ([vp, i32, i32, i32], i32),
         "hub_controller_read_stats": ([vp, P(hub_controller_stats)], i32),
         "hub_set_apply_path": ([vp, i32], i32),
+        "hub_spectral": ([i32, i32, i32, vp, P(i32), dbl, dbl, i32, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -438,6 +439,16 @@ def hub_controller_read_stats(h) -> dict:
     s = hub_controller_stats()
     _check(load_library().hub_controller_read_stats(ctypes.c_void_p(h), ctypes.byref(s)))
     return {k: getattr(s, k) for k, _ in hub_controller_stats._fields_}
+
+
+def hub_spectral(overlaps, lesser, dt: float, eps: float, nu, out, stream=None) -> None:
+    """A[m, f] from overlaps [n_members, n_s] (complex128 device tensor), nu
+    [n_nu] and out [n_members, n_nu] (float64 device tensors); lesser: host
+    sequence of flags (1 removal / c, 0 addition / c^dag)."""
+    nm, ns = int(overlaps.shape[0]), int(overlaps.shape[1])
+    flags = (ctypes.c_int32 * max(1, nm))(*[int(bool(x)) for x in lesser])
+    _check(load_library().hub_spectral(_device_of(overlaps), nm, ns, _dptr(overlaps), flags, float(dt), float(eps),
+                                       int(nu.shape[0]), _dptr(nu), _dptr(out), _stream_ptr(stream)))
 
 
 def hub_set_apply_path(h, path: int) -> None:

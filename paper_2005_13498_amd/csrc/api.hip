@@ -1621,6 +1621,19 @@ hub_status hub_controller_read_stats(hub_basis h, hub_controller_stats* out) {
   return HUB_OK;
 }
 
+hub_status hub_spectral(int32_t device, int32_t n_members, int32_t n_s, const double* overlaps, const int32_t* lesser,
+                        double dt, double eps, int32_t n_nu, const double* nu, double* out, void* stream) {
+  if (n_members < 0 || n_s < 0 || n_nu < 0) return fail(HUB_E_INVALID, "negative size");
+  if (n_members == 0 || n_nu == 0) return HUB_OK;
+  if (!overlaps || !lesser || !nu || !out) return fail(HUB_E_INVALID, "null argument");
+  if (!std::isfinite(dt) || !(dt > 0.0) || !std::isfinite(eps) || eps < 0.0)
+    return fail(HUB_E_INVALID, "dt must be > 0 and eps >= 0, both finite");
+  HUB_HIP(hipSetDevice(device));
+  HUB_HIP(hub::launch_spectral(n_members, n_s, overlaps, lesser, dt, eps, n_nu, nu, out,
+                               static_cast<hipStream_t>(stream)));
+  return HUB_OK;
+}
+
 hub_status hub_set_apply_path(hub_basis h, int32_t path) {
   if (!h) return fail(HUB_E_INVALID, "null basis handle");
   if (path < -1 || path > 1) return fail(HUB_E_INVALID, "path must be -1, 0 or 1");

@@ -138,6 +138,11 @@ hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, V
 hipError_t launch_reorth(int prec, int nv, int64_t n, void* const* slots_dev, int j, const VecState* st,
                          const StepCtl* ctl, double* dot_partials, double* coef, double* norm_partials,
                          hipStream_t s);
+// Broadened spectral functions of n_members overlap series [n_members][n_s]
+// (complex, device) on the frequencies nu [n_nu] (device) into out
+// [n_members][n_nu] (device); lesser[m] (host) selects conj(o) for removal.
+hipError_t launch_spectral(int n_members, int n_s, const void* overlaps, const int32_t* lesser, double dt, double eps,
+                           int n_nu, const double* nu, double* out, hipStream_t s);
 // v = beta0 sum_k y_k s_k u_k over the m_v vectors of each vector v (in place
 // into slot 0), and |v|^2 partials [elem_grid][nv].  If some vector is still
 // undecided the step is abandoned: ctl->abort is set and slot 0 is kept.

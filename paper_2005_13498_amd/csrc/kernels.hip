@@ -378,6 +378,32 @@ __global__ __launch_bounds__(kBlock) void k_reorth_axpy(int64_t n, void* const* 
   block_partials<NV>(&n2, 1, red, partials + (size_t)blockIdx.x * NV);
 }
 
+// ------------------- broadened spectral functions ---------------------------
+// A(nu) = (1/pi) Re sum_k w_k e^{-eps s_k} e^{i nu s_k} z_k on s_k = k dt with
+// trapezoidal weights, z = conj(o) for removal (lesser) members and z = o for
+// addition (greater) members; one thread per (member, frequency), FP64.
+__global__ __launch_bounds__(kBlock) void k_spectral(int n_s, const double2* __restrict__ o,
+                                                     unsigned long long lesser_mask, double dt, double eps,
+                                                     int n_nu, const double* __restrict__ nu,
+                                                     double* __restrict__ out) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  const int m = blockIdx.y;
+  if (f >= n_nu) return;
+  const double w = nu[f];
+  const double cj = ((lesser_mask >> m) & 1ull) ? -1.0 : 1.0;
+  const double2* om = o + (size_t)m * n_s;
+  double acc = 0.0;
+  for (int k = 0; k < n_s; ++k) {
+    const double s = k * dt;
+    const double wt = (k == 0 || k == n_s - 1) ? 0.5 * dt : dt;
+    double sn, cs;
+    sincos(w * s, &sn, &cs);
+    const double2 z = om[k];
+    acc += wt * exp(-eps * s) * (cs * z.x - sn * (cj * z.y));
+  }
+  out[(size_t)m * n_nu + f] = n_s > 1 ? acc / M_PI : 0.0;
+}
+
 // ------------------------------- BLAS-1 ------------------------------------
 __global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, const double2* const* vecs, int kv,
                                                      const double2* w, double* partials) {
@@ -580,6 +606,23 @@ hipError_t launch_reorth(int prec, int nv, int64_t n, void* const* slots_dev, in
                                          slots_dev, j, coef, ctl, norm_partials));
   }
   return hipGetLastError();
+}
+
+hipError_t launch_spectral(int n_members, int n_s, const void* overlaps, const int32_t* lesser, double dt, double eps,
+                           int n_nu, const double* nu, double* out, hipStream_t s) {
+  for (int m0 = 0; m0 < n_members; m0 += 64) {
+    const int mc = std::min(64, n_members - m0);
+    unsigned long long mask = 0;
+    for (int k = 0; k < mc; ++k)
+      if (lesser[m0 + k]) mask |= 1ull << k;
+    const dim3 grid((n_nu + kBlock - 1) / kBlock, mc);
+    hipLaunchKernelGGL(k_spectral, grid, dim3(kBlock), 0, s, n_s,
+                       static_cast<const double2*>(overlaps) + static_cast<size_t>(m0) * n_s, mask, dt, eps, n_nu,
+                       nu, out + static_cast<size_t>(m0) * n_nu);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, VecState* st, StepCtl* ctl, int j,
