@@ -93,6 +93,11 @@ typedef struct {
   int32_t reorth;
   int32_t substeps;
   int32_t m_hint;
+  int32_t scheme;  /* hub_propagate only: 0 = exponential midpoint rule (Eq. (time-stepping));
+                      1 = fourth-order commutator-free exponential: per step
+                      exp(-i dt (a1 H1 + a2 H2)) exp(-i dt (a2 H1 + a1 H2)), H_k = H(t + c_k dt),
+                      c = 1/2 -+ sqrt(3)/6, a = (3 -+ 2 sqrt(3))/12, each factor a Krylov
+                      step of length dt/2 (and split into `substeps`) */
 } hub_krylov_opts;
 
 /* Per step (per vector) report. err_est = last a-posteriori estimate eps. */
@@ -268,7 +273,8 @@ const char *hub_last_error(void);
  * for step n, whose history ends at step h <= n - 1 (the last step finished
  * when the chunk was planned):
  *     x[0] = A(t_mid_n)            x[1] = A'(t_mid_n) / 10
- *     x[2] = tau |H|_inf           (tau = dt / substeps; |H|_inf as in Alg. 6)
+ *     x[2] = tau |H|_inf           (tau = the length of one Krylov solve: dt / substeps,
+ *                                   halved for scheme 1; |H|_inf as in Alg. 6)
  *     x[3..6] = log10(eps_{h-k}) / 10, k = 0..3   (a-posteriori estimate of
  *               step h-k, floored at 1e-40; log10(tol)/10 before step 0)
  *     x[7] = m_h / 10              (m_hint / 10, or 0.8, before step 0)

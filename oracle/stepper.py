@@ -44,6 +44,21 @@ def midpoint_step_exact(ham, v: np.ndarray, t: float, tau: float, pulse) -> np.n
     return expm_apply(ham.H(A_mid), v, tau)
 
 
+def cfet4_step_exact(ham, v: np.ndarray, t: float, tau: float, pulse) -> np.ndarray:
+    """One step of the fourth-order commutator-free exponential integrator
+    (the higher-order alternative the paper points to in Sec. 3.4): with the
+    Gauss nodes c = 1/2 -+ sqrt(3)/6 and a = (3 -+ 2 sqrt(3))/12,
+        v <- exp(-i tau (a1 H1 + a2 H2)) exp(-i tau (a2 H1 + a1 H2)) v,
+    H_k = H(A(t + c_k tau)), each exponential exact."""
+    r3 = np.sqrt(3.0)
+    c1, c2 = 0.5 - r3 / 6.0, 0.5 + r3 / 6.0
+    a1, a2 = (3.0 - 2.0 * r3) / 12.0, (3.0 + 2.0 * r3) / 12.0
+    H1 = ham.H(pulse_A(pulse, t + c1 * tau))
+    H2 = ham.H(pulse_A(pulse, t + c2 * tau))
+    w = expm_apply(a2 * H1 + a1 * H2, v, tau)
+    return expm_apply(a1 * H1 + a2 * H2, w, tau)
+
+
 def observables(ham, v: np.ndarray, A: float):
     """(norm, energy per site, double occupation per site, site-resolved docc)."""
     p = np.abs(v) ** 2

@@ -67,7 +67,7 @@ class hub_pulse(ctypes.Structure):
 
 class hub_krylov_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("m_max", ctypes.c_int32), ("reorth", ctypes.c_int32),
-                ("substeps", ctypes.c_int32), ("m_hint", ctypes.c_int32)]
+                ("substeps", ctypes.c_int32), ("m_hint", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 class hub_step_info(ctypes.Structure):
@@ -189,8 +189,8 @@ def make_pulse(p) -> hub_pulse:
     return hub_pulse(int(kind), float(A0), float(omega), float(t0), float(sigma), float(b))
 
 
-def make_opts(tol=1e-10, m_max=30, reorth=0, substeps=1, m_hint=0) -> hub_krylov_opts:
-    return hub_krylov_opts(float(tol), int(m_max), int(reorth), int(substeps), int(m_hint))
+def make_opts(tol=1e-10, m_max=30, reorth=0, substeps=1, m_hint=0, scheme=0) -> hub_krylov_opts:
+    return hub_krylov_opts(float(tol), int(m_max), int(reorth), int(substeps), int(m_hint), int(scheme))
 
 
 # ------------------------------------------------------------------- ABI calls

@@ -222,8 +222,23 @@ hub_status check_opts(const hub_krylov_opts& o) {
   if (o.substeps < 1) return fail(HUB_E_INVALID, "opts.substeps must be >= 1");
   if (o.reorth != 0 && o.reorth != 1) return fail(HUB_E_INVALID, "opts.reorth must be 0 or 1");
   if (o.m_hint < 0) return fail(HUB_E_INVALID, "opts.m_hint must be >= 0");
+  if (o.scheme != 0 && o.scheme != 1) return fail(HUB_E_INVALID, "opts.scheme must be 0 or 1");
   return HUB_OK;
 }
+
+// Exponentials per step of the scheme, and the Krylov solves per step.
+int scheme_exps(const hub_krylov_opts& o) { return o.scheme == 1 ? 2 : 1; }
+int solves_per_step(const hub_krylov_opts& o) { return o.substeps * scheme_exps(o); }
+
+// Fourth-order commutator-free exponential (two exponentials per step): Gauss
+// nodes c_{1,2} = 1/2 -+ sqrt(3)/6 and weights a_{1,2} = (3 -+ 2 sqrt(3))/12;
+// the step is exp(-i dt (a1 H1 + a2 H2)) exp(-i dt (a2 H1 + a1 H2)) (right
+// factor first).  Since a1 + a2 = 1/2 each factor is exp(-i (dt/2) H_eff)
+// with the same diagonal and hop coefficients 2 (a H1 + b H2) per class.
+constexpr double kCf4C1 = 0.5 - 0.28867513459481287;  // sqrt(3)/6
+constexpr double kCf4C2 = 0.5 + 0.28867513459481287;
+constexpr double kCf4A1 = (3.0 - 3.4641016151377546) / 12.0;  // 2 sqrt(3)
+constexpr double kCf4A2 = (3.0 + 3.4641016151377546) / 12.0;
 
 hub_status check_common(hub_basis h, hub_prec prec, int32_t nvec) {
   if (!h) return fail(HUB_E_INVALID, "null basis handle");
@@ -324,7 +339,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
 
   // device logs
   const int nobs_rows = want_obs ? n_steps + 1 : 0;
-  const size_t log_bytes = static_cast<size_t>(std::max(1, n_steps)) * o.substeps * nv * sizeof(CombineLog);
+  const size_t log_bytes = static_cast<size_t>(std::max(1, n_steps)) * solves_per_step(o) * nv * sizeof(CombineLog);
   const size_t obs_bytes = static_cast<size_t>(std::max(1, nobs_rows)) * nv * kObsQ * sizeof(double);
   void* dlog = nullptr;
   double* dobs = nullptr;
@@ -343,7 +358,10 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   HUB_HIP(hipMemcpyAsync(h->ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
   HUB_HIP(hipStreamSynchronize(stream));
 
-  const double tau = dt / o.substeps;
+  // each of the scheme's exponentials exp(-i (dt/E) H_e) is split into
+  // `substeps` equal factors: S Krylov solves of length tau per step
+  const int E = scheme_exps(o);
+  const double tau = dt / solves_per_step(o);
   const int rows = pi == 0 ? h->rows_c128 : h->rows_c64;
   hub::ApplyLaunch L{};
   L.db = &h->D;
@@ -360,7 +378,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   L.prev_nblk = hub::elem_grid(dim * nv);
   L.stream = stream;
 
-  const int S = o.substeps;
+  const int S = solves_per_step(o);
   CombineLog* dlog_c = static_cast<CombineLog*>(dlog);
   // one Lanczos iteration j of substep `sub` of step n (apply, then update)
   auto enqueue_iter = [&](int n, int sub, int jj) -> hub_status {
@@ -371,7 +389,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.x = ptrs[jj];
     A.y = jj < o.m_max ? ptrs[jj + 1] : nullptr;
     A.xprev = jj > 0 ? ptrs[jj - 1] : nullptr;
-    A.coef = coef_mid.data() + static_cast<size_t>(n) * nv * 2 * nc;
+    A.coef = coef_mid.data() + (static_cast<size_t>(n) * E + sub / o.substeps) * nv * 2 * nc;
     A.j = jj;
     // a two-pass apply with observables leaves the row pass's partials after
     // the column pass's
@@ -643,7 +661,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   // copy logs back
   const int nd = *steps_done;
   if (reports && nd > 0) {
-    std::vector<CombineLog> lg(static_cast<size_t>(nd) * o.substeps * nv);
+    std::vector<CombineLog> lg(static_cast<size_t>(nd) * S * nv);
     HUB_HIP(hipMemcpyAsync(lg.data(), dlog, lg.size() * sizeof(CombineLog), hipMemcpyDeviceToHost, stream));
     HUB_HIP(hipStreamSynchronize(stream));
     reports->assign(static_cast<size_t>(nd) * nv, StepReport{});
@@ -651,8 +669,8 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       for (int v = 0; v < nv; ++v) {
         StepReport& R = (*reports)[static_cast<size_t>(n) * nv + v];
         R.status = 1;
-        for (int sub = 0; sub < o.substeps; ++sub) {
-          const CombineLog& c = lg[(static_cast<size_t>(n) * o.substeps + sub) * nv + v];
+        for (int sub = 0; sub < S; ++sub) {
+          const CombineLog& c = lg[(static_cast<size_t>(n) * S + sub) * nv + v];
           R.m = std::max(R.m, static_cast<int>(c.m));
           R.eps = std::max(R.eps, c.eps);
           R.beta_last = c.beta_last;
@@ -968,7 +986,8 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
                           const std::vector<std::vector<double>>* A_sample /* [nvec][n_steps+1] */,
                           double t_start, double dt, const hub_krylov_opts& o, hub_obs* obs,
                           hub_step_info* log, void* stream,
-                          const std::vector<std::vector<double>>* dA_mid = nullptr /* [nvec][n_steps] */) {
+                          const std::vector<std::vector<double>>* dA_mid = nullptr /* [nvec][n_steps] */,
+                          const std::vector<std::vector<double>>* A_gauss = nullptr /* [nvec][2 n_steps] */) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int pi = prec == HUB_C128 ? 0 : 1;
   const size_t es = elem_bytes(prec);
@@ -978,10 +997,25 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
   bool any_nc = false;
   int k0 = 0;
   for (int nv : groups) {
-    std::vector<double> cm(static_cast<size_t>(n_steps) * nv * 2 * nc);
+    // hop coefficients of every exponential of every step: [n][e][v][2 nc]
+    const int E = scheme_exps(o);
+    std::vector<double> cm(static_cast<size_t>(n_steps) * E * nv * 2 * nc);
     for (int n = 0; n < n_steps; ++n)
-      for (int v = 0; v < nv; ++v)
-        coef_for(h->B, A_mid[k0 + v][n], cm.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
+      for (int v = 0; v < nv; ++v) {
+        if (E == 1) {
+          coef_for(h->B, A_mid[k0 + v][n], cm.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
+          continue;
+        }
+        double c1[2 * kMaxClasses], c2[2 * kMaxClasses];
+        coef_for(h->B, (*A_gauss)[k0 + v][2 * n], c1);
+        coef_for(h->B, (*A_gauss)[k0 + v][2 * n + 1], c2);
+        double* e0 = cm.data() + ((static_cast<size_t>(n) * E + 0) * nv + v) * 2 * nc;  // applied first
+        double* e1 = cm.data() + ((static_cast<size_t>(n) * E + 1) * nv + v) * 2 * nc;
+        for (int k = 0; k < 2 * nc; ++k) {
+          e0[k] = 2.0 * (kCf4A2 * c1[k] + kCf4A1 * c2[k]);
+          e1[k] = 2.0 * (kCf4A1 * c1[k] + kCf4A2 * c2[k]);
+        }
+      }
     const bool want_obs = obs != nullptr && A_sample != nullptr;
     // hop coefficients at the sample times t_start + n dt, n = 0..n_steps
     std::vector<double> co;
@@ -1046,6 +1080,7 @@ hub_status hub_krylov_expm_step(hub_basis h, const double* A_mid, double dt, con
   if (s != HUB_OK) return s;
   if (!A_mid || !opts || !v_inout) return fail(HUB_E_INVALID, "null argument");
   if ((s = check_opts(*opts)) != HUB_OK) return s;
+  if (opts->scheme != 0) return fail(HUB_E_INVALID, "a single exponential takes opts.scheme = 0");
   if (!std::isfinite(dt)) return fail(HUB_E_INVALID, "non-finite dt");
   std::vector<std::vector<double>> am(nvec, std::vector<double>(1));
   for (int k = 0; k < nvec; ++k) {
@@ -1068,12 +1103,20 @@ hub_status hub_propagate(hub_basis h, const hub_pulse* pulses, double t_start, d
     if ((s = check_pulse(pulses[k])) != HUB_OK) return s;
   std::vector<std::vector<double>> am(nvec, std::vector<double>(n_steps)), as(nvec, std::vector<double>(n_steps + 1));
   std::vector<std::vector<double>> dam(nvec, std::vector<double>(n_steps));
+  std::vector<std::vector<double>> ag;
+  if (opts->scheme == 1) ag.assign(nvec, std::vector<double>(2 * static_cast<size_t>(n_steps)));
   for (int k = 0; k < nvec; ++k) {
     for (int n = 0; n < n_steps; ++n) am[k][n] = pulse_value(pulses[k], t_start + n * dt + 0.5 * dt);
     for (int n = 0; n < n_steps; ++n) dam[k][n] = pulse_deriv(pulses[k], t_start + n * dt + 0.5 * dt);
     for (int n = 0; n <= n_steps; ++n) as[k][n] = pulse_value(pulses[k], t_start + n * dt);
+    if (opts->scheme == 1)
+      for (int n = 0; n < n_steps; ++n) {
+        ag[k][2 * n] = pulse_value(pulses[k], t_start + (n + kCf4C1) * dt);
+        ag[k][2 * n + 1] = pulse_value(pulses[k], t_start + (n + kCf4C2) * dt);
+      }
   }
-  return run_all(h, prec, nvec, v_inout, n_steps, am, &as, t_start, dt, *opts, obs, log, stream, &dam);
+  return run_all(h, prec, nvec, v_inout, n_steps, am, &as, t_start, dt, *opts, obs, log, stream, &dam,
+                 opts->scheme == 1 ? &ag : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1194,6 +1237,7 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
       n_rel < 0)
     return fail(HUB_E_INVALID, "null or empty argument");
   if ((s = check_opts(*opts)) != HUB_OK) return s;
+  if (opts->scheme != 0) return fail(HUB_E_INVALID, "Green's functions use the midpoint scheme (opts.scheme = 0)");
   if ((s = check_pulse(*pulse)) != HUB_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int pi = prec == HUB_C128 ? 0 : 1;
@@ -1566,7 +1610,7 @@ hub_status hub_controller_features(const hub_pulse* pulse, double t_start, doubl
   if ((s = check_opts(*opts)) != HUB_OK) return s;
   if (!std::isfinite(dt) || !std::isfinite(t_start) || !std::isfinite(norm_inf))
     return fail(HUB_E_INVALID, "non-finite argument");
-  const double tau = dt / opts->substeps;
+  const double tau = dt / solves_per_step(*opts);
   for (int n = 0; n < n_steps; ++n) {
     const int hs = n - 1 - (n % chunk);
     double eh[4];

@@ -1,0 +1,87 @@
+"""hub_propagate with opts.scheme = 1 (fourth-order commutator-free
+exponential, two Krylov solves per step) against the oracle's CFET4 stepper:
+8-site ring from its ground state under the pulse, complex128 on the one- and
+two-pass kernels (psi, d(t), E(t) within 1e-10), complex64 within 1e-5, and the
+learned controller's schedule bit-identical on this scheme."""
+import numpy as np
+import pytest
+
+import paper_2005_13498_amd as hub
+from paper_2005_13498_amd import controller as ctl
+from oracle import HubbardOracle, to_canonical, from_canonical, pulse_A
+from oracle.stepper import cfet4_step_exact, observables
+from synth import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+N_STEPS = 60
+
+
+@pytest.fixture(scope="module")
+def setup():
+    w = workloads()["ring8"]
+    ham = HubbardOracle(w.lattice, w.U, 4, 4)
+    B = hub.Basis(w.lattice, w.U, 4, 4, device=0)
+    v = torch.empty(B.dim, dtype=torch.complex128, device=DEV)
+    hub.hub_ground_state(B.handle, pulse_A(w.pulse, 0.0), v, hub.make_opts(tol=1e-13, m_max=60))
+    psi = from_canonical(v.cpu().numpy(), ham.states, 8)
+    x = psi.copy()
+    ref = []
+    dt = 2 * w.dt
+    for k in range(N_STEPS + 1):
+        t = k * dt
+        _, e, d, _ = observables(ham, x, pulse_A(w.pulse, t))
+        ref.append((e, d))
+        if k < N_STEPS:
+            x = cfet4_step_exact(ham, x, t, dt, w.pulse)
+    yield w, ham, B, v, to_canonical(x, ham.states, 8), np.array(ref), dt
+    B.close()
+
+
+@pytest.mark.parametrize("path,dtype,tol", [(0, torch.complex128, 1e-10), (1, torch.complex128, 1e-10),
+                                            (1, torch.complex64, 1e-5)])
+def test_cfet4_matches_oracle(setup, path, dtype, tol):
+    w, ham, B, v0, psi_ref, ref, dt = setup
+    hub.hub_set_apply_path(B.handle, path)
+    try:
+        x = v0.clone().to(dtype)
+        st, obs, log = hub.hub_propagate(B.handle, [w.pulse], 0.0, dt, N_STEPS,
+                                         hub.make_opts(tol=1e-13 if dtype == torch.complex128 else 1e-8,
+                                                       m_max=30, scheme=1), x)
+        got = x.cpu().numpy().astype(np.complex128)
+        assert np.linalg.norm(got - psi_ref) / np.linalg.norm(psi_ref) < tol
+        assert np.max(np.abs(obs[:, 0, 2] - ref[:, 0])) < tol * np.max(np.abs(ref[:, 0]))
+        assert np.max(np.abs(obs[:, 0, 3] - ref[:, 1])) < tol * max(1.0, np.max(np.abs(ref[:, 1])))
+        assert (log[:, 0, 2] == 1).all()
+    finally:
+        hub.hub_set_apply_path(B.handle, -1)
+
+
+def test_cfet4_controller_bit_identical(setup):
+    w, ham, B, v0, psi_ref, ref, dt = setup
+    opts = hub.make_opts(tol=1e-12, m_max=30, scheme=1)
+    outs = []
+    for params in (None, ctl.constant_params(3), ctl.constant_params(12)):
+        x = v0.clone()
+        if params is not None:
+            hub.hub_controller_load(B.handle, params)
+            hub.hub_controller_enable(B.handle, True, 8, 0)
+        try:
+            st, obs, log = hub.hub_propagate(B.handle, [w.pulse], 0.0, dt, 40, opts, x)
+        finally:
+            hub.hub_controller_enable(B.handle, False)
+        outs.append((x, obs, log))
+    for x, obs, log in outs[1:]:
+        assert torch.equal(x, outs[0][0])
+        assert np.array_equal(obs, outs[0][1]) and np.array_equal(log, outs[0][2])
+
+
+def test_scheme_rejected_where_unsupported(setup):
+    w, ham, B, v0, psi_ref, ref, dt = setup
+    x = v0.clone()
+    with pytest.raises(hub.HubError) as e:
+        hub.hub_krylov_expm_step(B.handle, [0.1], 0.01, hub.make_opts(scheme=1), x)
+    assert e.value.status == hub.HUB_E_INVALID
+    with pytest.raises(hub.HubError):
+        hub.hub_propagate(B.handle, [w.pulse], 0.0, dt, 1, hub.make_opts(scheme=2), x)
