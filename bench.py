@@ -274,6 +274,37 @@ def controller_variant(hub, B, w, v0, v_start, t_start: float, steps: int, v_pla
             "train_seconds_untimed": t_train}
 
 
+def cfet4_variant(hub, B, w, v_start, t_start: float, steps: int, v_plain, plain_seconds: float):
+    """Accuracy per cost of the fourth-order commutator-free scheme at 12
+    sites: over the timed window of the midpoint run (steps x dt), CFET4 with
+    a 4x larger step (two Krylov solves each) is timed and both end states
+    are compared with a CFET4 reference at the midpoint run's step (untimed)."""
+    import numpy as np
+    import torch
+
+    T = steps * w.dt
+    opts = hub.make_opts(tol=w.tol, m_max=w.m_max, scheme=1)
+    ref = v_start.clone()
+    hub.hub_propagate(B.handle, [w.pulse], t_start, w.dt, steps, opts, ref, want_obs=False)
+    n4 = steps // 4
+    v = v_start.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, obs, log = hub.hub_propagate(B.handle, [w.pulse], t_start, 4 * w.dt, n4, opts, v)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nr = float(torch.linalg.vector_norm(ref))
+    err4 = float(torch.linalg.vector_norm(v - ref)) / nr
+    err2 = float(torch.linalg.vector_norm(v_plain - ref)) / nr
+    print(f"[bench] cfet4 dt={4 * w.dt}: {el:.3f} s (midpoint {plain_seconds:.3f} s), |dpsi| {err4:.2e} vs "
+          f"midpoint {err2:.2e}", file=sys.stderr, flush=True)
+    return {"window": T, "cfet4_dt": 4 * w.dt, "cfet4_steps": n4, "cfet4_seconds": el,
+            "midpoint_dt": w.dt, "midpoint_seconds": plain_seconds,
+            "cfet4_rel_error_vs_fine_cfet4": err4, "midpoint_rel_error_vs_fine_cfet4": err2,
+            "time_ratio_midpoint_over_cfet4": plain_seconds / el,
+            "mean_krylov_m_per_solve": float(np.mean(log[:, 0, 0]))}
+
+
 def run_cpu_baseline_child(seconds: float) -> dict:
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -398,6 +429,7 @@ def main() -> int:
     if not args.no_variants:
         var = batched_variants(hub, B, v0, w, args.steps)
         var["controller"] = controller_variant(hub, B, w, v0, v_start, t_start, args.steps, v, obs, steps_per_s)
+        var["cfet4"] = cfet4_variant(hub, B, w, v_start, t_start, args.steps, v, elapsed)
         var["speedup_c64_batch8_vs_plain_c128"] = var["c64_batch8"]["member_steps_per_s"] / steps_per_s
         out["variants"] = var
     if not args.no_cpu_baseline:
