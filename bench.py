@@ -305,6 +305,52 @@ def cfet4_variant(hub, B, w, v_start, t_start: float, steps: int, v_plain, plain
             "mean_krylov_m_per_solve": float(np.mean(log[:, 0, 0]))}
 
 
+def large_tile_variant(hub, steps: int = 4) -> dict:
+    """HBM-resident tiles: the 14-site ring (7/7, 188 MB per complex128 vector)
+    and the 16-site ring (8/8, 2.65 GB; down hops gathered from the row in
+    global memory).  Per size: the plain H*v's kernel time and algorithmic
+    GB/s (HIP events on 10 launches), and midpoint steps/s of a few complex128
+    steps from a seeded random state under the ring pulse."""
+    import numpy as np
+    import torch
+    from synth import ring, PulseParams
+
+    out = {}
+    for ns in (14, 16):
+        half = ns // 2
+        B = hub.Basis(ring(ns), 8.0, half, half)
+        g = torch.Generator(device="cuda:0").manual_seed(ns)
+        x = torch.randn(B.dim, dtype=torch.complex128, device="cuda:0", generator=g)
+        x /= torch.linalg.vector_norm(x)
+        y = torch.empty_like(x)
+        hub.hub_apply_H(B.handle, [0.3], x, y)
+        hub.hub_profile_enable(B.handle, 1)
+        hub.hub_profile_read(B.handle)
+        for _ in range(10):
+            hub.hub_apply_H(B.handle, [0.3], x, y)
+        n, ms, bpl = hub.hub_profile_read(B.handle)
+        hub.hub_profile_enable(B.handle, 0)
+        del y
+        us = ms / max(n, 1) * 1e3
+        p = PulseParams(0, 0.5, 8.0, 0.05, 0.3)
+        opts = hub.make_opts(tol=1e-10, m_max=20)
+        hub.hub_propagate(B.handle, [p], 0.0, 0.01, 1, opts, x, want_obs=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, obs, log = hub.hub_propagate(B.handle, [p], 0.01, 0.01, steps, opts, x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"ring{ns}"] = {"dim": int(B.dim), "hv_us": us, "hv_bytes": bpl, "hv_gbps": bpl / (us * 1e-6) / 1e9,
+                            "hv_frac_of_8TBs": bpl / (us * 1e-6) / 8e12, "steps": steps,
+                            "midpoint_steps_per_s": steps / el, "mean_krylov_m": float(np.mean(log[:, 0, 0]))}
+        print(f"[bench] ring{ns}: H*v {us:.0f} us = {bpl / (us * 1e-6) / 1e9:.0f} GB/s, "
+              f"{steps / el:.1f} steps/s", file=sys.stderr, flush=True)
+        B.close()
+        del x
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_cpu_baseline_child(seconds: float) -> dict:
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -430,6 +476,7 @@ def main() -> int:
         var = batched_variants(hub, B, v0, w, args.steps)
         var["controller"] = controller_variant(hub, B, w, v0, v_start, t_start, args.steps, v, obs, steps_per_s)
         var["cfet4"] = cfet4_variant(hub, B, w, v_start, t_start, args.steps, v, elapsed)
+        var["large_tiles"] = large_tile_variant(hub)
         var["speedup_c64_batch8_vs_plain_c128"] = var["c64_batch8"]["member_steps_per_s"] / steps_per_s
         out["variants"] = var
     if not args.no_cpu_baseline:

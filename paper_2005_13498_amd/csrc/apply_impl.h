@@ -92,7 +92,9 @@ __device__ __forceinline__ void block_partials_seq(const double (&vals)[NQ], int
 // UPH = false: row pass of the two-pass apply (diagonal and down hops only;
 // in Lanczos mode the prologue still takes the Krylov decision, and the raw
 // partial product is written for the column pass to finish).
-template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE>
+// GDN: rows too long for LDS (16 sites): the down hops read the row of x in
+// global memory (it stays in L2) and decode sign and padding from the index.
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE, bool GDN>
 __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   using V = typename CT<R>::T;
   constexpr int kBlockA = BLK;
@@ -116,6 +118,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
 
   R sj = 1, bprev = 0;
   static_assert(!FUSE || (NV == 1 && MODE == M_LANCZOS && !UPH), "fused update: single-vector row pass");
+  static_assert(!GDN || (NV == 1 && UPH && !FUSE), "global down-hop gathers: one-pass single vectors");
   R c_upd = 0;  // fused update: alpha_{j-1} s_{j-1}
   if (FUSE) {
     // Row pass of a fused iteration: finish u_j = w_{j-1} - alpha_{j-1} s_{j-1}
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     const double rs = block_sum<kWavesA>(n2, red);
     if (tid == 0) p.norm_out[lb] = rs;
     if (!p.y) return;  // j = m_max: only the norm was needed
-  } else {
+  } else if (!GDN) {
     const V* src = x + (size_t)a * rowlen;
     for (int t = tid; t < half; t += kBlockA) {
       const V val = (t < rowlen) ? src[t] : V{0, 0};
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
       xs[half + t] = V{-val.x, -val.y};
     }
   }
+  const V* __restrict__ xrow = x + (size_t)a * rowlen;  // GDN: the row in global memory
   if (NV > 1) {
     for (int t = tid; t < 64 * NV; t += kBlockA) {
       const int s = t / NV, vv = t % NV;
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     const int b = q / NV;
     const uint32_t db = p.dn_bits[b];
     const double eb = p.eps_dn ? p.eps_dn[b] : 0.0;
-    const V xv = xs[q];
+    const V xv = GDN ? xrow[q] : xs[q];
     const double nd = static_cast<double>(__popc(ua & db));
     const double dg = p.U * nd + ea + eb;
     V acc = V{static_cast<R>(dg) * xv.x, static_cast<R>(dg) * xv.y};
@@ -276,7 +280,17 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     for (int s = 0; s < MAXS; ++s) {
       const uint32_t w2 = (s & 3) < 2 ? ev[s >> 2].x : ev[s >> 2].y;
       const uint32_t idx = (s & 1) ? (w2 >> 16) : (w2 & 0xFFFFu);
-      const V t = xs[idx * NV + v];
+      V t;
+      if (GDN) {  // index = src, src + dim_dn + 1 (negative hop), or dim_dn (pad)
+        const uint32_t dd = static_cast<uint32_t>(p.dim_dn);
+        const bool neg = idx > dd;
+        const uint32_t src = neg ? idx - dd - 1 : idx;
+        t = V{0, 0};
+        if (src < dd) t = xrow[src];
+        if (neg) t = V{-t.x, -t.y};
+      } else {
+        t = xs[idx * NV + v];
+      }
       V cf;
       if (NV == 1) cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
       else cf = sh_slot[s * NV + v];
@@ -346,7 +360,7 @@ hipError_t launch_ev(K fn, int grid, int blk, size_t lds, hipStream_t st, hipEve
   return hipExtLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(blk), kargs, lds, st, e0, e1, 0);
 }
 
-template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE>
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE, bool GDN = false>
 hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   const DevBasis& db = *L.db;
   KArgs p;
@@ -398,7 +412,7 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.obs_row = L.obs_row;
   p.dim_up_rows = db.dim_up;
   p.norm_out = L.norm_partials;
-  auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH, FUSE>;
+  auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH, FUSE, GDN>;
   // dynamic LDS above the 64 KB default must be opted into (CU total 160 KB)
   static int max_dyn = -1;
   if (max_dyn < 0) {
@@ -614,10 +628,32 @@ hipError_t colpass_s(const ApplyLaunch& L, int* pgrid) {
   }
 }
 
+template <typename R, int MODE, int BLK>
+hipError_t apply_gdn_s(const ApplyLaunch& L, int grid) {
+  switch (L.db->maxs_pad) {
+    case 4: return apply_t<R, 1, MODE, 4, BLK, true, false, true>(L, grid, 0);
+    case 8: return apply_t<R, 1, MODE, 8, BLK, true, false, true>(L, grid, 0);
+    case 12: return apply_t<R, 1, MODE, 12, BLK, true, false, true>(L, grid, 0);
+    case 16: return apply_t<R, 1, MODE, 16, BLK, true, false, true>(L, grid, 0);
+    case 20: return apply_t<R, 1, MODE, 20, BLK, true, false, true>(L, grid, 0);
+    case 24: return apply_t<R, 1, MODE, 24, BLK, true, false, true>(L, grid, 0);
+    case 32: return apply_t<R, 1, MODE, 32, BLK, true, false, true>(L, grid, 0);
+    case 48: return apply_t<R, 1, MODE, 48, BLK, true, false, true>(L, grid, 0);
+    case 64: return apply_t<R, 1, MODE, 64, BLK, true, false, true>(L, grid, 0);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename R, int NV>
 hipError_t apply_mode(const ApplyLaunch& L, int grid, size_t lds, int* pgrid) {
   if (pgrid) *pgrid = grid;
   if constexpr (NV == 1) {
+    if (apply_global_rows(*L.db, L.prec, 1)) {  // a row does not fit LDS
+      if (L.mode == kPlain) return apply_gdn_s<R, M_PLAIN, 1024>(L, grid);
+      if (L.mode == kObsOnly) return apply_gdn_s<R, M_OBS, 256>(L, grid);
+      if (L.obs) return apply_gdn_s<R, M_LANCZOS_OBS, 256>(L, grid);
+      return apply_gdn_s<R, M_LANCZOS, 1024>(L, grid);
+    }
     const bool longrow = L.db->dim_dn >= kRowsLong;
     if (apply_two_pass(*L.db, L.prec, 1, L.mode, L.obs)) {
       hipError_t e;

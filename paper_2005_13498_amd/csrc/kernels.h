@@ -115,6 +115,9 @@ int apply_grid(const DevBasis& db, int prec, int nv);    // most workgroups any 
 // for all up strings in LDS and adds the up hops (and the Lanczos epilogue).
 constexpr int kColW = 4;
 bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs);
+// Rows whose staged copy (+x, -x) exceeds the LDS budget (16 sites): the
+// one-pass kernel then gathers the down hops from the row in global memory.
+bool apply_global_rows(const DevBasis& db, int prec, int nv);
 int colpass_grid(const DevBasis& db);
 size_t colpass_lds_bytes(const DevBasis& db, int prec);
 int apply_chunks(const DevBasis& db, int prec, int nv);  // column chunks per tile row

@@ -534,6 +534,10 @@ size_t colpass_lds_bytes(const DevBasis& db, int prec) {
   return 2 * (static_cast<size_t>(db.dim_up) + 1) * kColW * (prec == 0 ? 16 : 8);  // +x, -x, zero row
 }
 
+bool apply_global_rows(const DevBasis& db, int prec, int nv) {
+  return nv == 1 && apply_lds_bytes(db, prec, 1, 1) > 150 * 1024;
+}
+
 bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
   if (nv != 1 || !(mode == kPlain || mode == kLanczos) || db.two_pass == 0 || !db.up_tab) return false;
   if (obs && mode != kLanczos) return false;
