@@ -186,7 +186,9 @@ hub_status hub_krylov_expm_step(hub_basis basis, const double *A_mid, double dt,
  * column k), with H(t) evaluated at the sample time.  log: host
  * [n_steps * nvec] or NULL.  Returns HUB_E_NOT_CONVERGED (and stops) at the
  * first step where a vector hits m_max; v_inout then holds that step's
- * m_max approximation.  Synchronises `stream`. */
+ * m_max approximation.  The schedule (hub_set_schedule,
+ * hub_controller_enable) changes how the launches overlap the host, never the
+ * result.  Synchronises `stream`. */
 hub_status hub_propagate(hub_basis basis, const hub_pulse *pulses, double t_start, double dt,
                          int32_t n_steps, const hub_krylov_opts *opts, hub_prec prec,
                          int32_t nvec, void *v_inout, hub_obs *obs, hub_step_info *log,
@@ -337,8 +339,24 @@ typedef struct {
   int64_t iterations;     /* Krylov iterations those steps needed (sum of m over steps and vectors) */
 } hub_controller_stats;
 
-/* Counters since the last read (then reset). */
+/* Counters since the last read (then reset).  They count the chunks of the
+ * default schedule (hub_set_schedule) as well as the learned controller's. */
 hub_status hub_controller_read_stats(hub_basis basis, hub_controller_stats *out);
+
+/* Schedule of hub_propagate when the learned controller is off.
+ *   chunk >= 1 (default 16, margin 1): chunks of `chunk` steps are enqueued
+ *     without waiting for the host; every step of a chunk runs
+ *     min(m_max, m_ref + margin) + 1 Lanczos launches, m_ref being the largest
+ *     Krylov dimension of the previous chunk's steps (the first chunk:
+ *     m_hint, else 8).  A step that has not decided within its launches stops
+ *     the chunk on the device and is re-run with the synchronous schedule.
+ *   chunk = 0: synchronous schedule, one host round trip per (sub)step plus
+ *     one per iteration beyond the previous step's m.
+ * Both give bit-identical states, observables and logs (the decisions are
+ * taken on the device either way); only the host/device overlap differs.
+ * chunk in [0, 256], margin in [0, 16]; HUB_E_INVALID otherwise.  Runs of a
+ * single step use the synchronous schedule. */
+hub_status hub_set_schedule(hub_basis basis, int32_t chunk, int32_t margin);
 
 /* ------------------------------------------------------------------------ */
 /* Choice of the H*v kernels for single vectors (plain applies and the
@@ -361,9 +379,14 @@ hub_status hub_set_apply_path(hub_basis basis, int32_t path);
  * dispatches of every k-th eligible H*v: hub_apply_H launches and Lanczos
  * H*v launches of a propagation except the first of each step, which also
  * records observables (a different kernel).  When a propagation runs the
- * two-pass kernels without re-orthogonalisation, iterations j >= 2 fuse the
+ * two-pass kernels without re-orthogonalisation, iterations j >= 1 fuse the
  * Lanczos update into the row pass, and only those fused iterations are
  * timed.  A two-pass apply is timed as the sum of its two kernels.
+ * Launches enqueued past a step's Krylov decision (speculative iterations,
+ * which exit at once) are left out once the step's m is known.  The events
+ * come from a pool of 8192 created here (on >= 1); a propagation reads them
+ * back and reuses them only when fewer than 512 are left, so a run of up to
+ * about 2000 timed launches adds neither event creation nor read-back to it. 
  * hub_profile_read returns the number of timed launches, their summed kernel
  * time in ms, and the algorithmic bytes of one timed launch (H*v: 2 * nvec *
  * dim * complex size, read x once and write y once; fused iteration: 4 *

@@ -40,7 +40,7 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_profile_read", "hub_apply_cop", "hub_dot", "hub_greens_diag",
            "hub_mlp_forward", "hub_mlp_workspace_bytes", "hub_mlp_train_step", "hub_controller_features",
            "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats",
-           "hub_set_apply_path", "hub_spectral")
+           "hub_set_apply_path", "hub_spectral", "hub_set_schedule")
 
 # Controller MLP sizes (HUB_MLP_* in hub.h).
 MLP_IN, MLP_HID, MLP_OUT = 8, 64, 2
@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_controller_enable": ([vp, i32, i32, i32], i32),
         "hub_controller_read_stats": ([vp, P(hub_controller_stats)], i32),
         "hub_set_apply_path": ([vp, i32], i32),
+        "hub_set_schedule": ([vp, i32, i32], i32),
         "hub_spectral": ([i32, i32, i32, vp, P(i32), dbl, dbl, i32, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -454,6 +455,12 @@ def hub_spectral(overlaps, lesser, dt: float, eps: float, nu, out, stream=None) 
 def hub_set_apply_path(h, path: int) -> None:
     """-1 automatic, 0 one-pass, 1 two-pass H*v kernels for single vectors."""
     _check(load_library().hub_set_apply_path(ctypes.c_void_p(h), int(path)))
+
+
+def hub_set_schedule(h, chunk: int, margin: int = 1) -> None:
+    """Default propagation schedule: chunks of `chunk` steps without host
+    synchronisation (0: one synchronisation per step)."""
+    _check(load_library().hub_set_schedule(ctypes.c_void_p(h), int(chunk), int(margin)))
 
 
 class Basis:

@@ -51,8 +51,20 @@ hub_status fail(hub_status s, const std::string& msg) {
 size_t elem_bytes(hub_prec p) { return p == HUB_C128 ? 16 : 8; }
 
 constexpr int kCtrlMaxChunk = 256;
+// Event pool of the apply timing: created when timing is enabled, and read
+// back (elapsed times) only when fewer than kProfLowWater events are left.
+constexpr size_t kProfPool = 8192, kProfLowWater = 512;
 
 }  // namespace
+
+// One timed apply: start/stop events of its kernel(s) until they are read
+// (then returned to the pool), its kernel time, and whether it did work.
+struct ProfSample {
+  std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
+  double ms = 0.0;
+  int n = -1, sub = 0, j = 0;  // Lanczos launch: step, substep, iteration (n = -1: plain apply)
+  int worked = 1;              // 0: launched past the Krylov decision (exits at once); -1: not yet known
+};
 
 struct hub_basis_s {
   hub::Basis B;
@@ -85,10 +97,11 @@ struct hub_basis_s {
   float* ctrl_hout = nullptr;
   hub_controller_stats cstats{};
   // profiling of the apply kernel
+  int sched_chunk = 16, sched_margin = 1;  // default chunked schedule (chunk 0: synchronous)
   bool prof = false;
   int prof_period = 1;
   int64_t prof_count = 0;
-  std::vector<std::array<hipEvent_t, 4>> ev_used;  // per sampled apply; unused entries null
+  std::vector<ProfSample> prof_samples;
   std::vector<hipEvent_t> ev_free;
   double prof_bytes = 0.0;
 };
@@ -253,7 +266,8 @@ hub_status check_common(hub_basis h, hub_prec prec, int32_t nvec) {
 // Lanczos-mode applies that do not also accumulate observables (every
 // prof_period-th such apply): one start/end pair per kernel, so a sampled
 // apply's time is its kernel time (row plus column pass for two passes).
-hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid = nullptr, bool fusing = false) {
+hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid = nullptr, bool fusing = false,
+                              int step = -1, int sub = 0) {
   // with fused iterations in the loop, only those (the dominant kernels) are timed
   bool timed = h->prof && (L.mode == hub::kPlain || (L.mode == hub::kLanczos && !L.obs && (!fusing || L.fuse)));
   if (timed) timed = (h->prof_count++ % h->prof_period) == 0;
@@ -277,10 +291,38 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid 
   T.ev2_start = ev[2];
   T.ev2_stop = ev[3];
   HUB_HIP(hub::launch_apply(T, grid));
-  h->ev_used.push_back(ev);
+  ProfSample smp;
+  smp.ev = ev;
+  smp.n = step;
+  smp.sub = sub;
+  smp.j = L.j;
+  smp.worked = step < 0 ? 1 : -1;
+  h->prof_samples.push_back(smp);
   // algorithmic bytes: H*v reads x, writes y; a fused iteration also reads
   // w_{j-1} and u_{j-1} and writes u_j instead of reading x
   h->prof_bytes = (L.fuse ? 4.0 : 2.0) * L.nv * static_cast<double>(h->D.dim) * (L.prec == 0 ? 16.0 : 8.0);
+  return HUB_OK;
+}
+
+// Kernel times of the samples [from, end) (their events must have completed:
+// call after synchronising the stream they were recorded on); the events go
+// back to the pool.  Returns the end.
+hub_status prof_harvest(hub_basis h, size_t from, size_t* end) {
+  for (size_t i = from; i < h->prof_samples.size(); ++i) {
+    ProfSample& p = h->prof_samples[i];
+    for (int k = 0; k < 4; k += 2) {
+      if (!p.ev[k]) continue;
+      float ms = 0.0f;
+      HUB_HIP(hipEventElapsedTime(&ms, p.ev[k], p.ev[k + 1]));
+      p.ms += ms;
+    }
+    for (hipEvent_t& x : p.ev)
+      if (x) {
+        h->ev_free.push_back(x);
+        x = nullptr;
+      }
+  }
+  *end = h->prof_samples.size();
   return HUB_OK;
 }
 
@@ -323,6 +365,15 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   const int pi = prec == HUB_C128 ? 0 : 1;
   hub_status s = ensure_workspace(h, vbytes, o.m_max, nv > 1 ? vbytes : 0);
   if (s != HUB_OK) return s;
+  // timed applies of this call: when the event pool runs low, their kernel
+  // times are read at the next synchronisation (so the events are reused);
+  // at the end the launches past a step's Krylov decision are marked as such
+  const size_t prof_s0 = h->prof_samples.size();
+  size_t prof_hv = prof_s0;
+  auto harvest = [&]() -> hub_status {
+    if (h->ev_free.size() >= kProfLowWater) return HUB_OK;
+    return prof_harvest(h, prof_hv, &prof_hv);
+  };
 
   void* slot0 = user;
   if (nv > 1) {
@@ -412,7 +463,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       A.norm_partials = h->partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ;
     }
     int agrid = 0;  // workgroups that wrote the apply's partial sums
-    hub_status r = launch_apply_timed(h, A, &agrid, fusable);
+    hub_status r = launch_apply_timed(h, A, &agrid, fusable, n, sub);
     if (r != HUB_OK) return r;
     const bool next_fused = fusable;  // every later iteration finishes this update itself
     if (jj < o.m_max && !next_fused) {
@@ -464,7 +515,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       }
       m_step_max = std::max(m_step_max, static_cast<int>(h->h_ctl->iter));
       *maxed = h->h_ctl->any_maxed != 0;
-      hub_status r = finish_sub(n, sub);
+      hub_status r = harvest();
+      if (r != HUB_OK) return r;
+      r = finish_sub(n, sub);
       if (r != HUB_OK) return r;
       if (*maxed) break;
     }
@@ -473,7 +526,13 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     return HUB_OK;
   };
 
-  const bool controlled = h->ctrl_on && ctrl != nullptr && n_steps > 0;
+  // Chunked schedule: with the learned controller, or (default) with the
+  // previous chunk's largest m as the prediction; results are the same as
+  // the synchronous loop below either way.
+  const bool learned = h->ctrl_on && ctrl != nullptr;
+  const bool controlled = n_steps > 0 && (learned || (h->sched_chunk > 0 && n_steps >= 2));
+  const int chunk = learned ? h->ctrl_chunk : h->sched_chunk;
+  const int margin = learned ? h->ctrl_margin : h->sched_margin;
   if (!controlled) {
     for (int n = 0; n < n_steps; ++n) {
       bool maxed = false;
@@ -486,11 +545,12 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       }
     }
   } else {
-    // Controlled schedule: plan `chunk` steps with one MLP launch, enqueue
-    // them without host synchronisation, then check on the device counters
-    // how many finished; an undecided step is re-run adaptively.
+    // Chunked schedule: plan `chunk` steps (one MLP launch, or the largest m
+    // of the previous chunk), enqueue them without host synchronisation, then
+    // check on the device counters how many finished; an undecided step is
+    // re-run adaptively.
     std::vector<CombineLog> hlog(static_cast<size_t>(n_steps) * S * nv);
-    std::vector<int> L_of(h->ctrl_chunk);
+    std::vector<int> L_of(chunk);
     auto step_hist = [&](int n, int v, double* eps, int* m) {  // step n's log of vector v
       double e = 0.0;
       int mm = 0;
@@ -512,10 +572,10 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     };
     int n = 0;
     while (n < n_steps) {
-      const int K = std::min(h->ctrl_chunk, n_steps - n);
+      const int K = std::min(chunk, n_steps - n);
       // plan: features of every (step, vector) row, history up to step n-1
       float* hf = h->ctrl_hfeat;
-      for (int k = 0; k < K; ++k)
+      for (int k = 0; learned && k < K; ++k)
         for (int v = 0; v < nv; ++v) {
           double eh[4];
           for (int q = 0; q < 4; ++q) {
@@ -532,11 +592,13 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
                         hf + (static_cast<size_t>(k) * nv + v) * HUB_MLP_IN);
         }
       const int rows = K * nv;
-      HUB_HIP(hipMemcpyAsync(h->ctrl_feat, hf, static_cast<size_t>(rows) * HUB_MLP_IN * sizeof(float),
-                             hipMemcpyHostToDevice, stream));
-      HUB_HIP(hub::launch_mlp_forward(h->ctrl_params, rows, h->ctrl_feat, h->ctrl_out, stream));
-      HUB_HIP(hipMemcpyAsync(h->ctrl_hout, h->ctrl_out, static_cast<size_t>(rows) * HUB_MLP_OUT * sizeof(float),
-                             hipMemcpyDeviceToHost, stream));
+      if (learned) {
+        HUB_HIP(hipMemcpyAsync(h->ctrl_feat, hf, static_cast<size_t>(rows) * HUB_MLP_IN * sizeof(float),
+                               hipMemcpyHostToDevice, stream));
+        HUB_HIP(hub::launch_mlp_forward(h->ctrl_params, rows, h->ctrl_feat, h->ctrl_out, stream));
+        HUB_HIP(hipMemcpyAsync(h->ctrl_hout, h->ctrl_out, static_cast<size_t>(rows) * HUB_MLP_OUT * sizeof(float),
+                               hipMemcpyDeviceToHost, stream));
+      }
       StepCtl c0 = *h->h_ctl;
       c0.abort = 0;
       c0.steps_done = 0;
@@ -545,17 +607,32 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       c0.iter = 0;
       *h->h_ctl = c0;
       HUB_HIP(hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
-      HUB_HIP(hipStreamSynchronize(stream));
-      for (int k = 0; k < K; ++k) {
-        double lg = 0.0;
-        for (int v = 0; v < nv; ++v) {
-          const double ov = h->ctrl_hout[(static_cast<size_t>(k) * nv + v) * HUB_MLP_OUT];
-          lg = std::max(lg, std::isfinite(ov) ? ov : 64.0);
+      if (learned) {
+        HUB_HIP(hipStreamSynchronize(stream));  // the predictions
+        for (int k = 0; k < K; ++k) {
+          double lg = 0.0;
+          for (int v = 0; v < nv; ++v) {
+            const double ov = h->ctrl_hout[(static_cast<size_t>(k) * nv + v) * HUB_MLP_OUT];
+            lg = std::max(lg, std::isfinite(ov) ? ov : 64.0);
+          }
+          const double mpred = std::ceil(std::exp2(std::min(lg, 10.0)) - 1e-6);
+          L_of[k] = std::min(o.m_max, static_cast<int>(mpred) + margin) + 1;  // launches j = 0..L-1
         }
-        const double mpred = std::ceil(std::exp2(std::min(lg, 10.0)) - 1e-6);
-        L_of[k] = std::min(o.m_max, static_cast<int>(mpred) + h->ctrl_margin) + 1;  // launches j = 0..L-1
+      } else {
+        // the largest m of the previous chunk's steps (the first chunk: the hint)
+        int m_ref = 0;
+        for (int q = std::max(0, n - chunk); q < n; ++q)
+          for (int v = 0; v < nv; ++v) {
+            double e;
+            int mm;
+            step_hist(q, v, &e, &mm);
+            m_ref = std::max(m_ref, mm);
+          }
+        if (m_ref == 0) m_ref = m_pred;
+        for (int k = 0; k < K; ++k) L_of[k] = std::min(o.m_max, m_ref + margin) + 1;
       }
       // enqueue the chunk
+      const size_t chunk_s = h->prof_samples.size();
       for (int k = 0; k < K; ++k)
         for (int sub = 0; sub < S; ++sub) {
           HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, first, h->partials_e, stream));
@@ -571,6 +648,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       HUB_HIP(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
       { hub_status r = fetch_logs(n, n + K); if (r != HUB_OK) return r; }
       HUB_HIP(hipStreamSynchronize(stream));
+      { hub_status r = harvest(); if (r != HUB_OK) return r; }
       h->cstats.chunks += 1;
       const int done_sub = h->h_ctl->steps_done;
       const int complete = std::min(K, done_sub / S);
@@ -604,6 +682,10 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       }
       // fallback: the first unfinished step, from its first unfinished substep
       const int nb = n + complete;
+      for (size_t i = chunk_s; i < h->prof_samples.size(); ++i) {  // launched after the stop
+        ProfSample& p = h->prof_samples[i];
+        if (p.n > nb || (p.n == nb && p.sub > done_sub % S)) p.worked = 0;
+      }
       StepCtl c1 = *h->h_ctl;
       c1.abort = 0;
       c1.all_done = 0;
@@ -660,10 +742,31 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
 
   // copy logs back
   const int nd = *steps_done;
-  if (reports && nd > 0) {
-    std::vector<CombineLog> lg(static_cast<size_t>(nd) * S * nv);
+  const bool classify = h->prof_samples.size() > prof_s0;
+  std::vector<CombineLog> lg;
+  if ((reports || classify) && nd > 0) {
+    lg.resize(static_cast<size_t>(nd) * S * nv);
     HUB_HIP(hipMemcpyAsync(lg.data(), dlog, lg.size() * sizeof(CombineLog), hipMemcpyDeviceToHost, stream));
     HUB_HIP(hipStreamSynchronize(stream));
+  }
+  if (classify) {
+    // launch j of a (sub)step with Krylov dimension m did work iff j <= m
+    // (j = m builds u_m, whose norm the decision needs) and j < m_max
+    // (launch m_max only takes the decision)
+    for (size_t i = prof_s0; i < h->prof_samples.size(); ++i) {
+      ProfSample& p = h->prof_samples[i];
+      if (p.worked != -1) continue;
+      if (p.n < 0 || p.n >= nd) {
+        p.worked = 0;
+        continue;
+      }
+      int m = 0;
+      for (int v = 0; v < nv; ++v)
+        m = std::max(m, static_cast<int>(lg[(static_cast<size_t>(p.n) * S + p.sub) * nv + v].m));
+      p.worked = (p.j <= m && p.j < o.m_max) ? 1 : 0;
+    }
+  }
+  if (reports && nd > 0) {
     reports->assign(static_cast<size_t>(nd) * nv, StepReport{});
     for (int n = 0; n < nd; ++n)
       for (int v = 0; v < nv; ++v) {
@@ -825,8 +928,8 @@ void hub_basis_destroy(hub_basis h) {
   if (h->ctrl_out) (void)hipFree(h->ctrl_out);
   if (h->ctrl_hfeat) (void)hipHostFree(h->ctrl_hfeat);
   if (h->ctrl_hout) (void)hipHostFree(h->ctrl_hout);
-  for (auto& e : h->ev_used)
-    for (hipEvent_t x : e)
+  for (auto& p : h->prof_samples)
+    for (hipEvent_t x : p.ev)
       if (x) (void)hipEventDestroy(x);
   for (hipEvent_t x : h->ev_free) (void)hipEventDestroy(x);
   delete h;
@@ -1678,6 +1781,15 @@ hub_status hub_spectral(int32_t device, int32_t n_members, int32_t n_s, const do
   return HUB_OK;
 }
 
+hub_status hub_set_schedule(hub_basis h, int32_t chunk, int32_t margin) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (chunk < 0 || chunk > kCtrlMaxChunk) return fail(HUB_E_INVALID, "chunk must be in [0, 256]");
+  if (margin < 0 || margin > 16) return fail(HUB_E_INVALID, "margin must be in [0, 16]");
+  h->sched_chunk = chunk;
+  h->sched_margin = margin;
+  return HUB_OK;
+}
+
 hub_status hub_set_apply_path(hub_basis h, int32_t path) {
   if (!h) return fail(HUB_E_INVALID, "null basis handle");
   if (path < -1 || path > 1) return fail(HUB_E_INVALID, "path must be -1, 0 or 1");
@@ -1692,6 +1804,14 @@ hub_status hub_profile_enable(hub_basis h, int32_t on) {
   h->prof = on != 0;
   h->prof_period = on > 0 ? on : 1;
   h->prof_count = 0;
+  if (on > 0) {  // events for a few thousand samples (recycled when they run low)
+    HUB_HIP(hipSetDevice(h->device));
+    while (h->ev_free.size() < kProfPool) {
+      hipEvent_t e;
+      HUB_HIP(hipEventCreate(&e));
+      h->ev_free.push_back(e);
+    }
+  }
   return HUB_OK;
 }
 
@@ -1699,21 +1819,20 @@ hub_status hub_profile_read(hub_basis h, int64_t* launches, double* total_ms, do
   if (!h) return fail(HUB_E_INVALID, "null basis handle");
   HUB_HIP(hipSetDevice(h->device));
   HUB_HIP(hipDeviceSynchronize());
+  size_t end = 0;
+  hub_status r = prof_harvest(h, 0, &end);
+  if (r != HUB_OK) return r;
   double tot = 0.0;
-  for (auto& e : h->ev_used) {
-    for (int k = 0; k < 4; k += 2) {
-      if (!e[k]) continue;
-      float ms = 0.0f;
-      HUB_HIP(hipEventElapsedTime(&ms, e[k], e[k + 1]));
-      tot += ms;
-    }
-    for (hipEvent_t x : e)
-      if (x) h->ev_free.push_back(x);
+  int64_t cnt = 0;
+  for (const ProfSample& p : h->prof_samples) {
+    if (p.worked == 0) continue;
+    tot += p.ms;
+    ++cnt;
   }
-  if (launches) *launches = static_cast<int64_t>(h->ev_used.size());
+  if (launches) *launches = cnt;
   if (total_ms) *total_ms = tot;
   if (bytes_per_launch) *bytes_per_launch = h->prof_bytes;
-  h->ev_used.clear();
+  h->prof_samples.clear();
   return HUB_OK;
 }
 

@@ -100,14 +100,16 @@ def _run(B, pulses, w, v0, prec, opts, params=None, chunk=8, margin=1, allow_nc=
     if params is not None:
         hub.hub_controller_load(B.handle, params)
         hub.hub_controller_enable(B.handle, True, chunk, margin)
-    else:
+    else:  # reference: the synchronous schedule
         hub.hub_controller_enable(B.handle, False)
+        hub.hub_set_schedule(B.handle, 0)
     hub.hub_controller_read_stats(B.handle)
     try:
         st, obs, log = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, w.n_steps, opts, v,
                                          allow_not_converged=allow_nc)
     finally:
         hub.hub_controller_enable(B.handle, False)
+        hub.hub_set_schedule(B.handle, 16, 1)
     return st, v, obs, log, hub.hub_controller_read_stats(B.handle)
 
 

@@ -1,0 +1,139 @@
+"""Default chunked propagation schedule against the synchronous one, through
+the C ABI.
+
+The chunked schedule plans every step of a chunk with the previous chunk's
+largest Krylov dimension (plus a margin) and enqueues the chunk without host
+synchronisation; a step that has not decided within its launches stops the
+chunk on the device and is re-run synchronously.  Since every decision is
+taken on the device, both schedules must give bit-identical states,
+observables and step logs: on the one-pass and the two-pass (fused) kernels,
+for blocks of vectors and complex64, with substeps and the fourth-order
+scheme, when m grows past the plan (margin 0, tight tolerance), and when a
+vector hits m_max.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2005_13498_amd as hub
+from synth import workloads, random_state, ring, PulseParams
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _run(B, pulses, v0, dt, n_steps, opts, chunk, margin=1, allow_nc=False, t0=0.0):
+    v = v0.clone()
+    hub.hub_set_schedule(B.handle, chunk, margin)
+    hub.hub_controller_read_stats(B.handle)
+    try:
+        st, obs, log = hub.hub_propagate(B.handle, pulses, t0, dt, n_steps, opts, v, allow_not_converged=allow_nc)
+    finally:
+        hub.hub_set_schedule(B.handle, 16, 1)
+    return st, v, obs, log, hub.hub_controller_read_stats(B.handle)
+
+
+def _same(a, b):
+    assert a[0] == b[0]
+    assert torch.equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2], equal_nan=True)
+    assert np.array_equal(a[3], b[3])
+
+
+def _vecs(B, nv, seed, dtype):
+    x = np.concatenate(random_state(B.dim, seed=seed, nvec=nv))
+    return torch.from_numpy(x).to(DEV).to(dtype).contiguous()
+
+
+@pytest.mark.parametrize("dtype,nv", [(torch.complex128, 1), (torch.complex128, 3), (torch.complex64, 2)])
+@pytest.mark.parametrize("chunk,margin", [(16, 1), (1, 0), (5, 0), (256, 2)])
+def test_chunked_equals_synchronous_ring8(dtype, nv, chunk, margin):
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        pulses = [w.pulse] + [PulseParams(0, 0.3 + 0.25 * k, 8.0, 1.0, 0.3) for k in range(nv - 1)]
+        v0 = _vecs(B, nv, 51, dtype)
+        opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+        ref = _run(B, pulses, v0, w.dt, 60, opts, 0)
+        got = _run(B, pulses, v0, w.dt, 60, opts, chunk, margin)
+        _same(got, ref)
+        assert ref[4]["chunks"] == 0
+        s = got[4]
+        assert s["chunks"] >= 1 and s["steps"] + s["fallbacks"] >= 60
+    finally:
+        B.close()
+
+
+def test_chunked_handles_growing_m():
+    """Tight tolerance with the hint far below the needed m: the first step of
+    the first chunk is abandoned on the device; margin 0 abandons every step
+    where m grows."""
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        v0 = _vecs(B, 1, 52, torch.complex128)
+        pulse = PulseParams(0, 1.2, 10.0, 2.0, 0.6)
+        opts = hub.make_opts(tol=1e-14, m_max=40, m_hint=2)
+        ref = _run(B, [pulse], v0, 0.05, 50, opts, 0)
+        got = _run(B, [pulse], v0, 0.05, 50, opts, 8, 0)
+        _same(got, ref)
+        assert got[4]["fallbacks"] >= 1
+        assert int(ref[3][:, 0, 0].max()) > 3
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("scheme,substeps", [(0, 3), (1, 1), (1, 2)])
+def test_chunked_with_substeps_and_cfet4(scheme, substeps):
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        v0 = _vecs(B, 2, 53, torch.complex128)
+        pulses = [w.pulse, PulseParams(0, 0.8, 7.0, 1.0, 0.3)]
+        opts = hub.make_opts(tol=w.tol, m_max=w.m_max, substeps=substeps, scheme=scheme)
+        ref = _run(B, pulses, v0, 0.04, 40, opts, 0)
+        for chunk, margin in ((16, 1), (3, 0)):
+            _same(_run(B, pulses, v0, 0.04, 40, opts, chunk, margin), ref)
+    finally:
+        B.close()
+
+
+def test_chunked_stops_at_m_max_like_synchronous():
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        v0 = _vecs(B, 1, 54, torch.complex128)
+        opts = hub.make_opts(tol=1e-15, m_max=4)
+        ref = _run(B, [w.pulse], v0, w.dt, 30, opts, 0, allow_nc=True)
+        assert ref[0] == hub.HUB_E_NOT_CONVERGED
+        for chunk, margin in ((16, 1), (4, 0), (2, 3)):
+            _same(_run(B, [w.pulse], v0, w.dt, 30, opts, chunk, margin, allow_nc=True), ref)
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_chunked_equals_synchronous_cluster3x4_two_pass(dtype):
+    """The 12-site tile runs the fused two-pass iterations."""
+    w = workloads()["cluster3x4"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        v0 = _vecs(B, 1, 55, dtype)
+        opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+        ref = _run(B, [w.pulse], v0, w.dt, 24, opts, 0, t0=1.7)
+        for chunk, margin in ((16, 1), (5, 0)):
+            _same(_run(B, [w.pulse], v0, w.dt, 24, opts, chunk, margin, t0=1.7), ref)
+    finally:
+        B.close()
+
+
+def test_schedule_argument_checks():
+    B = hub.Basis(ring(6), 4.0, 3, 3, device=0)
+    try:
+        for chunk, margin in ((-1, 1), (257, 1), (4, -1), (4, 17)):
+            with pytest.raises(hub.HubError):
+                hub.hub_set_schedule(B.handle, chunk, margin)
+        hub.hub_set_schedule(B.handle, 0, 0)
+        hub.hub_set_schedule(B.handle, 256, 16)
+    finally:
+        B.close()
