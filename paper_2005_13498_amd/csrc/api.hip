@@ -497,7 +497,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     int m_step_max = 0;
     *maxed = false;
     for (int sub = sub0; sub < S; ++sub) {
-      HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, first, h->partials_e, stream));
+      // later substeps need no step_begin: tau is set, k_combine left the
+      // |v|^2 partials and k_step_log cleared the control block
+      if (first) HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, true, h->partials_e, stream));
       first = false;
       int j = 0;
       for (; j <= m_pred && j <= o.m_max; ++j) {
@@ -635,7 +637,8 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       const size_t chunk_s = h->prof_samples.size();
       for (int k = 0; k < K; ++k)
         for (int sub = 0; sub < S; ++sub) {
-          HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, first, h->partials_e, stream));
+          if (first)
+            HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, true, h->partials_e, stream));
           first = false;
           for (int j = 0; j < L_of[k] && j <= o.m_max; ++j) {
             hub_status r = enqueue_iter(n + k, sub, j);

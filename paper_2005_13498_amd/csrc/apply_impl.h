@@ -37,7 +37,10 @@ struct KArgs {  // passed by value as kernel arguments (at most 4 KB)
   const uint32_t* up_hops;    // src | class << 16 | sign << 31
   const uint16_t* dn_tab;     // [dim_dn][MAXS] stage index (src + copy * (dim_dn + 1)), pad = dim_dn
   uint8_t slot_class[64];
-  double coef[2 * kMaxNV * kMaxClasses];  // [v][c] complex
+  union {
+    double coef[2 * kMaxNV * kMaxClasses];  // NV > 1: [v][c] complex
+    double slot_coef_obs[2 * 64];           // NV = 1, observables: coefficient of every down slot at t_obs
+  };
   double slot_coef[2 * 64];                // vector 0: coefficient of every down slot
   double up_coef[2 * 2 * kMaxClasses];     // vector 0: [c][sign] signed coefficient
   double coef_obs[2 * kMaxNV * kMaxClasses];  // [v][c] complex, observation time (obs modes)
@@ -55,6 +58,8 @@ struct KArgs {  // passed by value as kernel arguments (at most 4 KB)
   int dim_up_rows;
   double* norm_out;                // fused: |u_j|^2 partial of every row
 };
+
+static_assert(kMaxNV * kMaxClasses == 64, "the single-vector observation coefficients share coef's storage");
 
 // Threads per apply workgroup.  Long rows of single vectors use 1024 threads
 // (fewer column passes per thread); short rows, interleaved blocks and the
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   __shared__ double sh_beta[kMaxNV];
   __shared__ V sh_slot[NV > 1 ? 64 * NV : 1];
   __shared__ V sh_up[NV > 1 ? 2 * kMaxClasses * NV : 1];
-  __shared__ double2 sh_oslot[kO ? 64 * NV : 1];             // observation-time coefficient per slot
+  __shared__ double2 sh_oslot[kO && NV > 1 ? 64 * NV : 1];    // observation-time coefficient per slot
   __shared__ double2 sh_oup[kO ? 2 * kMaxClasses * NV : 1];  // and per signed up-hop class
 
   const int tid = threadIdx.x;
@@ -243,7 +248,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     }
   }
   if (kO) {
-    for (int t = tid; t < 64 * NV; t += kBlockA) {
+    for (int t = tid; NV > 1 && t < 64 * NV; t += kBlockA) {
       const int s = t / NV, vv = t % NV;
       const int c = p.slot_class[s];
       sh_oslot[t] = (s < p.nslots) ? make_double2(p.coef_obs[2 * (vv * nc + c)], p.coef_obs[2 * (vv * nc + c) + 1])
@@ -295,7 +300,11 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
       if (NV == 1) cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
       else cf = sh_slot[s * NV + v];
       acc = cfma(cf, t, acc);
-      if (kO) ko = cfma(sh_oslot[s * NV + v], make_double2(t.x, t.y), ko);  // staged value carries the sign
+      if (kO) {  // staged value carries the sign
+        const double2 co = NV == 1 ? make_double2(p.slot_coef_obs[2 * s], p.slot_coef_obs[2 * s + 1])
+                                   : sh_oslot[s * NV + v];
+        ko = cfma(co, make_double2(t.x, t.y), ko);
+      }
     }
     // up hops: whole source rows from global memory, uniform signed coefficients
     auto up_term = [&](uint32_t e, V t) {
@@ -382,7 +391,16 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.up_hops = db.up_hops;
   p.dn_tab = db.dn_tab;
   for (int s = 0; s < 64; ++s) p.slot_class[s] = db.slot_class[s];
-  for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef[k] = L.coef ? L.coef[k] : 0.0;
+  if (NV > 1) {
+    for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef[k] = L.coef ? L.coef[k] : 0.0;
+  } else {
+    for (int sl = 0; sl < 64; ++sl) {
+      const int c = db.slot_class[sl];
+      const bool ok = sl < db.nslots && L.coef_obs;
+      p.slot_coef_obs[2 * sl] = ok ? L.coef_obs[2 * c] : 0.0;
+      p.slot_coef_obs[2 * sl + 1] = ok ? L.coef_obs[2 * c + 1] : 0.0;
+    }
+  }
   for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef_obs[k] = L.coef_obs ? L.coef_obs[k] : 0.0;
   for (int s = 0; s < 64; ++s) {
     const int c = db.slot_class[s];
