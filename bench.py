@@ -215,10 +215,27 @@ def cpu_baseline(seconds: float) -> dict:
         el = time.perf_counter() - t_start
         if el >= seconds:
             break
+    # the oracle's H*v alone (m-independent): scipy CSR at A = 0.5, 1 thread
+    H = ham.H(0.5)
+    x = random_state(ham.dim, seed=1)[0]
+    H @ x
+    t1 = time.perf_counter()
+    nrep = 10
+    for _ in range(nrep):
+        H @ x
+    hv_ms = (time.perf_counter() - t1) / nrep * 1e3
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": steps / el, "unit": "midpoint steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} literal Alg.6 midpoint steps of the 12-site 3x4 workload from the "
                       f"oracle ground state (scipy CSR complex128, tol {w.tol:g}, dt {w.dt}, mean m "
-                      f"{float(np.mean(ms)):.2f}, {hv} H*v in {el:.1f} s, 1 thread)"}
+                      f"{float(np.mean(ms)):.2f}, {hv} H*v in {el:.1f} s, 1 thread)",
+            "hv_ms_1core": hv_ms, "hv_gbps_algorithmic_1core": 2 * ham.dim * 16 / (hv_ms * 1e-3) / 1e9,
+            "host_cpus": os.cpu_count(), "host_cpu_model": model}
 
 
 def batched_variants(hub, B, v0, w, steps: int) -> dict:
@@ -409,6 +426,171 @@ def large_tile_variant(hub, steps: int = 4) -> dict:
     return out
 
 
+def copy_bandwidth() -> dict:
+    """Measured device copy bandwidth (torch copy of 1 GiB, far beyond the
+    Infinity Cache): the practical ceiling the kernels are also compared with."""
+    import torch
+
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    gbps = 2 * nbytes / (ms * 1e-3) / 1e9
+    print(f"[bench] copy: {gbps:.0f} GB/s", file=sys.stderr, flush=True)
+    return {"bytes_read_plus_written": 2 * nbytes, "ms": ms, "gbps": gbps}
+
+
+def hv_variants(hub, B, copy_gbps: float, reps: int = 100) -> dict:
+    """Plain H*v at 12 sites (A = 0.5 fixed, seeded complex normal x): c128 and
+    c64, one vector and blocks of 8.  Per variant the kernel time per apply
+    (HIP events on every launch) and the algorithmic GB/s (2 B N s) with the
+    same buffers every time (working set in the Infinity Cache) and rotating
+    over distinct buffers totalling more than 2 x 256 MB (HBM-served)."""
+    import torch
+
+    out = {}
+    N = B.dim
+    for name, dtype, nv in (("c128x1", torch.complex128, 1), ("c64x1", torch.complex64, 1),
+                            ("c64x8", torch.complex64, 8), ("c128x8", torch.complex128, 8)):
+        es = 16 if dtype == torch.complex128 else 8
+        pair = 2 * nv * N * es
+        npairs = max(2, -(-(600 << 20) // pair))  # distinct x/y pairs above 600 MiB
+        g = torch.Generator(device="cuda:0").manual_seed(1)
+        xs = [torch.randn(nv * N, dtype=dtype, device="cuda:0", generator=g) for _ in range(npairs)]
+        ys = [torch.empty_like(xs[0]) for _ in range(npairs)]
+        A = [0.5] * nv
+        res = {"bytes_per_apply": pair, "buffers_rotated": npairs}
+        for mode in ("in_cache", "hbm_rotating"):
+            for r in range(10):  # untimed: same access pattern as the timed loop
+                k = 0 if mode == "in_cache" else r % npairs
+                hub.hub_apply_H(B.handle, A, xs[k], ys[k])
+            hub.hub_profile_enable(B.handle, 1)
+            hub.hub_profile_read(B.handle)
+            for r in range(reps):
+                k = 0 if mode == "in_cache" else r % npairs
+                hub.hub_apply_H(B.handle, A, xs[k], ys[k])
+            n, ms, bpl = hub.hub_profile_read(B.handle)
+            hub.hub_profile_enable(B.handle, 0)
+            # hub_profile counts one launch per vector group: per apply = n / reps groups
+            us = ms / reps * 1e3
+            gbps = pair / (us * 1e-6) / 1e9
+            res[mode] = {"us_per_apply": us, "gbps": gbps, "frac_of_8TBs": gbps / 8000.0,
+                         "frac_of_measured_copy": gbps / copy_gbps, "timed_kernel_launches": n}
+        out[name] = res
+        print(f"[bench] H*v {name}: {res['in_cache']['us_per_apply']:.1f} us in cache "
+              f"({res['in_cache']['gbps']:.0f} GB/s), {res['hbm_rotating']['us_per_apply']:.1f} us rotating "
+              f"({res['hbm_rotating']['gbps']:.0f} GB/s)", file=sys.stderr, flush=True)
+        del xs, ys
+        torch.cuda.empty_cache()
+    return out
+
+
+def greens_variant(hub) -> dict:
+    """Batched nonequilibrium Green's functions: the 10-site ring (U = 8, 5/5,
+    dim 63,504) from its ground state under the ring pulse; 64 members (c and
+    c^dag of both spins at sites 0, 3, 6, 9 from t' = 0.5, 1.0, 1.5, 2.0) in
+    the four N -/+ 1 sectors (dim 52,920 each), 400 relative steps of 0.01
+    each.  complex64 and complex128 runs (Krylov tol 1e-8): member-steps/s and
+    the complex64 overlaps' largest deviation from complex128."""
+    import numpy as np
+    import torch
+    from synth import workloads
+
+    w = workloads()["ring10_greens"]
+    B = hub.Basis(w.lattice, w.U, 5, 5)
+    T = [hub.Basis(w.lattice, w.U, *sec) for sec in ((4, 5), (6, 5), (5, 4), (5, 6))]
+    g = torch.empty(B.dim, dtype=torch.complex128, device="cuda:0")
+    hub.hub_ground_state(B.handle, hub.hub_pulse_A(w.pulse, 0.0), g, hub.make_opts(tol=1e-12, m_max=100))
+    members = [(site, spin, dagger, int(round(tp / w.dt)))
+               for spin, dagger in ((0, 1), (1, 1), (0, 0), (1, 0))
+               for site in w.extra["sites"] for tp in w.extra["t_primes"]]
+    n_rel = 400
+    opts = hub.make_opts(tol=1e-8, m_max=w.m_max)
+    res = {"members": len(members), "relative_steps": n_rel, "member_dim": int(T[0].dim)}
+    outs = {}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        psi = g.to(dtype).clone()
+        hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, 8, opts, members[:4],
+                            psi.clone())  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, n_rel, opts, members, psi)
+        el = time.perf_counter() - t0
+        outs[name] = o
+        res[name] = {"seconds": el, "member_steps_per_s": len(members) * n_rel / el}
+    res["max_abs_overlap_err_c64_vs_c128"] = float(np.max(np.abs(outs["c64"] - outs["c128"])))
+    print(f"[bench] greens: c64 {res['c64']['member_steps_per_s']:.0f} member-steps/s, c128 "
+          f"{res['c128']['member_steps_per_s']:.0f}; |dG| {res['max_abs_overlap_err_c64_vs_c128']:.1e}",
+          file=sys.stderr, flush=True)
+    for t in T:
+        t.close()
+    B.close()
+    return res
+
+
+def ring14_block_variant(hub, steps: int = 10) -> dict:
+    """14-site ring (7/7, dim 11,778,624; vectors far beyond the Infinity
+    Cache): a complex64 block of 8 pulse amplitudes (A0 = 0.1 .. 0.8) in one
+    hub_propagate call against complex128 single-vector calls, from a seeded
+    random state: member-steps/s of both and the complex64 block's largest
+    deviation in d(t) and E(t)/N_s from complex128 (same member)."""
+    import numpy as np
+    import torch
+    from synth import workloads, PulseParams
+
+    w = workloads()["ring14_block"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
+    pulses = [PulseParams(0, a, w.pulse.omega, w.pulse.t0, w.pulse.sigma) for a in w.extra["A0_batch"]]
+    g = torch.Generator(device="cuda:0").manual_seed(14)
+    x0 = torch.randn(B.dim, dtype=torch.complex128, device="cuda:0", generator=g)
+    x0 /= torch.linalg.vector_norm(x0)
+    opts = hub.make_opts(tol=1e-8, m_max=w.m_max)
+    res = {"dim": int(B.dim), "members": len(pulses), "steps": steps}
+    xb = x0.to(torch.complex64).repeat(len(pulses)).contiguous()
+    hub.hub_propagate(B.handle, pulses, 0.0, w.dt, 1, opts, xb.clone(), want_obs=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, obs64, log64 = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, steps, opts, xb)
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    del xb
+    torch.cuda.empty_cache()
+    obs128 = []
+    el128 = 0.0
+    for p in pulses:
+        x = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, o, lg = hub.hub_propagate(B.handle, [p], 0.0, w.dt, steps, opts, x)
+        torch.cuda.synchronize()
+        el128 += time.perf_counter() - t0
+        obs128.append(o[:, 0, :])
+        del x
+    obs128 = np.stack(obs128, axis=1)
+    res["c64_block8"] = {"seconds": el64, "member_steps_per_s": len(pulses) * steps / el64,
+                         "mean_krylov_m": float(np.mean(log64[:, :, 0]))}
+    res["c128_single"] = {"seconds": el128, "member_steps_per_s": len(pulses) * steps / el128}
+    res["max_abs_docc_err"] = float(np.max(np.abs(obs64[:, :, 3] - obs128[:, :, 3])))
+    res["max_abs_energy_per_site_err"] = float(np.max(np.abs(obs64[:, :, 2] - obs128[:, :, 2])))
+    print(f"[bench] ring14 block: c64x8 {res['c64_block8']['member_steps_per_s']:.1f} member-steps/s, c128 "
+          f"{res['c128_single']['member_steps_per_s']:.1f}; |dd| {res['max_abs_docc_err']:.1e}",
+          file=sys.stderr, flush=True)
+    B.close()
+    del x0
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_cpu_baseline_child(seconds: float) -> dict:
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -540,12 +722,17 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
     if not args.no_variants:
-        var = batched_variants(hub, B, v0, w, args.steps)
+        var = {}
+        var["copy"] = copy_bandwidth()
+        var["hv_12site"] = hv_variants(hub, B, var["copy"]["gbps"])
+        var.update(batched_variants(hub, B, v0, w, args.steps))
         var["synchronous_schedule"] = synchronous_variant(hub, B, w, v_start, t_start, args.steps, v, obs,
                                                           steps_per_s)
         var["controller"] = controller_variant(hub, B, w, v0, v_start, t_start, args.steps, v, obs, steps_per_s)
         var["cfet4"] = cfet4_variant(hub, B, w, v_start, t_start, args.steps, v, elapsed)
         var["large_tiles"] = large_tile_variant(hub)
+        var["greens_ring10"] = greens_variant(hub)
+        var["ring14_block"] = ring14_block_variant(hub)
         var["speedup_c64_batch8_vs_plain_c128"] = var["c64_batch8"]["member_steps_per_s"] / steps_per_s
         out["variants"] = var
     if not args.no_cpu_baseline:
