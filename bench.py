@@ -341,7 +341,7 @@ def synchronous_variant(hub, B, w, v_start, t_start: float, steps: int, v_plain,
     st, obs, log = hub.hub_propagate(B.handle, [w.pulse], t_start, w.dt, steps, opts, v)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    hub.hub_set_schedule(B.handle, 16, 1)
+    hub.hub_set_schedule(B.handle, 32, 1)
     same = bool(torch.equal(v, v_plain)) and bool(np.array_equal(obs, obs_plain))
     print(f"[bench] synchronous schedule: {steps / el:.0f} steps/s, bit-identical {same}", file=sys.stderr, flush=True)
     return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3,
@@ -703,7 +703,7 @@ def main() -> int:
                                "dt=0.005, tol=1e-10, ground-state start",
                    "A0": w.pulse.A0, "omega": w.pulse.omega, "t0": w.pulse.t0, "sigma": w.pulse.sigma,
                    "mean_krylov_m": mean_m,
-                   "schedule": {"kind": "chunked, 16 steps, margin 1", "chunks": sched["chunks"],
+                   "schedule": {"kind": "chunked, 32 steps, margin 1", "chunks": sched["chunks"],
                                 "fallback_steps": sched["fallbacks"],
                                 "lanczos_launches_per_step": sched["lanczos_launches"] / max(1, sched["steps"])}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

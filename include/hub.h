@@ -344,7 +344,7 @@ typedef struct {
 hub_status hub_controller_read_stats(hub_basis basis, hub_controller_stats *out);
 
 /* Schedule of hub_propagate when the learned controller is off.
- *   chunk >= 1 (default 16, margin 1): chunks of `chunk` steps are enqueued
+ *   chunk >= 1 (default 32, margin 1): chunks of `chunk` steps are enqueued
  *     without waiting for the host; every step of a chunk runs
  *     min(m_max, m_ref + margin) + 1 Lanczos launches, m_ref being the largest
  *     Krylov dimension of the previous chunk's steps (the first chunk:

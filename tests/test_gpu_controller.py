@@ -109,7 +109,7 @@ def _run(B, pulses, w, v0, prec, opts, params=None, chunk=8, margin=1, allow_nc=
                                          allow_not_converged=allow_nc)
     finally:
         hub.hub_controller_enable(B.handle, False)
-        hub.hub_set_schedule(B.handle, 16, 1)
+        hub.hub_set_schedule(B.handle, 32, 1)
     return st, v, obs, log, hub.hub_controller_read_stats(B.handle)
 
 

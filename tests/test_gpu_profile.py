@@ -65,7 +65,7 @@ def test_propagation_counts_only_launches_that_work(name, chunk):
         assert ms > 0
     finally:
         hub.hub_profile_enable(B.handle, 0)
-        hub.hub_set_schedule(B.handle, 16, 1)
+        hub.hub_set_schedule(B.handle, 32, 1)
         B.close()
 
 
@@ -92,5 +92,5 @@ def test_propagation_with_fallbacks():
         assert n < stats["lanczos_launches"]
     finally:
         hub.hub_profile_enable(B.handle, 0)
-        hub.hub_set_schedule(B.handle, 16, 1)
+        hub.hub_set_schedule(B.handle, 32, 1)
         B.close()

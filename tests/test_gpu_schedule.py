@@ -29,7 +29,7 @@ def _run(B, pulses, v0, dt, n_steps, opts, chunk, margin=1, allow_nc=False, t0=0
     try:
         st, obs, log = hub.hub_propagate(B.handle, pulses, t0, dt, n_steps, opts, v, allow_not_converged=allow_nc)
     finally:
-        hub.hub_set_schedule(B.handle, 16, 1)
+        hub.hub_set_schedule(B.handle, 32, 1)
     return st, v, obs, log, hub.hub_controller_read_stats(B.handle)
 
 
