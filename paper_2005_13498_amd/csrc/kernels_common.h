@@ -84,8 +84,11 @@ __device__ inline double reduce_column(const double* partials, int nrows, int nc
 
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+// acc + c s with the fused multiply-adds written out, so that every kernel
+// rounds a given sequence of terms the same way (the one- and two-pass
+// applies give bit-identical products whatever the compiler's contraction).
 template <typename V> __device__ __forceinline__ V cfma(V c, V s, V acc) {
-  return V{acc.x + c.x * s.x - c.y * s.y, acc.y + c.x * s.y + c.y * s.x};
+  return V{fma(-c.y, s.y, fma(c.x, s.x, acc.x)), fma(c.y, s.x, fma(c.x, s.y, acc.y))};
 }
 
 // ---------------------------------------------------------------------------
