@@ -178,13 +178,19 @@ def summarize_stats(trace_dir: str, out: str, command: str, top: int = 16) -> No
     print("\n".join(lines))
 
 
-def cpu_baseline(seconds: float) -> dict:
-    """Oracle timing on the host (run in a single-threaded child process)."""
+def cpu_baseline(seconds: float, member: int = -1) -> dict:
+    """Oracle timing on the host (run in a single-threaded child process).
+    member >= 0: only the midpoint steps of that member of the 8-pulse batch
+    (its A0 draw), for the all-cores figure."""
     import numpy as np
-    from synth import workloads, random_state
+    from synth import workloads, random_state, PulseParams
     from oracle import HubbardOracle, pulse_A, krylov_step_alg6
 
     w = workloads()["cluster3x4"]
+    if member >= 0:
+        p0 = w.pulse
+        w = w.__class__(**{**w.__dict__, "pulse": PulseParams(p0.kind, w.extra["A0_batch"][member], p0.omega,
+                                                                  p0.t0, p0.sigma)})
     ham = HubbardOracle(w.lattice, w.U, w.n_up, w.n_dn)
     hn = ham.norm_inf()
     import scipy.sparse.linalg as spla
@@ -215,6 +221,8 @@ def cpu_baseline(seconds: float) -> dict:
         el = time.perf_counter() - t_start
         if el >= seconds:
             break
+    if member >= 0:
+        return {"member": member, "steps_per_s": steps / el, "steps": steps}
     # the oracle's H*v alone (m-independent): scipy CSR at A = 0.5, 1 thread
     H = ham.H(0.5)
     x = random_state(ham.dim, seed=1)[0]
@@ -224,6 +232,21 @@ def cpu_baseline(seconds: float) -> dict:
     for _ in range(nrep):
         H @ x
     hv_ms = (time.perf_counter() - t1) / nrep * 1e3
+    # the latency case (8-site ring) on the oracle: literal Alg. 6 steps/s
+    w8 = workloads()["ring8"]
+    h8 = HubbardOracle(w8.lattice, w8.U, w8.n_up, w8.n_dn)
+    hn8 = h8.norm_inf()
+    _, vecs8 = spla.eigsh(h8.H(pulse_A(w8.pulse, 0.0)), k=1, which="SA", tol=1e-10,
+                          v0=random_state(h8.dim, seed=3)[0])
+    v8 = vecs8[:, 0].astype(np.complex128)
+    t8, n8 = 0.0, 0
+    t2 = time.perf_counter()
+    while n8 < w8.n_steps and time.perf_counter() - t2 < 5.0:
+        H8 = h8.H(pulse_A(w8.pulse, t8 + 0.5 * w8.dt))
+        v8, _ = krylov_step_alg6(lambda z: H8 @ z, v8, w8.dt, w8.m_max, w8.tol, hn8)
+        t8 += w8.dt
+        n8 += 1
+    ring8_sps = n8 / (time.perf_counter() - t2)
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -235,6 +258,7 @@ def cpu_baseline(seconds: float) -> dict:
                       f"oracle ground state (scipy CSR complex128, tol {w.tol:g}, dt {w.dt}, mean m "
                       f"{float(np.mean(ms)):.2f}, {hv} H*v in {el:.1f} s, 1 thread)",
             "hv_ms_1core": hv_ms, "hv_gbps_algorithmic_1core": 2 * ham.dim * 16 / (hv_ms * 1e-3) / 1e9,
+            "ring8_steps_per_s_1core": ring8_sps, "ring8_steps_timed": n8,
             "host_cpus": os.cpu_count(), "host_cpu_model": model}
 
 
@@ -426,6 +450,38 @@ def large_tile_variant(hub, steps: int = 4) -> dict:
     return out
 
 
+def ring8_variant(hub) -> dict:
+    """The latency case: 8-site ring (U = 8, 4/4, dim 4900) from its ground
+    state, 200 steps of 0.01 under the ring pulse, tol 1e-12, complex128
+    (a 157 KB apply: launch- and synchronisation-bound).  Steps/s with the
+    default and the synchronous schedule."""
+    import numpy as np
+    import torch
+    from synth import workloads
+
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
+    g = torch.empty(B.dim, dtype=torch.complex128, device="cuda:0")
+    hub.hub_ground_state(B.handle, hub.hub_pulse_A(w.pulse, 0.0), g, hub.make_opts(tol=1e-13, m_max=100))
+    opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+    res = {"dim": int(B.dim), "steps": w.n_steps}
+    for name, chunk in (("default", None), ("synchronous", 0)):
+        if chunk is not None:
+            hub.hub_set_schedule(B.handle, chunk, 0)
+        hub.hub_propagate(B.handle, [w.pulse], 0.0, w.dt, w.n_steps, opts, g.clone())  # warm-up
+        x = g.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, obs, log = hub.hub_propagate(B.handle, [w.pulse], 0.0, w.dt, w.n_steps, opts, x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"steps_per_s": w.n_steps / el, "mean_krylov_m": float(np.mean(log[:, 0, 0]))}
+    print(f"[bench] ring8: {res['default']['steps_per_s']:.0f} steps/s (synchronous "
+          f"{res['synchronous']['steps_per_s']:.0f})", file=sys.stderr, flush=True)
+    B.close()
+    return res
+
+
 def copy_bandwidth() -> dict:
     """Measured device copy bandwidth (torch copy of 1 GiB, far beyond the
     Infinity Cache): the practical ceiling the kernels are also compared with."""
@@ -591,6 +647,29 @@ def ring14_block_variant(hub, steps: int = 10) -> dict:
     return res
 
 
+def run_cpu_allcores(seconds: float) -> dict:
+    """All-cores oracle figure for the batched configuration: one single-threaded
+    oracle process per member of the 8-pulse batch (at most one per host CPU),
+    run side by side; member-steps/s summed."""
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    env["HIP_VISIBLE_DEVICES"] = ""
+    n = max(1, min(8, os.cpu_count() or 1))
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-seconds",
+                               str(seconds), "--cpu-member", str(k)], env=env, stdout=subprocess.PIPE,
+                              stderr=subprocess.PIPE, text=True) for k in range(n)]
+    out = []
+    for pr in procs:
+        so, se = pr.communicate(timeout=900)
+        if pr.returncode != 0:
+            return {"error": se[-500:]}
+        out.append(json.loads(so.strip().splitlines()[-1]))
+    total = sum(o["steps_per_s"] for o in out)
+    return {"processes": n, "member_steps_per_s": total, "unit": "member midpoint steps/s",
+            "sample": f"{n} oracle processes side by side, one batch member each, ~{seconds:.0f} s of steps each"}
+
+
 def run_cpu_baseline_child(seconds: float) -> dict:
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -613,6 +692,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-member", type=int, default=-1, help=argparse.SUPPRESS)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -623,7 +703,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline(args.cpu_seconds)))
+        print(json.dumps(cpu_baseline(args.cpu_seconds, args.cpu_member)))
         return 0
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, command=args.command)
@@ -724,6 +804,7 @@ def main() -> int:
     if not args.no_variants:
         var = {}
         var["copy"] = copy_bandwidth()
+        var["ring8"] = ring8_variant(hub)
         var["hv_12site"] = hv_variants(hub, B, var["copy"]["gbps"])
         var.update(batched_variants(hub, B, v0, w, args.steps))
         var["synchronous_schedule"] = synchronous_variant(hub, B, w, v_start, t_start, args.steps, v, obs,
@@ -738,6 +819,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = run_cpu_baseline_child(args.cpu_seconds)
+        out["cpu_baseline"]["allcores_batch8"] = run_cpu_allcores(10.0)
     B.close()
     print(json.dumps(out), flush=True)
     return 0
