@@ -7,6 +7,18 @@ HUB_C64) on the handle's GPU; torch supplies the memory and the stream.
 
 The library is loaded from this package directory (libhub.so, built by
 `paper_2005_13498_amd.build`).  If it is missing, every call raises.
+
+Typical use (12-site cluster, ground state, midpoint steps under a pulse):
+
+    import torch, paper_2005_13498_amd as hub
+    from synth import cluster_2d, PulseParams
+    B = hub.Basis(cluster_2d(3, 4), 8.0, 6, 6, device=0)
+    pulse = PulseParams(0, 0.9, 8.0, 2.5, 0.5)          # kind, A0, omega, t0, sigma
+    v = torch.empty(B.dim, dtype=torch.complex128, device="cuda:0")
+    hub.hub_ground_state(B.handle, hub.hub_pulse_A(pulse, 0.0), v, hub.make_opts(tol=1e-12, m_max=100))
+    st, obs, log = hub.hub_propagate(B.handle, [pulse], 0.0, 0.005, 1000, hub.make_opts(tol=1e-10), v)
+    # obs[n, k] = (t, norm, E/N_s, d) of member k at t = n dt; log[n, k, 0] = Krylov dimension m
+    B.close()
 """
 from __future__ import annotations
 
