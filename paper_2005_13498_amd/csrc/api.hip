@@ -96,8 +96,8 @@ struct hub_basis_s {
   float* ctrl_hfeat = nullptr;   // pinned host copies of the two
   float* ctrl_hout = nullptr;
   hub_controller_stats cstats{};
-  // profiling of the apply kernel
   int sched_chunk = 32, sched_margin = 1;  // default chunked schedule (chunk 0: synchronous)
+  // profiling of the apply kernel
   bool prof = false;
   int prof_period = 1;
   int64_t prof_count = 0;
