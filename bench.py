@@ -267,9 +267,12 @@ def batched_variants(hub, B, v0, w, steps: int) -> dict:
     8 pulse amplitudes (the seeded A0 draws), propagated by one hub_propagate
     call with 8 members in complex64 (FP64 Lanczos scalars) and in complex128
     (at this size the library runs the members as single vectors on the fused
-    two-pass kernels, which beat interleaved blocks); member-steps/s of both,
-    the timed iteration's GB/s, and the complex64 errors in d(t), E(t) against
-    the complex128 batch (max over members and sample times)."""
+    two-pass kernels, which beat interleaved blocks, on concurrent lanes);
+    member-steps/s of both (timed without apply timing, which would keep the
+    lanes sequential), the fused iteration's kernel time and GB/s from a
+    separate sequential run with apply timing, and the complex64 errors in
+    d(t), E(t) against the complex128 batch (max over members and sample
+    times)."""
     import numpy as np
     import torch
     from synth import PulseParams
@@ -283,13 +286,16 @@ def batched_variants(hub, B, v0, w, steps: int) -> dict:
         v = v0.to(dtype).repeat(nv).contiguous()
         hub.hub_propagate(B.handle, pulses, 0.0, w.dt, 5, opts, v, want_obs=False)  # warm-up
         v = v0.to(dtype).repeat(nv).contiguous()
-        hub.hub_profile_enable(B.handle, PROFILE_PERIOD)
-        hub.hub_profile_read(B.handle)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st, o, log = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, steps, opts, v)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        # kernel time of the fused iteration: a shorter sequential run with apply timing
+        hub.hub_profile_enable(B.handle, PROFILE_PERIOD // 4)
+        hub.hub_profile_read(B.handle)
+        hub.hub_propagate(B.handle, pulses, 0.0, w.dt, max(50, steps // 10), opts,
+                          v0.to(dtype).repeat(nv).contiguous(), want_obs=False)
         launches, kms, bpl = hub.hub_profile_read(B.handle)
         hub.hub_profile_enable(B.handle, False)
         us = kms / max(launches, 1) * 1e3

@@ -188,7 +188,13 @@ hub_status hub_krylov_expm_step(hub_basis basis, const double *A_mid, double dt,
  * first step where a vector hits m_max; v_inout then holds that step's
  * m_max approximation.  The schedule (hub_set_schedule,
  * hub_controller_enable) changes how the launches overlap the host, never the
- * result.  Synchronises `stream`. */
+ * result.  The library propagates the vectors in groups (interleaved blocks,
+ * or single vectors where the two-pass kernels apply); several groups run
+ * concurrently on up to 4 lanes, each with its own workspace, stream and host
+ * thread, started after the work already on `stream` (not while apply timing
+ * or the learned controller is enabled, and not beyond 48 GiB of Krylov
+ * workspace).  Results do not depend on this; with concurrent groups each
+ * group stops at its own first m_max step.  Synchronises `stream`. */
 hub_status hub_propagate(hub_basis basis, const hub_pulse *pulses, double t_start, double dt,
                          int32_t n_steps, const hub_krylov_opts *opts, hub_prec prec,
                          int32_t nvec, void *v_inout, hub_obs *obs, hub_step_info *log,

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
+#include <thread>
 #include <array>
 #include <cmath>
 #include <complex>
@@ -66,12 +68,12 @@ struct ProfSample {
   int worked = 1;              // 0: launched past the Krylov decision (exits at once); -1: not yet known
 };
 
-struct hub_basis_s {
-  hub::Basis B;
-  DevBasis D;
-  int device = 0;
-  std::vector<void*> allocs;  // table allocations
-  // workspace
+// Device workspace of one propagation lane.  The handle's own lane (w)
+// serves every entry point; a propagation of several vector groups runs the
+// groups on up to kMaxLanes lanes at once, each extra lane with its own
+// workspace and stream (HIP keeps the per-lane kernels independent, so
+// latency-bound applies of different groups overlap on the GPU).
+struct Work {
   void* slots = nullptr;
   size_t slots_bytes = 0;
   void* blockbuf = nullptr;
@@ -86,6 +88,22 @@ struct hub_basis_s {
   size_t partials_e_bytes = 0;
   double* scal = nullptr;         // device scalars [kMMax*2 + 16]
   double* rcoef = nullptr;        // device re-orthogonalisation coefficients [kMMax + 1][kMaxNV] complex
+  hipStream_t stream = nullptr;   // extra lanes: their own stream (lane 0 runs on the caller's)
+  hub_controller_stats cstats{};  // schedule counters of this lane's runs (folded into the handle's)
+};
+
+constexpr int kMaxLanes = 4;
+// Extra lanes are used only while all lanes' Krylov workspaces together stay
+// below this many bytes of device memory.
+constexpr size_t kLaneWorkBudget = size_t(48) << 30;
+
+struct hub_basis_s {
+  hub::Basis B;
+  DevBasis D;
+  int device = 0;
+  std::vector<void*> allocs;  // table allocations
+  Work w;                     // lane 0
+  std::vector<std::unique_ptr<Work>> lanes;  // extra lanes, created on demand
   int rows_c128 = 1, rows_c64 = 1;
   // learned Krylov controller
   bool ctrl_on = false, ctrl_loaded = false;
@@ -130,21 +148,53 @@ hub_status upload(hub_basis h, T** dst, const std::vector<T>& src) {
 
 int pick_rows(const hub_basis, int) { return 1; }  // one tile row per apply workgroup
 
-hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t blockbuf_bytes) {
+// Fixed-size part of a lane's workspace (the rest grows in ensure_workspace);
+// an extra lane also gets its own stream (default priority).
+hub_status work_init(Work& W, bool own_stream) {
+  if (hipMalloc(reinterpret_cast<void**>(&W.slot_ptrs), (kMMax + 2) * sizeof(void*)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&W.st), kMaxNV * sizeof(VecState)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&W.ctl), sizeof(StepCtl)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&W.scal), (2 * kMMax + 64) * sizeof(double) * 2) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&W.rcoef), (kMMax + 1) * kMaxNV * 2 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&W.h_ctl), sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
+    return fail(HUB_E_NOMEM, "workspace allocation failed");
+  if (hipMemset(W.ctl, 0, sizeof(StepCtl)) != hipSuccess || hipMemset(W.st, 0, kMaxNV * sizeof(VecState)) != hipSuccess)
+    return fail(HUB_E_DEVICE, "workspace initialisation failed");
+  if (own_stream && hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(HUB_E_DEVICE, "stream creation failed");
+  return HUB_OK;
+}
+
+void work_free(Work& W) {
+  if (W.slots) (void)hipFree(W.slots);
+  if (W.blockbuf) (void)hipFree(W.blockbuf);
+  if (W.slot_ptrs) (void)hipFree(W.slot_ptrs);
+  if (W.st) (void)hipFree(W.st);
+  if (W.ctl) (void)hipFree(W.ctl);
+  if (W.partials_e) (void)hipFree(W.partials_e);
+  if (W.scal) (void)hipFree(W.scal);
+  if (W.rcoef) (void)hipFree(W.rcoef);
+  if (W.partials) (void)hipFree(W.partials);
+  if (W.h_ctl) (void)hipHostFree(W.h_ctl);
+  if (W.stream) (void)hipStreamDestroy(W.stream);
+  W = Work{};
+}
+
+hub_status ensure_workspace(hub_basis h, Work& W, size_t slot_bytes, int nslots, size_t blockbuf_bytes) {
   const size_t need = slot_bytes * static_cast<size_t>(nslots);
-  if (need > h->slots_bytes) {
-    if (h->slots) HUB_HIP(hipFree(h->slots));
-    h->slots = nullptr;
-    h->slots_bytes = 0;
-    HUB_HIP(hipMalloc(&h->slots, need));
-    h->slots_bytes = need;
+  if (need > W.slots_bytes) {
+    if (W.slots) HUB_HIP(hipFree(W.slots));
+    W.slots = nullptr;
+    W.slots_bytes = 0;
+    HUB_HIP(hipMalloc(&W.slots, need));
+    W.slots_bytes = need;
   }
-  if (blockbuf_bytes > h->blockbuf_bytes) {
-    if (h->blockbuf) HUB_HIP(hipFree(h->blockbuf));
-    h->blockbuf = nullptr;
-    h->blockbuf_bytes = 0;
-    HUB_HIP(hipMalloc(&h->blockbuf, blockbuf_bytes));
-    h->blockbuf_bytes = blockbuf_bytes;
+  if (blockbuf_bytes > W.blockbuf_bytes) {
+    if (W.blockbuf) HUB_HIP(hipFree(W.blockbuf));
+    W.blockbuf = nullptr;
+    W.blockbuf_bytes = 0;
+    HUB_HIP(hipMalloc(&W.blockbuf, blockbuf_bytes));
+    W.blockbuf_bytes = blockbuf_bytes;
   }
   // partial sums of an apply: grid * (1 + kObsQ) * nv doubles at most
   // (also the CGS inner-product partials: elem_grid * (kMMax + 1) * 2 * nv)
@@ -155,23 +205,27 @@ hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t b
   // two-pass regions: column-pass partials, row-pass obs partials, row norms
   pb = std::max(pb, (2 * static_cast<size_t>(hub::colpass_grid(h->D)) +
                      static_cast<size_t>(h->D.dim_up) * (kObsQ + 1)) * sizeof(double));
-  if (pb > h->partials_bytes) {
-    if (h->partials) HUB_HIP(hipFree(h->partials));
-    h->partials = nullptr;
-    h->partials_bytes = 0;
-    HUB_HIP(hipMalloc(&h->partials, pb));
-    h->partials_bytes = pb;
+  if (pb > W.partials_bytes) {
+    if (W.partials) HUB_HIP(hipFree(W.partials));
+    W.partials = nullptr;
+    W.partials_bytes = 0;
+    HUB_HIP(hipMalloc(&W.partials, pb));
+    W.partials_bytes = pb;
   }
   // elementwise partials: elem_grid (<= 1024) rows of up to 2 * 64 columns
   const size_t pe = static_cast<size_t>(1024) * 2 * 64 * sizeof(double);
-  if (pe > h->partials_e_bytes) {
-    if (h->partials_e) HUB_HIP(hipFree(h->partials_e));
-    h->partials_e = nullptr;
-    h->partials_e_bytes = 0;
-    HUB_HIP(hipMalloc(&h->partials_e, pe));
-    h->partials_e_bytes = pe;
+  if (pe > W.partials_e_bytes) {
+    if (W.partials_e) HUB_HIP(hipFree(W.partials_e));
+    W.partials_e = nullptr;
+    W.partials_e_bytes = 0;
+    HUB_HIP(hipMalloc(&W.partials_e, pe));
+    W.partials_e_bytes = pe;
   }
   return HUB_OK;
+}
+
+hub_status ensure_workspace(hub_basis h, size_t slot_bytes, int nslots, size_t blockbuf_bytes) {
+  return ensure_workspace(h, h->w, slot_bytes, nslots, blockbuf_bytes);
 }
 
 void coef_for(const hub::Basis& B, double A, double* out /* 2*nc */) {
@@ -357,13 +411,13 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
                      const std::vector<double>& coef_mid, double dt, const hub_krylov_opts& o,
                      bool want_obs, const std::vector<double>* coef_obs, std::vector<double>* obs_out,
                      std::vector<StepReport>* reports, hipStream_t stream, bool* not_converged,
-                     int* steps_done, const CtrlInputs* ctrl) {
+                     int* steps_done, const CtrlInputs* ctrl, Work& W) {
   const size_t es = elem_bytes(prec);
   const int64_t dim = h->D.dim;
   const size_t vbytes = static_cast<size_t>(dim) * nv * es;
   const int nc = static_cast<int>(h->B.classes.size());
   const int pi = prec == HUB_C128 ? 0 : 1;
-  hub_status s = ensure_workspace(h, vbytes, o.m_max, nv > 1 ? vbytes : 0);
+  hub_status s = ensure_workspace(h, W, vbytes, o.m_max, nv > 1 ? vbytes : 0);
   if (s != HUB_OK) return s;
   // timed applies of this call: when the event pool runs low, their kernel
   // times are read at the next synchronisation (so the events are reused);
@@ -371,19 +425,19 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   const size_t prof_s0 = h->prof_samples.size();
   size_t prof_hv = prof_s0;
   auto harvest = [&]() -> hub_status {
-    if (h->ev_free.size() >= kProfLowWater) return HUB_OK;
+    if (!h->prof || h->ev_free.size() >= kProfLowWater) return HUB_OK;
     return prof_harvest(h, prof_hv, &prof_hv);
   };
 
   void* slot0 = user;
   if (nv > 1) {
-    slot0 = h->blockbuf;
+    slot0 = W.blockbuf;
     HUB_HIP(hub::launch_interleave(pi, nv, dim, user, slot0, true, stream));
   }
   std::vector<void*> ptrs(kMMax + 2, nullptr);
   ptrs[0] = slot0;
-  for (int k = 1; k <= o.m_max; ++k) ptrs[k] = static_cast<char*>(h->slots) + (k - 1) * vbytes;
-  HUB_HIP(hipMemcpyAsync(h->slot_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice,
+  for (int k = 1; k <= o.m_max; ++k) ptrs[k] = static_cast<char*>(W.slots) + (k - 1) * vbytes;
+  HUB_HIP(hipMemcpyAsync(W.slot_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice,
                          stream));
   // the copy above reads `ptrs` asynchronously: wait before it goes out of scope
   HUB_HIP(hipStreamSynchronize(stream));
@@ -406,7 +460,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   } freer{dlog, dobs};
 
   StepCtl ctl0{};
-  HUB_HIP(hipMemcpyAsync(h->ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
+  HUB_HIP(hipMemcpyAsync(W.ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
   HUB_HIP(hipStreamSynchronize(stream));
 
   // each of the scheme's exponentials exp(-i (dt/E) H_e) is split into
@@ -419,13 +473,13 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   L.prec = pi;
   L.nv = nv;
   L.rows = rows;
-  L.st = h->st;
-  L.ctl = h->ctl;
+  L.st = W.st;
+  L.ctl = W.ctl;
   L.m_max = o.m_max;
   L.tol = o.tol;
   L.norm_inf = h->B.norm_inf;
-  L.partials = h->partials;
-  L.prev_partials = h->partials_e;
+  L.partials = W.partials;
+  L.prev_partials = W.partials_e;
   L.prev_nblk = hub::elem_grid(dim * nv);
   L.stream = stream;
 
@@ -446,7 +500,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     // the column pass's
     const bool two_obs = A.obs && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
     const size_t cg2 = 2 * static_cast<size_t>(hub::colpass_grid(h->D));
-    if (two_obs) A.row_obs = h->partials + cg2;
+    if (two_obs) A.row_obs = W.partials + cg2;
     // From the second iteration on, the two-pass row pass also finishes the
     // previous update (u_j = w_{j-1} - alpha s u_{j-1}) and the column pass
     // takes the decision, so no separate update kernel runs in between
@@ -456,30 +510,30 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     if (A.fuse) {
       const bool after_obs = jj == 1 && want_obs && sub == 0 &&
                              hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
-      A.alpha_partials = h->partials;
+      A.alpha_partials = W.partials;
       A.alpha_nblk = hub::colpass_grid(h->D);
       A.alpha_stride = after_obs ? hub::apply_nq_two_pass(true) : 1;
-      A.obs_row = after_obs ? h->partials + cg2 : nullptr;
-      A.norm_partials = h->partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ;
+      A.obs_row = after_obs ? W.partials + cg2 : nullptr;
+      A.norm_partials = W.partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ;
     }
     int agrid = 0;  // workgroups that wrote the apply's partial sums
     hub_status r = launch_apply_timed(h, A, &agrid, fusable, n, sub);
     if (r != HUB_OK) return r;
     const bool next_fused = fusable;  // every later iteration finishes this update itself
     if (jj < o.m_max && !next_fused) {
-      HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], h->st, h->ctl, jj, h->partials, agrid,
+      HUB_HIP(hub::launch_update(pi, nv, dim, ptrs[jj + 1], ptrs[jj], W.st, W.ctl, jj, W.partials, agrid,
                                  two_obs ? hub::apply_nq_two_pass(true) : hub::apply_nq(hub::kLanczos, A.obs, nc),
-                                 two_obs ? A.row_obs : nullptr, h->D.dim_up, h->partials_e, stream));
+                                 two_obs ? A.row_obs : nullptr, h->D.dim_up, W.partials_e, stream));
       if (o.reorth)  // CGS2: two Gram-Schmidt passes against u_0..u_j
         for (int pass = 0; pass < 2; ++pass)
-          HUB_HIP(hub::launch_reorth(pi, nv, dim, h->slot_ptrs, jj, h->st, h->ctl, h->partials, h->rcoef,
-                                     h->partials_e, stream));
+          HUB_HIP(hub::launch_reorth(pi, nv, dim, W.slot_ptrs, jj, W.st, W.ctl, W.partials, W.rcoef,
+                                     W.partials_e, stream));
     }
     return HUB_OK;
   };
   auto finish_sub = [&](int n, int sub) -> hub_status {
-    HUB_HIP(hub::launch_combine(pi, nv, dim, h->slot_ptrs, h->st, h->ctl, h->partials_e, stream));
-    HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, dlog_c + (static_cast<size_t>(n) * S + sub) * nv,
+    HUB_HIP(hub::launch_combine(pi, nv, dim, W.slot_ptrs, W.st, W.ctl, W.partials_e, stream));
+    HUB_HIP(hub::launch_step_log(nv, W.st, W.ctl, dlog_c + (static_cast<size_t>(n) * S + sub) * nv,
                                  (want_obs && sub == 0) ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr,
                                  kObsQ, stream));
     return HUB_OK;
@@ -499,7 +553,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     for (int sub = sub0; sub < S; ++sub) {
       // later substeps need no step_begin: tau is set, k_combine left the
       // |v|^2 partials and k_step_log cleared the control block
-      if (first) HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, true, h->partials_e, stream));
+      if (first) HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, W.st, W.ctl, tau, true, W.partials_e, stream));
       first = false;
       int j = 0;
       for (; j <= m_pred && j <= o.m_max; ++j) {
@@ -507,16 +561,16 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         if (r != HUB_OK) return r;
       }
       while (true) {
-        HUB_HIP(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
+        HUB_HIP(hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
         HUB_HIP(hipStreamSynchronize(stream));
-        if (h->h_ctl->all_done) break;
+        if (W.h_ctl->all_done) break;
         if (j > o.m_max) return fail(HUB_E_DEVICE, "Krylov loop ended without a decision");
         hub_status r = enqueue_iter(n, sub, j);
         if (r != HUB_OK) return r;
         ++j;
       }
-      m_step_max = std::max(m_step_max, static_cast<int>(h->h_ctl->iter));
-      *maxed = h->h_ctl->any_maxed != 0;
+      m_step_max = std::max(m_step_max, static_cast<int>(W.h_ctl->iter));
+      *maxed = W.h_ctl->any_maxed != 0;
       hub_status r = harvest();
       if (r != HUB_OK) return r;
       r = finish_sub(n, sub);
@@ -601,14 +655,14 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         HUB_HIP(hipMemcpyAsync(h->ctrl_hout, h->ctrl_out, static_cast<size_t>(rows) * HUB_MLP_OUT * sizeof(float),
                                hipMemcpyDeviceToHost, stream));
       }
-      StepCtl c0 = *h->h_ctl;
+      StepCtl c0 = *W.h_ctl;
       c0.abort = 0;
       c0.steps_done = 0;
       c0.all_done = 0;
       c0.any_maxed = 0;
       c0.iter = 0;
-      *h->h_ctl = c0;
-      HUB_HIP(hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
+      *W.h_ctl = c0;
+      HUB_HIP(hipMemcpyAsync(W.ctl, W.h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
       if (learned) {
         HUB_HIP(hipStreamSynchronize(stream));  // the predictions
         for (int k = 0; k < K; ++k) {
@@ -638,7 +692,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       for (int k = 0; k < K; ++k)
         for (int sub = 0; sub < S; ++sub) {
           if (first)
-            HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, h->st, h->ctl, tau, true, h->partials_e, stream));
+            HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, W.st, W.ctl, tau, true, W.partials_e, stream));
           first = false;
           for (int j = 0; j < L_of[k] && j <= o.m_max; ++j) {
             hub_status r = enqueue_iter(n + k, sub, j);
@@ -646,14 +700,14 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
           }
           hub_status r = finish_sub(n + k, sub);
           if (r != HUB_OK) return r;
-          h->cstats.lanczos_launches += std::min(L_of[k], o.m_max + 1);
+          W.cstats.lanczos_launches += std::min(L_of[k], o.m_max + 1);
         }
-      HUB_HIP(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
+      HUB_HIP(hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
       { hub_status r = fetch_logs(n, n + K); if (r != HUB_OK) return r; }
       HUB_HIP(hipStreamSynchronize(stream));
       { hub_status r = harvest(); if (r != HUB_OK) return r; }
-      h->cstats.chunks += 1;
-      const int done_sub = h->h_ctl->steps_done;
+      W.cstats.chunks += 1;
+      const int done_sub = W.h_ctl->steps_done;
       const int complete = std::min(K, done_sub / S);
       bool maxed = false;
       for (int k = 0; k < complete && !maxed; ++k)
@@ -663,9 +717,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
           step_hist(n + k, v, &e, &mm);
           for (int sub = 0; sub < S; ++sub)
             maxed |= hlog[(static_cast<size_t>(n + k) * S + sub) * nv + v].status == 3;
-          h->cstats.iterations += mm;
+          W.cstats.iterations += mm;
         }
-      h->cstats.steps += complete;
+      W.cstats.steps += complete;
       *steps_done = n + complete;
       if (maxed) {  // a vector hit m_max: the device stopped after that step
         int k = 0;
@@ -679,7 +733,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         *not_converged = true;
         break;
       }
-      if (h->h_ctl->abort == 0) {
+      if (W.h_ctl->abort == 0) {
         n += K;
         continue;
       }
@@ -689,14 +743,14 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         ProfSample& p = h->prof_samples[i];
         if (p.n > nb || (p.n == nb && p.sub > done_sub % S)) p.worked = 0;
       }
-      StepCtl c1 = *h->h_ctl;
+      StepCtl c1 = *W.h_ctl;
       c1.abort = 0;
       c1.all_done = 0;
       c1.any_maxed = 0;
       c1.iter = 0;
       c1.steps_done = 0;
-      *h->h_ctl = c1;
-      HUB_HIP(hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
+      *W.h_ctl = c1;
+      HUB_HIP(hipMemcpyAsync(W.ctl, W.h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
       first = true;  // the abandoned step overwrote the |v|^2 partials
       int mp = 0;
       for (int v = 0; v < nv; ++v) {
@@ -713,7 +767,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       r = fetch_logs(nb, nb + 1);
       if (r != HUB_OK) return r;
       HUB_HIP(hipStreamSynchronize(stream));
-      h->cstats.fallbacks += 1;
+      W.cstats.fallbacks += 1;
       *steps_done = nb + 1;
       if (mx) {
         *not_converged = true;
@@ -725,8 +779,8 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   // observables at the final sample time
   if (want_obs && *steps_done == n_steps) {
     StepCtl c2 = StepCtl{};  // clear a stop flag left by the last step
-    *h->h_ctl = c2;
-    HUB_HIP(hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
+    *W.h_ctl = c2;
+    HUB_HIP(hipMemcpyAsync(W.ctl, W.h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
     hub::ApplyLaunch A = L;
     A.mode = hub::kObsOnly;
     A.obs = true;
@@ -737,8 +791,8 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.j = 0;
     int ogrid = 0;
     HUB_HIP(hub::launch_apply(A, &ogrid));
-    HUB_HIP(hub::launch_finalize_obs(nv, h->partials, ogrid, hub::apply_nq(hub::kObsOnly, true, nc), h->st, stream));
-    HUB_HIP(hub::launch_step_log(nv, h->st, h->ctl, nullptr, dobs + static_cast<size_t>(n_steps) * nv * kObsQ,
+    HUB_HIP(hub::launch_finalize_obs(nv, W.partials, ogrid, hub::apply_nq(hub::kObsOnly, true, nc), W.st, stream));
+    HUB_HIP(hub::launch_step_log(nv, W.st, W.ctl, nullptr, dobs + static_cast<size_t>(n_steps) * nv * kObsQ,
                                  kObsQ, stream));
   }
   if (nv > 1) HUB_HIP(hub::launch_interleave(pi, nv, dim, slot0, user, false, stream));
@@ -890,16 +944,7 @@ hub_status hub_basis_create(const hub_lattice* lat, int32_t n_up, int32_t n_dn, 
   D.up_maxs_pad = B.up.maxs_pad;
   for (int k = 0; k < 64; ++k) D.up_slot_class[k] = B.up.slot_class[k];
 
-  if (hipMalloc(reinterpret_cast<void**>(&h->slot_ptrs), (kMMax + 2) * sizeof(void*)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&h->st), kMaxNV * sizeof(VecState)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&h->ctl), sizeof(StepCtl)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&h->scal), (2 * kMMax + 64) * sizeof(double) * 2) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&h->rcoef), (kMMax + 1) * kMaxNV * 2 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
-    return cleanup(fail(HUB_E_NOMEM, "workspace allocation failed"));
-  if (hipMemset(h->ctl, 0, sizeof(StepCtl)) != hipSuccess ||
-      hipMemset(h->st, 0, kMaxNV * sizeof(VecState)) != hipSuccess)
-    return cleanup(fail(HUB_E_DEVICE, "workspace initialisation failed"));
+  if ((s = work_init(h->w, false)) != HUB_OK) return cleanup(s);
   h->rows_c128 = pick_rows(h, 0);
   h->rows_c64 = pick_rows(h, 1);
   *out = h;
@@ -916,16 +961,8 @@ void hub_basis_destroy(hub_basis h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   for (void* p : h->allocs) (void)hipFree(p);
-  if (h->slots) (void)hipFree(h->slots);
-  if (h->blockbuf) (void)hipFree(h->blockbuf);
-  if (h->slot_ptrs) (void)hipFree(h->slot_ptrs);
-  if (h->st) (void)hipFree(h->st);
-  if (h->ctl) (void)hipFree(h->ctl);
-  if (h->partials_e) (void)hipFree(h->partials_e);
-  if (h->scal) (void)hipFree(h->scal);
-  if (h->rcoef) (void)hipFree(h->rcoef);
-  if (h->partials) (void)hipFree(h->partials);
-  if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  work_free(h->w);
+  for (auto& l : h->lanes) work_free(*l);
   if (h->ctrl_params) (void)hipFree(h->ctrl_params);
   if (h->ctrl_feat) (void)hipFree(h->ctrl_feat);
   if (h->ctrl_out) (void)hipFree(h->ctrl_out);
@@ -1027,12 +1064,12 @@ hub_status hub_apply_H(hub_basis h, const double* A, hub_prec prec, int32_t nvec
       s = launch_apply_timed(h, L);
       if (s != HUB_OK) return s;
     } else {
-      HUB_HIP(hub::launch_interleave(pi, nv, dim, xin, h->blockbuf, true, st));
-      L.x = h->blockbuf;
-      L.y = h->slots;
+      HUB_HIP(hub::launch_interleave(pi, nv, dim, xin, h->w.blockbuf, true, st));
+      L.x = h->w.blockbuf;
+      L.y = h->w.slots;
       s = launch_apply_timed(h, L);
       if (s != HUB_OK) return s;
-      HUB_HIP(hub::launch_interleave(pi, nv, dim, h->slots, yout, false, st));
+      HUB_HIP(hub::launch_interleave(pi, nv, dim, h->w.slots, yout, false, st));
     }
     k0 += nv;
   }
@@ -1064,22 +1101,22 @@ hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t 
     L.x = static_cast<const char*>(v) + static_cast<size_t>(k) * dim * es;
     L.coef = cf.data();
     L.coef_obs = cf.data();
-    L.st = h->st;
-    L.ctl = h->ctl;
-    L.partials = h->partials;
+    L.st = h->w.st;
+    L.ctl = h->w.ctl;
+    L.partials = h->w.partials;
     L.stream = st;
     int grid = 0;
     HUB_HIP(hub::launch_apply(L, &grid));
-    HUB_HIP(hub::launch_finalize_obs(1, h->partials, grid, hub::apply_nq(hub::kObsOnly, true, nc), h->st, st));
+    HUB_HIP(hub::launch_finalize_obs(1, h->w.partials, grid, hub::apply_nq(hub::kObsOnly, true, nc), h->w.st, st));
     double o[kObsQ];
-    HUB_HIP(hipMemcpyAsync(o, reinterpret_cast<char*>(h->st) + offsetof(VecState, obs), sizeof(o),
+    HUB_HIP(hipMemcpyAsync(o, reinterpret_cast<char*>(h->w.st) + offsetof(VecState, obs), sizeof(o),
                            hipMemcpyDeviceToHost, st));
     HUB_HIP(hipStreamSynchronize(st));
     fill_obs(h->B, o, 0.0, &out[k]);
     out[k].t = 0.0;
     if (site_docc) {
-      HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, h->scal, h->partials_e, st));
-      HUB_HIP(hipMemcpyAsync(site_docc + static_cast<size_t>(k) * h->D.n_sites, h->scal,
+      HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, h->w.scal, h->w.partials_e, st));
+      HUB_HIP(hipMemcpyAsync(site_docc + static_cast<size_t>(k) * h->D.n_sites, h->w.scal,
                              h->D.n_sites * sizeof(double), hipMemcpyDeviceToHost, st));
       HUB_HIP(hipStreamSynchronize(st));
     }
@@ -1100,66 +1137,153 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
   const int64_t dim = h->D.dim;
   const int nc = h->D.nc;
   const std::vector<int> groups = groups_for(h, nvec, pi);
-  bool any_nc = false;
-  int k0 = 0;
-  for (int nv : groups) {
-    // hop coefficients of every exponential of every step: [n][e][v][2 nc]
-    const int E = scheme_exps(o);
-    std::vector<double> cm(static_cast<size_t>(n_steps) * E * nv * 2 * nc);
+  const bool want_obs = obs != nullptr && A_sample != nullptr;
+  const int E = scheme_exps(o);
+
+  // host inputs of every group: hop coefficients of every exponential of
+  // every step [n][e][v][2 nc], at the sample times [n][v][2 nc], controller rows
+  struct GroupRun {
+    int nv = 0, k0 = 0;
+    std::vector<double> cm, co;
+    CtrlInputs ci;
+    std::vector<double> obs_raw;
+    std::vector<StepReport> reps;
+    bool ncv = false, ran = false;
+    int done = 0;
+    hub_status s = HUB_OK;
+    std::string err;
+  };
+  std::vector<GroupRun> runs(groups.size());
+  for (size_t g = 0, k0 = 0; g < groups.size(); k0 += groups[g], ++g) {
+    GroupRun& R = runs[g];
+    const int nv = groups[g];
+    R.nv = nv;
+    R.k0 = static_cast<int>(k0);
+    R.cm.assign(static_cast<size_t>(n_steps) * E * nv * 2 * nc, 0.0);
     for (int n = 0; n < n_steps; ++n)
       for (int v = 0; v < nv; ++v) {
         if (E == 1) {
-          coef_for(h->B, A_mid[k0 + v][n], cm.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
+          coef_for(h->B, A_mid[k0 + v][n], R.cm.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
           continue;
         }
         double c1[2 * kMaxClasses], c2[2 * kMaxClasses];
         coef_for(h->B, (*A_gauss)[k0 + v][2 * n], c1);
         coef_for(h->B, (*A_gauss)[k0 + v][2 * n + 1], c2);
-        double* e0 = cm.data() + ((static_cast<size_t>(n) * E + 0) * nv + v) * 2 * nc;  // applied first
-        double* e1 = cm.data() + ((static_cast<size_t>(n) * E + 1) * nv + v) * 2 * nc;
+        double* e0 = R.cm.data() + ((static_cast<size_t>(n) * E + 0) * nv + v) * 2 * nc;  // applied first
+        double* e1 = R.cm.data() + ((static_cast<size_t>(n) * E + 1) * nv + v) * 2 * nc;
         for (int k = 0; k < 2 * nc; ++k) {
           e0[k] = 2.0 * (kCf4A2 * c1[k] + kCf4A1 * c2[k]);
           e1[k] = 2.0 * (kCf4A1 * c1[k] + kCf4A2 * c2[k]);
         }
       }
-    const bool want_obs = obs != nullptr && A_sample != nullptr;
-    // hop coefficients at the sample times t_start + n dt, n = 0..n_steps
-    std::vector<double> co;
     if (want_obs) {
-      co.assign(static_cast<size_t>(n_steps + 1) * nv * 2 * nc, 0.0);
+      R.co.assign(static_cast<size_t>(n_steps + 1) * nv * 2 * nc, 0.0);
       for (int n = 0; n <= n_steps; ++n)
         for (int v = 0; v < nv; ++v)
-          coef_for(h->B, (*A_sample)[k0 + v][n], co.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
+          coef_for(h->B, (*A_sample)[k0 + v][n], R.co.data() + (static_cast<size_t>(n) * nv + v) * 2 * nc);
     }
-    std::vector<double> obs_raw;
-    std::vector<StepReport> reps;
-    bool ncv = false;
-    int done = 0;
-    char* user = static_cast<char*>(v_inout) + static_cast<size_t>(k0) * dim * es;
-    CtrlInputs ci;
     if (dA_mid) {
-      ci.A_mid.resize(static_cast<size_t>(n_steps) * nv);
-      ci.dA_mid.resize(static_cast<size_t>(n_steps) * nv);
+      R.ci.A_mid.resize(static_cast<size_t>(n_steps) * nv);
+      R.ci.dA_mid.resize(static_cast<size_t>(n_steps) * nv);
       for (int n = 0; n < n_steps; ++n)
         for (int v = 0; v < nv; ++v) {
-          ci.A_mid[static_cast<size_t>(n) * nv + v] = A_mid[k0 + v][n];
-          ci.dA_mid[static_cast<size_t>(n) * nv + v] = (*dA_mid)[k0 + v][n];
+          R.ci.A_mid[static_cast<size_t>(n) * nv + v] = A_mid[k0 + v][n];
+          R.ci.dA_mid[static_cast<size_t>(n) * nv + v] = (*dA_mid)[k0 + v][n];
         }
     }
-    hub_status s = run_group(h, prec, nv, user, n_steps, cm, dt, o, want_obs, &co, &obs_raw, &reps, st, &ncv,
-                             &done, dA_mid ? &ci : nullptr);
-    if (s != HUB_OK) return s;
+  }
+  auto run_one = [&](GroupRun& R, Work& W, hipStream_t s_lane) {
+    char* user = static_cast<char*>(v_inout) + static_cast<size_t>(R.k0) * dim * es;
+    R.s = run_group(h, prec, R.nv, user, n_steps, R.cm, dt, o, want_obs, &R.co, &R.obs_raw, &R.reps, s_lane, &R.ncv,
+                    &R.done, dA_mid ? &R.ci : nullptr, W);
+    if (R.s != HUB_OK) R.err = g_err;
+    R.ran = true;
+  };
+
+  // Lanes: groups run concurrently when there are several, unless the apply
+  // timing (shared event pool) or the learned controller (shared MLP buffers)
+  // is on, or the lanes' Krylov workspaces would exceed the budget.
+  int nlanes = 1;
+  if (groups.size() > 1 && !h->prof && !(h->ctrl_on && dA_mid)) {
+    const size_t per_lane = static_cast<size_t>(o.m_max + 2) * dim * kMaxNV * es;
+    nlanes = static_cast<int>(std::min<size_t>(kMaxLanes, groups.size()));
+    while (nlanes > 1 && per_lane * nlanes > kLaneWorkBudget) --nlanes;
+  }
+  if (nlanes == 1) {
+    for (GroupRun& R : runs) {
+      run_one(R, h->w, st);
+      if (R.s != HUB_OK || R.ncv) break;  // stop at the first group that hit m_max
+    }
+  } else {
+    while (static_cast<int>(h->lanes.size()) < nlanes - 1) {
+      auto l = std::make_unique<Work>();
+      hub_status s = work_init(*l, true);
+      if (s != HUB_OK) {
+        work_free(*l);
+        return s;
+      }
+      h->lanes.push_back(std::move(l));
+    }
+    // the lanes start after the work already on the caller's stream
+    hipEvent_t ready = nullptr;
+    HUB_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HUB_HIP(hipEventRecord(ready, st));
+    for (int l = 1; l < nlanes; ++l) HUB_HIP(hipStreamWaitEvent(h->lanes[l - 1]->stream, ready, 0));
+    std::vector<std::thread> threads;
+    for (int l = 0; l < nlanes; ++l)
+      threads.emplace_back([&, l]() {
+        Work& W = l == 0 ? h->w : *h->lanes[l - 1];
+        const hipStream_t s_lane = l == 0 ? st : W.stream;
+        if (hipSetDevice(h->device) != hipSuccess) {
+          for (size_t g = l; g < runs.size(); g += nlanes) {
+            runs[g].s = HUB_E_DEVICE;
+            runs[g].err = "hipSetDevice failed in a propagation lane";
+          }
+          return;
+        }
+        for (size_t g = l; g < runs.size(); g += nlanes) {
+          try {
+            run_one(runs[g], W, s_lane);
+          } catch (const std::bad_alloc&) {
+            runs[g].s = HUB_E_NOMEM;
+            runs[g].err = "host allocation failed";
+          }
+          if (runs[g].s != HUB_OK) break;
+        }
+      });
+    for (auto& t : threads) t.join();
+    (void)hipEventDestroy(ready);
+  }
+  for (Work* W : [&] {
+         std::vector<Work*> ws{&h->w};
+         for (auto& l : h->lanes) ws.push_back(l.get());
+         return ws;
+       }()) {
+    h->cstats.steps += W->cstats.steps;
+    h->cstats.chunks += W->cstats.chunks;
+    h->cstats.fallbacks += W->cstats.fallbacks;
+    h->cstats.lanczos_launches += W->cstats.lanczos_launches;
+    h->cstats.iterations += W->cstats.iterations;
+    W->cstats = hub_controller_stats{};
+  }
+  for (const GroupRun& R : runs)
+    if (R.ran && R.s != HUB_OK) return fail(R.s, R.err);
+
+  bool any_nc = false;
+  for (const GroupRun& R : runs) {
+    if (!R.ran) continue;
+    const int nv = R.nv, k0 = R.k0, done = R.done;
     if (log)
       for (int n = 0; n < done; ++n)
         for (int v = 0; v < nv; ++v) {
-          const StepReport& R = reps[static_cast<size_t>(n) * nv + v];
+          const StepReport& P = R.reps[static_cast<size_t>(n) * nv + v];
           hub_step_info& I = log[static_cast<size_t>(n) * nvec + k0 + v];
-          I.m_used = R.m;
+          I.m_used = P.m;
           I.substeps = o.substeps;
-          I.converged = R.status != 3;
-          I.breakdown = R.status == 2;
-          I.err_est = R.eps;
-          I.beta_last = R.beta_last;
+          I.converged = P.status != 3;
+          I.breakdown = P.status == 2;
+          I.err_est = P.eps;
+          I.beta_last = P.beta_last;
         }
     if (want_obs) {
       for (int n = 0; n <= n_steps; ++n)
@@ -1169,12 +1293,10 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
             O = hub_obs{t_start + n * dt, NAN, NAN, NAN};
             continue;
           }
-          fill_obs(h->B, obs_raw.data() + (static_cast<size_t>(n) * nv + v) * kObsQ, t_start + n * dt, &O);
+          fill_obs(h->B, R.obs_raw.data() + (static_cast<size_t>(n) * nv + v) * kObsQ, t_start + n * dt, &O);
         }
     }
-    any_nc |= ncv;
-    if (ncv) break;
-    k0 += nv;
+    any_nc |= R.ncv;
   }
   if (any_nc) return fail(HUB_E_NOT_CONVERGED, "a Krylov step reached m_max before the tolerance");
   return HUB_OK;
@@ -1325,7 +1447,7 @@ hub_status hub_dot(hub_basis h, hub_prec prec, int32_t nvec, const void* x, cons
   hipStream_t st = static_cast<hipStream_t>(stream);
   double* dout = nullptr;
   HUB_HIP(hipMalloc(reinterpret_cast<void**>(&dout), 2 * nvec * sizeof(double)));
-  hipError_t e = hub::launch_dots(prec == HUB_C128 ? 0 : 1, h->D.dim, nvec, x, y, dout, h->partials_e, st);
+  hipError_t e = hub::launch_dots(prec == HUB_C128 ? 0 : 1, h->D.dim, nvec, x, y, dout, h->w.partials_e, st);
   if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 2 * nvec * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(dout);
@@ -1421,8 +1543,8 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
         hub_basis T = targets[tb[k]];
         if (op_psi(k, tmp) != hipSuccess ||
             hub::launch_dots(pi, T->D.dim, 1, tmp, slot_of(k),
-                             dover + (static_cast<size_t>(k) * (n_rel + 1) + sidx) * 2, T->partials_e ? T->partials_e
-                                                                                                : h->partials_e,
+                             dover + (static_cast<size_t>(k) * (n_rel + 1) + sidx) * 2, T->w.partials_e ? T->w.partials_e
+                                                                                                : h->w.partials_e,
                              st) != hipSuccess)
           return cleanup(fail(HUB_E_DEVICE, "overlap kernels"));
       }
@@ -1509,7 +1631,7 @@ hub_status gs_lanczos(hub_basis h, double A, hipStream_t st, GSBufs& G, int kmax
       for (int k0 = 0; k0 < nb; k0 += 64) {
         const int kk = std::min(64, nb - k0);
         HUB_HIP(hub::launch_multidot(dim, reinterpret_cast<const double2* const*>(G.Vdev) + k0, kk,
-                                     static_cast<const double2*>(w), G.coef + k0, h->partials_e, st));
+                                     static_cast<const double2*>(w), G.coef + k0, h->w.partials_e, st));
       }
       for (int k0 = 0; k0 < nb; k0 += 64) {
         const int kk = std::min(64, nb - k0);
@@ -1521,9 +1643,9 @@ hub_status gs_lanczos(hub_basis h, double A, hipStream_t st, GSBufs& G, int kmax
       HUB_HIP(hipStreamSynchronize(st));
       a_j += cj.x;
     }
-    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(w), h->scal, h->partials_e, st));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(w), h->w.scal, h->w.partials_e, st));
     double n2 = 0.0;
-    HUB_HIP(hipMemcpyAsync(&n2, h->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipMemcpyAsync(&n2, h->w.scal, sizeof(double), hipMemcpyDeviceToHost, st));
     HUB_HIP(hipStreamSynchronize(st));
     const double b_j = std::sqrt(n2);
     alpha.push_back(a_j);
@@ -1542,7 +1664,7 @@ hub_status gs_lanczos(hub_basis h, double A, hipStream_t st, GSBufs& G, int kmax
     for (int i = 0; i < m; ++i) svec[i] = vecs[static_cast<size_t>(i) * m + 0];
     kused = m;
     if (resid < tol_res || b_j < 1e-14 * h->B.norm_inf || m == dim - (deflate ? 1 : 0)) break;
-    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(w), h->scal, double2{0, 0}, st));
+    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(w), h->w.scal, double2{0, 0}, st));
   }
   return HUB_OK;
 }
@@ -1563,8 +1685,8 @@ hub_status gs_ritz_vector(hub_basis h, hipStream_t st, GSBufs& G, const std::vec
                                   static_cast<double2*>(out), st));
   }
   // normalise
-  HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(out), h->scal, h->partials_e, st));
-  HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(out), h->scal, double2{0, 0}, st));
+  HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(out), h->w.scal, h->w.partials_e, st));
+  HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(out), h->w.scal, double2{0, 0}, st));
   HUB_HIP(hipStreamSynchronize(st));
   return HUB_OK;
 }
@@ -1587,7 +1709,7 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
   s = ensure_workspace(h, static_cast<size_t>(dim) * 16, kmax + 1, 0);
   if (s != HUB_OK) return s;
   GSBufs G;
-  for (int k = 0; k <= kmax; ++k) G.V.push_back(static_cast<char*>(h->slots) + static_cast<size_t>(k) * dim * 16);
+  for (int k = 0; k <= kmax; ++k) G.V.push_back(static_cast<char*>(h->w.slots) + static_cast<size_t>(k) * dim * 16);
   void* extra = nullptr;
   HUB_HIP(hipMalloc(&extra, (kmax + 2) * (sizeof(void*) + 2 * sizeof(double2))));
   struct Fr {
@@ -1605,8 +1727,8 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
     std::vector<double2> x(static_cast<size_t>(dim));
     for (auto& e : x) e = double2{nd(rng), nd(rng)};
     HUB_HIP(hipMemcpy(dst, x.data(), x.size() * sizeof(double2), hipMemcpyHostToDevice));
-    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(dst), h->scal, h->partials_e, st));
-    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(dst), h->scal, double2{0, 0}, st));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(dst), h->w.scal, h->w.partials_e, st));
+    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(dst), h->w.scal, double2{0, 0}, st));
     return HUB_OK;
   };
   const double tol_res = tol * h->B.norm_inf;
@@ -1630,17 +1752,17 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
   }
   if (!conv) return fail(HUB_E_NOT_CONVERGED, "ground-state Lanczos did not reach the tolerance");
   // phase: largest-modulus component (lowest index within 1e-12 of the max) real positive
-  HUB_HIP(hub::launch_absmax(dim, static_cast<const double2*>(v_out), h->scal, h->partials_e, st));
+  HUB_HIP(hub::launch_absmax(dim, static_cast<const double2*>(v_out), h->w.scal, h->w.partials_e, st));
   double mx2 = 0.0;
-  HUB_HIP(hipMemcpyAsync(&mx2, h->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  HUB_HIP(hipMemcpyAsync(&mx2, h->w.scal, sizeof(double), hipMemcpyDeviceToHost, st));
   HUB_HIP(hipStreamSynchronize(st));
   const double th = mx2 * (1.0 - 1e-12) * (1.0 - 1e-12);
-  HUB_HIP(hipMemcpy(h->scal + 1, &th, sizeof(double), hipMemcpyHostToDevice));
-  HUB_HIP(hub::launch_first_above(dim, static_cast<const double2*>(v_out), h->scal + 1,
-                                  reinterpret_cast<int64_t*>(h->scal + 2), reinterpret_cast<int64_t*>(h->partials_e),
+  HUB_HIP(hipMemcpy(h->w.scal + 1, &th, sizeof(double), hipMemcpyHostToDevice));
+  HUB_HIP(hub::launch_first_above(dim, static_cast<const double2*>(v_out), h->w.scal + 1,
+                                  reinterpret_cast<int64_t*>(h->w.scal + 2), reinterpret_cast<int64_t*>(h->w.partials_e),
                                   st));
   int64_t kmaxidx = 0;
-  HUB_HIP(hipMemcpyAsync(&kmaxidx, h->scal + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HUB_HIP(hipMemcpyAsync(&kmaxidx, h->w.scal + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HUB_HIP(hipStreamSynchronize(st));
   double2 comp;
   HUB_HIP(hipMemcpy(&comp, static_cast<double2*>(v_out) + kmaxidx, sizeof(double2), hipMemcpyDeviceToHost));
@@ -1656,11 +1778,11 @@ hub_status hub_ground_state(hub_basis h, double A, const hub_krylov_opts* opts, 
     HUB_HIP(hipMemcpyAsync(G.Vdev, &v_out, sizeof(void*), hipMemcpyHostToDevice, st));
     HUB_HIP(hipStreamSynchronize(st));
     HUB_HIP(hub::launch_multidot(dim, reinterpret_cast<const double2* const*>(G.Vdev), 1,
-                                 static_cast<const double2*>(G.V[0]), G.coef, h->partials_e, st));
+                                 static_cast<const double2*>(G.V[0]), G.coef, h->w.partials_e, st));
     HUB_HIP(hub::launch_multiaxpy(dim, reinterpret_cast<const double2* const*>(G.Vdev), 1, G.coef,
                                   static_cast<double2*>(G.V[0]), st));
-    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(G.V[0]), h->scal, h->partials_e, st));
-    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(G.V[0]), h->scal, double2{0, 0}, st));
+    HUB_HIP(hub::launch_norm2(dim, static_cast<const double2*>(G.V[0]), h->w.scal, h->w.partials_e, st));
+    HUB_HIP(hub::launch_scale(dim, static_cast<double2*>(G.V[0]), h->w.scal, double2{0, 0}, st));
     double r1 = INFINITY;
     for (int restart = 0; restart < 20; ++restart) {
       s = gs_lanczos(h, A, st, G, kmax, v_out, 1e-6 * h->B.norm_inf, ritz, svec, kused, r1);
