@@ -89,6 +89,11 @@ struct Work {
   double* scal = nullptr;         // device scalars [kMMax*2 + 16]
   double* rcoef = nullptr;        // device re-orthogonalisation coefficients [kMMax + 1][kMaxNV] complex
   hipStream_t stream = nullptr;   // extra lanes: their own stream (lane 0 runs on the caller's)
+  void** h_ptrs = nullptr;        // pinned host mirror of slot_ptrs (uploaded without a wait)
+  void* dlog = nullptr;           // device step logs and observables of a propagation (grow only)
+  size_t dlog_bytes = 0;
+  double* dobs = nullptr;
+  size_t dobs_bytes = 0;
   hub_controller_stats cstats{};  // schedule counters of this lane's runs (folded into the handle's)
 };
 
@@ -156,7 +161,9 @@ hub_status work_init(Work& W, bool own_stream) {
       hipMalloc(reinterpret_cast<void**>(&W.ctl), sizeof(StepCtl)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&W.scal), (2 * kMMax + 64) * sizeof(double) * 2) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&W.rcoef), (kMMax + 1) * kMaxNV * 2 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&W.h_ctl), sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc(reinterpret_cast<void**>(&W.h_ctl), sizeof(StepCtl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&W.h_ptrs), (kMMax + 2) * sizeof(void*), hipHostMallocDefault) !=
+          hipSuccess)
     return fail(HUB_E_NOMEM, "workspace allocation failed");
   if (hipMemset(W.ctl, 0, sizeof(StepCtl)) != hipSuccess || hipMemset(W.st, 0, kMaxNV * sizeof(VecState)) != hipSuccess)
     return fail(HUB_E_DEVICE, "workspace initialisation failed");
@@ -176,6 +183,9 @@ void work_free(Work& W) {
   if (W.rcoef) (void)hipFree(W.rcoef);
   if (W.partials) (void)hipFree(W.partials);
   if (W.h_ctl) (void)hipHostFree(W.h_ctl);
+  if (W.h_ptrs) (void)hipHostFree(W.h_ptrs);
+  if (W.dlog) (void)hipFree(W.dlog);
+  if (W.dobs) (void)hipFree(W.dobs);
   if (W.stream) (void)hipStreamDestroy(W.stream);
   W = Work{};
 }
@@ -437,27 +447,30 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   std::vector<void*> ptrs(kMMax + 2, nullptr);
   ptrs[0] = slot0;
   for (int k = 1; k <= o.m_max; ++k) ptrs[k] = static_cast<char*>(W.slots) + (k - 1) * vbytes;
-  HUB_HIP(hipMemcpyAsync(W.slot_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice,
-                         stream));
-  // the copy above reads `ptrs` asynchronously: wait before it goes out of scope
-  HUB_HIP(hipStreamSynchronize(stream));
+  // from the pinned mirror (free again: the previous run on this lane ended with a wait on its stream)
+  std::copy(ptrs.begin(), ptrs.end(), W.h_ptrs);
+  HUB_HIP(hipMemcpyAsync(W.slot_ptrs, W.h_ptrs, ptrs.size() * sizeof(void*), hipMemcpyHostToDevice, stream));
 
   // device logs
   const int nobs_rows = want_obs ? n_steps + 1 : 0;
   const size_t log_bytes = static_cast<size_t>(std::max(1, n_steps)) * solves_per_step(o) * nv * sizeof(CombineLog);
   const size_t obs_bytes = static_cast<size_t>(std::max(1, nobs_rows)) * nv * kObsQ * sizeof(double);
-  void* dlog = nullptr;
-  double* dobs = nullptr;
-  HUB_HIP(hipMalloc(&dlog, log_bytes));
-  if (want_obs) HUB_HIP(hipMalloc(reinterpret_cast<void**>(&dobs), obs_bytes));
-  struct Freer {
-    void* a;
-    void* b;
-    ~Freer() {
-      if (a) (void)hipFree(a);
-      if (b) (void)hipFree(b);
-    }
-  } freer{dlog, dobs};
+  if (log_bytes > W.dlog_bytes) {
+    if (W.dlog) HUB_HIP(hipFree(W.dlog));
+    W.dlog = nullptr;
+    W.dlog_bytes = 0;
+    HUB_HIP(hipMalloc(&W.dlog, log_bytes));
+    W.dlog_bytes = log_bytes;
+  }
+  if (want_obs && obs_bytes > W.dobs_bytes) {
+    if (W.dobs) HUB_HIP(hipFree(W.dobs));
+    W.dobs = nullptr;
+    W.dobs_bytes = 0;
+    HUB_HIP(hipMalloc(reinterpret_cast<void**>(&W.dobs), obs_bytes));
+    W.dobs_bytes = obs_bytes;
+  }
+  void* dlog = W.dlog;
+  double* dobs = want_obs ? W.dobs : nullptr;
 
   StepCtl ctl0{};
   HUB_HIP(hipMemcpyAsync(W.ctl, &ctl0, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
