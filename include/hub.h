@@ -236,7 +236,10 @@ hub_status hub_dot(hub_basis basis, hub_prec prec, int32_t nvec, const void *x, 
  * so that G^<(t', t'+s) = i o(s) for c and G^>(t'+s, t') = -i o(s) for c^dag.
  * targets: host array of n_targets basis handles covering the members'
  * sectors (matched by particle numbers); members sharing a sector are
- * propagated together.  psi_inout: device vector of `basis` in precision
+ * propagated together.  Each step, psi and the members of every sector are
+ * propagated side by side (own streams and host threads, after the work on
+ * `stream`), so the handles must be distinct and not in use elsewhere during
+ * the call.  psi_inout: device vector of `basis` in precision
  * `prec`, advanced in place to t_start + (max start_step + n_rel) dt.
  * overlaps: host [n_members][n_rel + 1][2].  Synchronises `stream`. */
 typedef struct {

@@ -1508,14 +1508,20 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
   std::vector<DevOpMap> ops(n_members);
   void* tmp = nullptr;
   double* dover = nullptr;
+  std::vector<hipStream_t> jstreams;  // one per concurrent propagation of a step
+  hipEvent_t jready = nullptr;
   auto cleanup = [&](hub_status r) {
     for (void* p : gbuf)
       if (p) (void)hipFree(p);
     for (auto& o : ops) o.release();
     if (tmp) (void)hipFree(tmp);
     if (dover) (void)hipFree(dover);
+    for (hipStream_t x : jstreams) (void)hipStreamDestroy(x);
+    if (jready) (void)hipEventDestroy(jready);
     return r;
   };
+  if (hipEventCreateWithFlags(&jready, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(HUB_E_DEVICE, "event creation failed"));
   int64_t maxdim = 0;
   for (int g = 0; g < n_targets; ++g) {
     if (grp[g].empty()) continue;
@@ -1564,13 +1570,18 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
     }
     if (n == n_total) break;
     const double amid = pulse_value(*pulse, t_start + n * dt + 0.5 * dt);
-    // psi one step
-    {
-      std::vector<std::vector<double>> am(1, std::vector<double>(1, amid));
-      if ((s = run_all(h, prec, 1, psi_inout, 1, am, nullptr, 0.0, dt, o1, nullptr, nullptr, stream)) != HUB_OK)
-        return cleanup(s);
-    }
-    // active members of every target sector one step (contiguous, batched)
+    // psi and the active members of every target sector (contiguous, batched)
+    // one step each: independent propagations, run side by side on their own
+    // streams and host threads after the overlap kernels above
+    struct Job {
+      hub_basis H;
+      int nvec;
+      void* base;
+      hub_status s = HUB_OK;
+      std::string err;
+    };
+    std::vector<Job> jobs;
+    jobs.push_back(Job{h, 1, psi_inout});
     for (int g = 0; g < n_targets; ++g) {
       const auto& v = grp[g];
       int lo = -1, hi = -1;
@@ -1584,11 +1595,38 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
       if (lo < 0) continue;
       hub_basis T = targets[g];
       if ((s = ensure_workspace(T, 16, 1, 0)) != HUB_OK) return cleanup(s);
-      std::vector<std::vector<double>> am(hi - lo, std::vector<double>(1, amid));
-      char* base = static_cast<char*>(gbuf[g]) + static_cast<size_t>(lo) * T->D.dim * es;
-      if ((s = run_all(T, prec, hi - lo, base, 1, am, nullptr, 0.0, dt, o1, nullptr, nullptr, stream)) != HUB_OK)
-        return cleanup(s);
+      jobs.push_back(Job{T, hi - lo, static_cast<char*>(gbuf[g]) + static_cast<size_t>(lo) * T->D.dim * es});
     }
+    while (jstreams.size() < jobs.size()) {
+      hipStream_t x = nullptr;
+      if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(fail(HUB_E_DEVICE, "stream creation failed"));
+      jstreams.push_back(x);
+    }
+    if (hipEventRecord(jready, st) != hipSuccess) return cleanup(fail(HUB_E_DEVICE, "event record failed"));
+    for (size_t q = 0; q < jobs.size(); ++q)
+      if (hipStreamWaitEvent(jstreams[q], jready, 0) != hipSuccess)
+        return cleanup(fail(HUB_E_DEVICE, "stream wait failed"));
+    std::vector<std::thread> threads;
+    for (size_t q = 0; q < jobs.size(); ++q)
+      threads.emplace_back([&, q]() {
+        Job& J = jobs[q];
+        if (hipSetDevice(h->device) != hipSuccess) {
+          J.s = HUB_E_DEVICE;
+          J.err = "hipSetDevice failed";
+          return;
+        }
+        try {
+          std::vector<std::vector<double>> am(J.nvec, std::vector<double>(1, amid));
+          J.s = run_all(J.H, prec, J.nvec, J.base, 1, am, nullptr, 0.0, dt, o1, nullptr, nullptr, jstreams[q]);
+        } catch (const std::bad_alloc&) {
+          J.s = fail(HUB_E_NOMEM, "host allocation failed");
+        }
+        if (J.s != HUB_OK) J.err = g_err;
+      });
+    for (auto& t : threads) t.join();
+    for (const Job& J : jobs)
+      if (J.s != HUB_OK) return cleanup(fail(J.s, J.err));
   }
   if (hipMemcpyAsync(overlaps, dover, static_cast<size_t>(n_members) * (n_rel + 1) * 2 * sizeof(double),
                      hipMemcpyDeviceToHost, st) != hipSuccess ||
