@@ -1218,7 +1218,8 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
   // is on, or the lanes' Krylov workspaces would exceed the budget.
   int nlanes = 1;
   if (groups.size() > 1 && !h->prof && !(h->ctrl_on && dA_mid)) {
-    const size_t per_lane = static_cast<size_t>(o.m_max + 2) * dim * kMaxNV * es;
+    const int gmax = *std::max_element(groups.begin(), groups.end());
+    const size_t per_lane = static_cast<size_t>(o.m_max + 2) * dim * gmax * es;  // slots and block buffer
     nlanes = static_cast<int>(std::min<size_t>(kMaxLanes, groups.size()));
     while (nlanes > 1 && per_lane * nlanes > kLaneWorkBudget) --nlanes;
   }
