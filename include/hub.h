@@ -186,7 +186,8 @@ hub_status hub_krylov_expm_step(hub_basis basis, const double *A_mid, double dt,
  * column k), with H(t) evaluated at the sample time.  log: host
  * [n_steps * nvec] or NULL.  Returns HUB_E_NOT_CONVERGED (and stops) at the
  * first step where a vector hits m_max; v_inout then holds that step's
- * m_max approximation.  The schedule (hub_set_schedule,
+ * m_max approximation, the obs row after that step holds its observables and
+ * later rows are NaN.  The schedule (hub_set_schedule,
  * hub_controller_enable) changes how the launches overlap the host, never the
  * result.  The library propagates the vectors in groups (interleaved blocks,
  * or single vectors where the two-pass kernels apply); several groups run

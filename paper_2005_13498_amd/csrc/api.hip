@@ -789,8 +789,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       n = nb + 1;
     }
   }
-  // observables at the final sample time
-  if (want_obs && *steps_done == n_steps) {
+  // observables at the last sample time reached (after n_steps steps, or
+  // after the step that stopped at m_max)
+  if (want_obs) {
     StepCtl c2 = StepCtl{};  // clear a stop flag left by the last step
     *W.h_ctl = c2;
     HUB_HIP(hipMemcpyAsync(W.ctl, W.h_ctl, sizeof(StepCtl), hipMemcpyHostToDevice, stream));
@@ -799,13 +800,13 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.obs = true;
     A.x = slot0;
     A.y = nullptr;
-    A.coef = coef_obs->data() + static_cast<size_t>(n_steps) * nv * 2 * nc;
+    A.coef = coef_obs->data() + static_cast<size_t>(*steps_done) * nv * 2 * nc;
     A.coef_obs = A.coef;
     A.j = 0;
     int ogrid = 0;
     HUB_HIP(hub::launch_apply(A, &ogrid));
     HUB_HIP(hub::launch_finalize_obs(nv, W.partials, ogrid, hub::apply_nq(hub::kObsOnly, true, nc), W.st, stream));
-    HUB_HIP(hub::launch_step_log(nv, W.st, W.ctl, nullptr, dobs + static_cast<size_t>(n_steps) * nv * kObsQ,
+    HUB_HIP(hub::launch_step_log(nv, W.st, W.ctl, nullptr, dobs + static_cast<size_t>(*steps_done) * nv * kObsQ,
                                  kObsQ, stream));
   }
   if (nv > 1) HUB_HIP(hub::launch_interleave(pi, nv, dim, slot0, user, false, stream));
@@ -1303,7 +1304,7 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
       for (int n = 0; n <= n_steps; ++n)
         for (int v = 0; v < nv; ++v) {
           hub_obs& O = obs[static_cast<size_t>(n) * nvec + k0 + v];
-          if (n > done || (n == n_steps && done < n_steps)) {
+          if (n > done) {  // past the step that stopped at m_max
             O = hub_obs{t_start + n * dt, NAN, NAN, NAN};
             continue;
           }

@@ -137,3 +137,34 @@ def test_schedule_argument_checks():
         hub.hub_set_schedule(B.handle, 256, 16)
     finally:
         B.close()
+
+
+@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("chunk", [0, 16])
+def test_stop_at_m_max_reports_the_last_state(path, chunk):
+    """After a stop at m_max the obs row after the stopping step holds the
+    observables of the returned vector; later rows are NaN (one- and two-pass
+    kernels, synchronous and chunked schedules)."""
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        hub.hub_set_apply_path(B.handle, path)
+        v0 = torch.empty(B.dim, dtype=torch.complex128, device=DEV)
+        hub.hub_ground_state(B.handle, hub.hub_pulse_A(w.pulse, 0.0), v0, hub.make_opts(tol=1e-13, m_max=60))
+        # from the ground state the steps need m = 11, 11, 12, 13, ... (tol
+        # 1e-13, dt 0.1): m_max 12 stops a few steps in
+        opts = hub.make_opts(tol=1e-13, m_max=12)
+        n = 40
+        st, v, obs, log, _ = _run(B, [w.pulse], v0, 0.1, n, opts, chunk, allow_nc=True)
+        assert st == hub.HUB_E_NOT_CONVERGED
+        stop = int(np.argmax(log[:, 0, 2] == 0))
+        assert log[stop, 0, 0] == 12 and (log[:stop, 0, 2] == 1).all() and 1 <= stop < 10
+        done = stop + 1
+        o_ref, _ = hub.hub_observables(B.handle, [hub.hub_pulse_A(w.pulse, done * 0.1)], v)
+        assert obs[done, 0, 0] == pytest.approx(done * 0.1)
+        assert np.allclose(obs[done, 0, 1:], o_ref[0, 1:], rtol=1e-12, atol=1e-13)
+        assert np.isnan(obs[done + 1:, 0, 1:]).all()
+        assert np.isfinite(obs[:done + 1, 0, 1:]).all()
+    finally:
+        hub.hub_set_apply_path(B.handle, -1)
+        B.close()
