@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* partials, int
                                                      int op) {
   __shared__ double red[kWaves];
   for (int t = 0; t < ncols; ++t) {
-    double s = op ? 0.0 : 0.0;
+    double s = 0.0;  // the maxima are of non-negative partials
     for (int b = threadIdx.x; b < nrows; b += blockDim.x) {
       const double x = partials[(size_t)b * ncols + t];
       s = op ? fmax(s, x) : s + x;
