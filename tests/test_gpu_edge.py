@@ -1,0 +1,95 @@
+"""Edge cases of the propagation through the C ABI.
+
+* no steps: the state is untouched and the single observables row is that of
+  the input at t_start (one- and two-pass kernels, several vectors);
+* a zero vector: every Krylov step breaks down at once (beta_0 = 0) and the
+  vector stays exactly zero, with zero observables;
+* a spin sector with a single string (every site occupied by one spin):
+  no hops of that spin, the apply and the midpoint steps against the oracle.
+"""
+import numpy as np
+import pytest
+
+import paper_2005_13498_amd as hub
+from synth import ring, random_state, workloads
+from oracle import HubbardOracle, to_canonical, from_canonical, midpoint_step_exact
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _vecs(B, nv, seed, dtype):
+    x = np.concatenate(random_state(B.dim, seed=seed, nvec=nv))
+    return torch.from_numpy(x).to(DEV).to(dtype).contiguous()
+
+
+@pytest.mark.parametrize("name,nv", [("ring8", 1), ("ring8", 3), ("cluster3x4", 1)])
+def test_zero_steps_report_the_input(name, nv):
+    w = workloads()[name]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        x0 = _vecs(B, nv, 61, torch.complex128)
+        x = x0.clone()
+        t0 = 0.7
+        pulses = [w.pulse] * nv
+        st, obs, log = hub.hub_propagate(B.handle, pulses, t0, w.dt, 0, hub.make_opts(tol=w.tol, m_max=w.m_max), x)
+        assert st == hub.HUB_OK
+        assert torch.equal(x, x0)
+        assert obs.shape == (1, nv, 4) and log is None
+        ref, _ = hub.hub_observables(B.handle, [hub.hub_pulse_A(w.pulse, t0)] * nv, x0)
+        assert np.allclose(obs[0, :, 0], t0)
+        assert np.allclose(obs[0, :, 1:], ref[:, 1:], rtol=1e-12, atol=1e-13)
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("name,dtype,nv", [("ring8", torch.complex128, 1), ("ring8", torch.complex64, 2),
+                                           ("cluster3x4", torch.complex128, 1)])
+def test_zero_vector_stays_zero(name, dtype, nv):
+    w = workloads()[name]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        x = torch.zeros(nv * B.dim, dtype=dtype, device=DEV)
+        n = 6
+        for chunk in (0, 32):
+            hub.hub_set_schedule(B.handle, chunk, 1)
+            st, obs, log = hub.hub_propagate(B.handle, [w.pulse] * nv, 0.0, w.dt, n,
+                                             hub.make_opts(tol=w.tol, m_max=w.m_max), x)
+            assert st == hub.HUB_OK
+            assert not bool(x.abs().gt(0).any())
+            assert np.all(obs[:, :, 1:] == 0.0)
+            assert (log[:, :, 2] == 1).all() and (log[:, :, 3] == 1).all()  # converged, breakdown
+    finally:
+        hub.hub_set_schedule(B.handle, 32, 1)
+        B.close()
+
+
+def test_single_string_spin_sector():
+    lat, U, nu, nd = ring(6), 4.0, 6, 2
+    ham = HubbardOracle(lat, U, nu, nd)
+    B = hub.Basis(lat, U, nu, nd, device=0)
+    try:
+        assert B.dim == ham.dim == 15
+        x = random_state(ham.dim, seed=62)[0]
+        xc = torch.from_numpy(to_canonical(x, ham.states, 6)).to(DEV)
+        y = torch.empty_like(xc)
+        hub.hub_apply_H(B.handle, [0.37], xc, y)
+        assert _rel(y.cpu().numpy(), to_canonical(ham.apply(0.37, x), ham.states, 6)) < 1e-13
+        w = workloads()["ring8"]
+        n, dt = 20, 0.05
+        st, obs, log = hub.hub_propagate(B.handle, [w.pulse], 0.0, dt, n, hub.make_opts(tol=1e-13, m_max=30), xc)
+        assert st == hub.HUB_OK
+        v = x.copy()
+        for k in range(n):
+            v = midpoint_step_exact(ham, v, k * dt, dt, w.pulse)
+        assert _rel(from_canonical(xc.cpu().numpy(), ham.states, 6), v) < 1e-10
+        # every site holds an up electron: the double occupancy per site is n_dn / N_s
+        assert np.allclose(obs[:, 0, 3], nd / 6, rtol=1e-10)
+    finally:
+        B.close()
