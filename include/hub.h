@@ -393,7 +393,9 @@ hub_status hub_set_apply_path(hub_basis basis, int32_t path);
  * Lanczos update into the row pass, and only those fused iterations are
  * timed.  A two-pass apply is timed as the sum of its two kernels.
  * Launches enqueued past a step's Krylov decision (speculative iterations,
- * which exit at once) are left out once the step's m is known.  The events
+ * which exit at once) are left out once the step's m is known, and so is a
+ * step's last fused iteration (j = m), whose column pass skips the apply
+ * when the row pass has already found the error estimate below tol.  The events
  * come from a pool of 8192 created here (on >= 1); a propagation reads them
  * back and reuses them only when fewer than 512 are left, so a run of up to
  * about 2000 timed launches adds neither event creation nor read-back to it. 

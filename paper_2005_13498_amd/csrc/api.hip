@@ -65,6 +65,7 @@ struct ProfSample {
   std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
   double ms = 0.0;
   int n = -1, sub = 0, j = 0;  // Lanczos launch: step, substep, iteration (n = -1: plain apply)
+  bool fused = false;          // fused two-pass iteration
   int worked = 1;              // 0: launched past the Krylov decision (exits at once); -1: not yet known
 };
 
@@ -360,6 +361,7 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid 
   smp.n = step;
   smp.sub = sub;
   smp.j = L.j;
+  smp.fused = L.fuse;
   smp.worked = step < 0 ? 1 : -1;
   h->prof_samples.push_back(smp);
   // algorithmic bytes: H*v reads x, writes y; a fused iteration also reads
@@ -823,7 +825,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   if (classify) {
     // launch j of a (sub)step with Krylov dimension m did work iff j <= m
     // (j = m builds u_m, whose norm the decision needs) and j < m_max
-    // (launch m_max only takes the decision)
+    // (launch m_max only takes the decision); a fused iteration j = m is left
+    // out too: its column pass skips the apply when the row pass already
+    // found the estimate below tol
     for (size_t i = prof_s0; i < h->prof_samples.size(); ++i) {
       ProfSample& p = h->prof_samples[i];
       if (p.worked != -1) continue;
@@ -834,7 +838,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       int m = 0;
       for (int v = 0; v < nv; ++v)
         m = std::max(m, static_cast<int>(lg[(static_cast<size_t>(p.n) * S + p.sub) * nv + v].m));
-      p.worked = (p.j <= m && p.j < o.m_max) ? 1 : 0;
+      p.worked = (p.fused ? p.j < m : p.j <= m) && p.j < o.m_max ? 1 : 0;
     }
   }
   if (reports && nd > 0) {

@@ -131,6 +131,23 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     // are taken by the column pass.
     if (p.ctl->all_done) return;
     const double al = reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, p.alpha_stride, 0, red);
+    if (blockIdx.x == gridDim.x - 1) {
+      // The extra last workgroup: the estimate for m = j needs only T_j
+      // (alpha_{j-1} = al, the rest recorded), not |u_j|.  When it is below
+      // tol the step ends at m = j whatever |u_j| turns out to be, and the
+      // column pass then skips this iteration's apply.
+      if (tid < 64) {
+        const VecState& S = p.st[0];
+        bool stop = false;
+        if (S.status == 0) {
+          const double aj = tid < p.j - 1 ? S.alpha[tid] : (tid == p.j - 1 ? al : 0.0);
+          double yr, yi;
+          stop = wave_krylov_eps(p.j, aj, S.beta, S.tau, S.y, tid, yr, yi) < p.tol;
+        }
+        if (tid == 0) p.ctl->eps_stop = stop ? p.j : -1;
+      }
+      return;
+    }
     if (blockIdx.x == 0 && tid == 0 && p.st[0].status == 0) p.st[0].alpha[p.j - 1] = al;
     if (blockIdx.x == 0 && p.obs_row) {
       // observables of the step's first vector: [diag, docc, n2, down-hop
@@ -171,7 +188,7 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   const int half = (p.dim_dn + 1) * NV;   // one staged copy incl. the zero slot
   // workgroup = (row a, column chunk); the chunks of one row are consecutive
   // logical blocks, so they run on one XCD and re-read the staged row from L2
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, FUSE ? gridDim.x - 1 : gridDim.x);
   const int a = lb / p.chunks;
   const int cw = (rowlen + p.chunks - 1) / p.chunks;
   const int qbeg = (lb % p.chunks) * cw;
@@ -445,7 +462,8 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
     (void)hipGetLastError();  // a refused opt-in is not a launch error
   }
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
-  return launch_ev(fn, grid, BLK, lds, L.stream, L.ev_start, L.ev_stop, p);
+  // fused row pass: one more workgroup for the early estimate
+  return launch_ev(fn, FUSE ? grid + 1 : grid, BLK, lds, L.stream, L.ev_start, L.ev_stop, p);
 }
 
 template <typename R, int NV, int MODE, int BLK, bool UPH = true, bool FUSE = false>
@@ -506,12 +524,17 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
       // |u_j| from the row pass's partials.  An extra last workgroup takes
       // the decision for m = j alongside the column blocks (a single round of
       // workgroups: the decision would otherwise add to the kernel's time).
+      // When the row pass already found the estimate for m = j below tol,
+      // the step ends here and the column blocks have nothing to do.
+      const bool decide = blockIdx.x == gridDim.x - 1;
+      const bool ends = p.ctl->eps_stop == p.j;
+      if (ends && !decide) return;
       const double s2 = reduce_column<kW>(p.norm_partials, p.dim_up, 1, 0, red);
       bv = sqrt(s2);
-      if (blockIdx.x == gridDim.x - 1) {
+      if (decide) {
         if (threadIdx.x == 0) sh_b[0] = bv;
         __syncthreads();
-        krylov_decide<1, kW>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+        krylov_decide<1, kW>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf, ends ? p.j : -1);
         return;
       }
     } else {

@@ -36,6 +36,7 @@ struct StepCtl {
   int32_t any_maxed;         // some vector reached m_max in this step
   int32_t abort;             // a step ended undecided: later kernels do nothing
   int32_t steps_done;        // (sub)steps logged since the host last cleared it
+  int32_t eps_stop;          // fused iteration j whose row pass found the estimate for m = j below tol, else -1
   double tol;
   double norm_inf;
 };

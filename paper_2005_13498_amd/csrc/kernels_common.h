@@ -93,16 +93,13 @@ template <typename V> __device__ __forceinline__ V cfma(V c, V s, V acc) {
 
 // ---------------------------------------------------------------------------
 // One wavefront: y = exp(-i tau T) e_1 for the j x j real symmetric
-// tridiagonal T (diagonal alpha, off-diagonal beta).  Taylor series of the
-// action on a vector with scaling, exp(-i tau T) = exp(-i (tau/s) T)^s, s
-// chosen so that |tau/s| |T|_inf <= 1/2; each factor's series is summed
-// until a term falls below 1e-18 of the partial sum.  Lane i holds
-// component i (j <= 64).
-__device__ inline void wave_small_expm(int j, const double* alpha, const double* beta, double tau,
-                                int lane, double& yr, double& yi) {
-  const double a = lane < j ? alpha[lane] : 0.0;
-  const double bl = (lane >= 1 && lane < j) ? beta[lane - 1] : 0.0;
-  const double bu = (lane + 1 < j) ? beta[lane] : 0.0;
+// tridiagonal T.  Taylor series of the action on a vector with scaling,
+// exp(-i tau T) = exp(-i (tau/s) T)^s, s chosen so that |tau/s| |T|_inf <=
+// 1/2; each factor's series is summed until a term falls below 1e-18 of the
+// partial sum.  Lane i holds row i of T (diagonal a, off-diagonals bl left
+// and bu right of it; zero past j) and returns component i of y (j <= 64).
+__device__ inline void wave_small_expm(int j, double a, double bl, double bu, double tau, int lane, double& yr,
+                                       double& yi) {
   const double nrm = wave_max(fabs(a) + fabs(bl) + fabs(bu));
   const int s = max(1, static_cast<int>(ceil(fabs(tau) * nrm * 2.0)));
   const double h = tau / s;
@@ -130,15 +127,36 @@ __device__ inline void wave_small_expm(int j, const double* alpha, const double*
   yi = zi;
 }
 
+// y^(j) = exp(-i tau T_j) e_1 (lane i: component i) and the estimate of
+// Alg. 6 for m = j: delta = |y^(j) - y^(j-1)| / |y^(j)|, eps = min(1 + |y|,
+// delta/(1-delta) |y|) (or 1 + |y| if delta >= 1).  a: alpha_i of lane i (the
+// diagonal of T_j); beta: the off-diagonals beta_0..beta_{j-2}; yprev: y^(j-1)
+// (j - 1 complex components).
+__device__ inline double wave_krylov_eps(int j, double a, const double* beta, double tau, const double* yprev,
+                                         int lane, double& yr, double& yi) {
+  const double bl = (lane >= 1 && lane < j) ? beta[lane - 1] : 0.0;
+  const double bu = (lane + 1 < j) ? beta[lane] : 0.0;
+  wave_small_expm(j, a, bl, bu, tau, lane, yr, yi);
+  const double pr = (lane < j - 1) ? yprev[2 * lane] : 0.0;
+  const double pi = (lane < j - 1) ? yprev[2 * lane + 1] : 0.0;
+  const double d2 = wave_sum((yr - pr) * (yr - pr) + (yi - pi) * (yi - pi));
+  const double y2 = wave_sum(yr * yr + yi * yi);
+  const double ny = sqrt(y2);
+  const double delta = sqrt(d2) / ny;
+  return (delta < 1.0) ? fmin(1.0 + ny, delta / (1.0 - delta) * ny) : 1.0 + ny;
+}
+
 // Krylov decision for Krylov dimension m = j (T_j complete: alpha[0..j-1],
 // beta[0..j-2]; the new off-diagonal beta_{j-1} = beta_new[v]); for j == 0
 // it starts the step (beta0 = beta_new).  One wave per vector; run by one
 // workgroup.  Alg. 6: y^(j) = exp(-i tau T_j) e_1, delta = |y^(j) - y^(j-1)|
 // / |y^(j)|, eps = min(1 + |y|, delta/(1-delta) |y|) (or 1 + |y| if
-// delta >= 1); stop when eps < tol or beta_{j-1} < |H| tol.
+// delta >= 1); stop when eps < tol or beta_{j-1} < |H| tol.  j == stop_j:
+// an earlier kernel already found eps < tol for this j (and let work that
+// only a longer step needs go undone), so the step stops here.
 template <int NV, int W = kWaves>
 __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepCtl* ctl, int m_max, double tol,
-                              double norm_inf) {
+                              double norm_inf, int stop_j = -1) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int v = wv; v < NV; v += W) {
     VecState& S = st[v];
@@ -158,14 +176,7 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
     if (S.status != 0) continue;
     double yr, yi;
     // beta[j-1] is not part of T_j; store it after the exponential
-    wave_small_expm(j, S.alpha, S.beta, S.tau, lane, yr, yi);
-    const double pr = (lane < j - 1) ? S.y[2 * lane] : 0.0;
-    const double pi = (lane < j - 1) ? S.y[2 * lane + 1] : 0.0;
-    const double d2 = wave_sum((yr - pr) * (yr - pr) + (yi - pi) * (yi - pi));
-    const double y2 = wave_sum(yr * yr + yi * yi);
-    const double ny = sqrt(y2);
-    const double delta = sqrt(d2) / ny;
-    const double eps = (delta < 1.0) ? fmin(1.0 + ny, delta / (1.0 - delta) * ny) : 1.0 + ny;
+    const double eps = wave_krylov_eps(j, lane < j ? S.alpha[lane] : 0.0, S.beta, S.tau, S.y, lane, yr, yi);
     if (lane < j) {
       S.y[2 * lane] = yr;
       S.y[2 * lane + 1] = yi;
@@ -176,7 +187,7 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
       S.m = j;
       int status = 0;
       if (b < norm_inf * tol) status = 2;
-      else if (eps < tol) status = 1;
+      else if (eps < tol || j == stop_j) status = 1;
       else if (j >= m_max) status = 3;
       S.status = status;
       S.scale[j] = (status == 0 && b > 0.0) ? 1.0 / b : 0.0;
