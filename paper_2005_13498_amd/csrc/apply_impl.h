@@ -134,15 +134,24 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     if (blockIdx.x == gridDim.x - 1) {
       // The extra last workgroup: the estimate for m = j needs only T_j
       // (alpha_{j-1} = al, the rest recorded), not |u_j|.  When it is below
-      // tol the step ends at m = j whatever |u_j| turns out to be, and the
-      // column pass then skips this iteration's apply.
+      // tol the step ends at m = j whatever |u_j| turns out to be: y^(j) and
+      // eps are recorded here, and the column pass skips this iteration's
+      // apply and only records |u_j| and the status.
       if (tid < 64) {
-        const VecState& S = p.st[0];
+        VecState& S = p.st[0];
         bool stop = false;
         if (S.status == 0) {
           const double aj = tid < p.j - 1 ? S.alpha[tid] : (tid == p.j - 1 ? al : 0.0);
           double yr, yi;
-          stop = wave_krylov_eps(p.j, aj, S.beta, S.tau, S.y, tid, yr, yi) < p.tol;
+          const double eps = wave_krylov_eps(p.j, aj, S.beta, S.tau, S.y, tid, yr, yi);
+          stop = eps < p.tol;
+          if (stop) {  // every lane has read y^(j-1): its reductions fed eps
+            if (tid < p.j) {
+              S.y[2 * tid] = yr;
+              S.y[2 * tid + 1] = yi;
+            }
+            if (tid == 0) S.eps = eps;
+          }
         }
         if (tid == 0) p.ctl->eps_stop = stop ? p.j : -1;
       }
@@ -532,9 +541,13 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
       const double s2 = reduce_column<kW>(p.norm_partials, p.dim_up, 1, 0, red);
       bv = sqrt(s2);
       if (decide) {
+        if (ends) {
+          if (threadIdx.x == 0) krylov_end_at(p.j, bv, p.st[0], p.ctl, p.tol, p.norm_inf);
+          return;
+        }
         if (threadIdx.x == 0) sh_b[0] = bv;
         __syncthreads();
-        krylov_decide<1, kW>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf, ends ? p.j : -1);
+        krylov_decide<1, kW>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
         return;
       }
     } else {

@@ -151,12 +151,10 @@ __device__ inline double wave_krylov_eps(int j, double a, const double* beta, do
 // it starts the step (beta0 = beta_new).  One wave per vector; run by one
 // workgroup.  Alg. 6: y^(j) = exp(-i tau T_j) e_1, delta = |y^(j) - y^(j-1)|
 // / |y^(j)|, eps = min(1 + |y|, delta/(1-delta) |y|) (or 1 + |y| if
-// delta >= 1); stop when eps < tol or beta_{j-1} < |H| tol.  j == stop_j:
-// an earlier kernel already found eps < tol for this j (and let work that
-// only a longer step needs go undone), so the step stops here.
+// delta >= 1); stop when eps < tol or beta_{j-1} < |H| tol.
 template <int NV, int W = kWaves>
 __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepCtl* ctl, int m_max, double tol,
-                              double norm_inf, int stop_j = -1) {
+                              double norm_inf) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int v = wv; v < NV; v += W) {
     VecState& S = st[v];
@@ -187,7 +185,7 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
       S.m = j;
       int status = 0;
       if (b < norm_inf * tol) status = 2;
-      else if (eps < tol || j == stop_j) status = 1;
+      else if (eps < tol) status = 1;
       else if (j >= m_max) status = 3;
       S.status = status;
       S.scale[j] = (status == 0 && b > 0.0) ? 1.0 / b : 0.0;
@@ -204,6 +202,20 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
     ctl->any_maxed = maxed;
     ctl->iter = j;
   }
+}
+
+// The end of a single vector's step at m = j, decided before |u_j| was
+// known: an earlier kernel found the estimate for m = j below tol and
+// recorded y^(j) and eps.  Records beta_{j-1} = b and the status as
+// krylov_decide would (breakdown if b < |H| tol, else converged).  One thread.
+__device__ inline void krylov_end_at(int j, double b, VecState& S, StepCtl* ctl, double tol, double norm_inf) {
+  S.beta[j - 1] = b;
+  S.m = j;
+  S.status = b < norm_inf * tol ? 2 : 1;
+  S.scale[j] = 0.0;
+  ctl->all_done = 1;
+  ctl->any_maxed = 0;
+  ctl->iter = j;
 }
 
 // ---------------------------------------------------------------------------
