@@ -132,11 +132,22 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     if (p.ctl->all_done) return;
     const double al = reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, p.alpha_stride, 0, red);
     if (blockIdx.x == gridDim.x - 1) {
-      // The extra last workgroup: the estimate for m = j needs only T_j
-      // (alpha_{j-1} = al, the rest recorded), not |u_j|.  When it is below
-      // tol the step ends at m = j whatever |u_j| turns out to be: y^(j) and
-      // eps are recorded here, and the column pass skips this iteration's
-      // apply and only records |u_j| and the status.
+      // The extra last workgroup records alpha_{j-1} and (j = 1) finalizes
+      // the observables of the step's first vector: [diag, docc, n2,
+      // down-hop part] from its row pass plus the up-hop part from its
+      // column pass.  The estimate for m = j needs only T_j (alpha_{j-1} =
+      // al, the rest recorded), not |u_j|.  When it is below tol the step
+      // ends at m = j whatever |u_j| turns out to be: y^(j) and eps are
+      // recorded here, and the column pass skips this iteration's apply and
+      // only records |u_j| and the status.
+      if (tid == 0 && p.st[0].status == 0) p.st[0].alpha[p.j - 1] = al;
+      if (p.obs_row) {
+        for (int t = 0; t < kObsQ; ++t) {
+          double s2 = reduce_column<kWavesA>(p.obs_row, p.dim_up_rows, kObsQ, t, red);
+          if (t == kObsQ - 1) s2 += reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, p.alpha_stride, 1, red);
+          if (tid == 0) p.st[0].obs[t] = s2;
+        }
+      }
       if (tid < 64) {
         VecState& S = p.st[0];
         bool stop = false;
@@ -156,16 +167,6 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
         if (tid == 0) p.ctl->eps_stop = stop ? p.j : -1;
       }
       return;
-    }
-    if (blockIdx.x == 0 && tid == 0 && p.st[0].status == 0) p.st[0].alpha[p.j - 1] = al;
-    if (blockIdx.x == 0 && p.obs_row) {
-      // observables of the step's first vector: [diag, docc, n2, down-hop
-      // part] from its row pass plus the up-hop part from its column pass
-      for (int t = 0; t < kObsQ; ++t) {
-        double s2 = reduce_column<kWavesA>(p.obs_row, p.dim_up_rows, kObsQ, t, red);
-        if (t == kObsQ - 1) s2 += reduce_column<kWavesA>(p.alpha_partials, p.alpha_nblk, p.alpha_stride, 1, red);
-        if (tid == 0) p.st[0].obs[t] = s2;
-      }
     }
     c_upd = static_cast<R>(al * p.st[0].scale[p.j - 1]);
   } else if (kL) {
