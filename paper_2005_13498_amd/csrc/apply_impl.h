@@ -97,6 +97,8 @@ __device__ __forceinline__ void block_partials_seq(const double (&vals)[NQ], int
 // UPH = false: row pass of the two-pass apply (diagonal and down hops only;
 // in Lanczos mode the prologue still takes the Krylov decision, and the raw
 // partial product is written for the column pass to finish).
+// FUSE: row pass of a fused Lanczos iteration j >= 1 (forms u_j first; one
+// extra workgroup for the recording and the early estimate, see below).
 // GDN: rows too long for LDS (16 sites): the down hops read the row of x in
 // global memory (it stays in L2) and decode sign and padding from the index.
 template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE, bool GDN>
