@@ -81,6 +81,14 @@ def test_lanczos_two_pass_matches_one_pass_and_oracle():
             res[path] = (x.cpu().numpy(), obs, log)
         assert _rel(res[1][0], res[0][0]) < 1e-12
         assert np.max(np.abs(res[1][1] - res[0][1])) < 1e-12
+        # the fused path ends most steps from the row pass's early estimate
+        # (y^(m), eps recorded there, |u_m| and the status by the column pass):
+        # the same step logs as the one-pass decision
+        lg0, lg1 = res[0][2], res[1][2]
+        assert np.array_equal(lg1[:, :, 0], lg0[:, :, 0])  # m
+        assert np.array_equal(lg1[:, :, 2:4], lg0[:, :, 2:4])  # converged, breakdown
+        assert np.allclose(lg1[:, :, 4], lg0[:, :, 4], rtol=0.05, atol=1e-16)  # eps (a difference of nearby vectors)
+        assert np.allclose(lg1[:, :, 5], lg0[:, :, 5], rtol=1e-10)  # beta of the last vector
         v = g.copy()
         for k in range(n):
             v = midpoint_step_exact(ham, v, k * w.dt, w.dt, w.pulse)
