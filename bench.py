@@ -143,12 +143,14 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
     print("\n".join(lines))
 
 
-def summarize_stats(trace_dir: str, out: str, command: str, top: int = 16) -> None:
-    """Top kernels of a --kernel-trace --stats run as text."""
+def summarize_stats(trace_dir: str, out: str, command: str, top: int = 16, note: str = "") -> None:
+    """Top kernels of a --kernel-trace --stats run as text (and the fused
+    iteration's split when the trace has it)."""
     rows = _rows(_find(trace_dir, "kernel_stats.csv"))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}",
-             f"{'calls':>8} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}"]
+    lines += [f"# {x}" for x in note.split("|") if x]
+    lines += [f"{'calls':>8} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
     for r in rows[:top]:
         lines.append(f"{int(r['Calls']):>8} {float(r['AverageNs']) / 1e3:>10.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}  {r['Name'][:150]}")
@@ -156,7 +158,7 @@ def summarize_stats(trace_dir: str, out: str, command: str, top: int = 16) -> No
         trace = _rows(_find(trace_dir, "kernel_trace.csv"))
     except SystemExit:
         trace = []
-    if trace:
+    if trace and any(want in r["Kernel_Name"] for r in trace for want in DOMINANT_KERNELS):
         lines += ["", "# fused Lanczos iteration (the roofline kernel pair), from the per-dispatch trace:",
                   f"# dispatches under {EARLY_EXIT_FRACTION} x the kernel's 90th percentile are speculative launches past",
                   "# the Krylov decision (they exit at once) or the skipped column pass of a step's last iteration,",
@@ -708,6 +710,9 @@ def main() -> int:
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
     ap.add_argument("--summarize-stats", nargs=2, metavar=("TRACE_DIR", "OUT"))
     ap.add_argument("--command", default="", help="profiling command recorded in a summary")
+    ap.add_argument("--note", default="", help="comment lines (separated by |) recorded in a summary")
+    ap.add_argument("--variant", choices=("greens_ring10", "ring14_block", "ring8"),
+                    help="run only this variant and print its result (for profiling it alone)")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -717,7 +722,7 @@ def main() -> int:
         summarize_counters(*args.summarize_counters, command=args.command)
         return 0
     if args.summarize_stats:
-        summarize_stats(*args.summarize_stats, command=args.command)
+        summarize_stats(*args.summarize_stats, command=args.command, note=args.note)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -730,6 +735,12 @@ def main() -> int:
 
     import paper_2005_13498_amd as hub
     from synth import workloads
+
+    if args.variant:
+        torch.cuda.set_device(0)
+        run = {"greens_ring10": greens_variant, "ring14_block": ring14_block_variant, "ring8": ring8_variant}
+        print(json.dumps({args.variant: run[args.variant](hub)}), flush=True)
+        return 0
 
     w = workloads()["cluster3x4"]
     dev = "cuda:0"

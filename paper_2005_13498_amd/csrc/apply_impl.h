@@ -398,6 +398,20 @@ hipError_t launch_ev(K fn, int grid, int blk, size_t lds, hipStream_t st, hipEve
   return hipExtLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(blk), kargs, lds, st, e0, e1, 0);
 }
 
+// Opts kernel fn into the largest dynamic LDS a CU allows (160 KB minus its
+// static LDS); returns the dynamic LDS bytes a launch may then request.
+inline int dyn_lds_opt_in(const void* fn) {
+  hipFuncAttributes fa{};
+  size_t stat = 0;
+  if (hipFuncGetAttributes(&fa, fn) == hipSuccess) stat = fa.sharedSizeBytes;
+  const int want = 160 * 1024 - static_cast<int>(stat);
+  const int got = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess
+                      ? want
+                      : 64 * 1024 - static_cast<int>(stat);
+  (void)hipGetLastError();  // a refused opt-in is not a launch error
+  return got;
+}
+
 template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE, bool GDN = false>
 hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   const DevBasis& db = *L.db;
@@ -420,8 +434,10 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.up_hops = db.up_hops;
   p.dn_tab = db.dn_tab;
   for (int s = 0; s < 64; ++s) p.slot_class[s] = db.slot_class[s];
+  // the caller's coefficient arrays hold [nv][nc] complex pairs, no more
+  const int ncoef = 2 * L.nv * db.nc;
   if (NV > 1) {
-    for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef[k] = L.coef ? L.coef[k] : 0.0;
+    for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef[k] = (L.coef && k < ncoef) ? L.coef[k] : 0.0;
   } else {
     for (int sl = 0; sl < 64; ++sl) {
       const int c = db.slot_class[sl];
@@ -430,7 +446,7 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
       p.slot_coef_obs[2 * sl + 1] = ok ? L.coef_obs[2 * c + 1] : 0.0;
     }
   }
-  for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef_obs[k] = L.coef_obs ? L.coef_obs[k] : 0.0;
+  for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef_obs[k] = (L.coef_obs && k < ncoef) ? L.coef_obs[k] : 0.0;
   for (int s = 0; s < 64; ++s) {
     const int c = db.slot_class[s];
     p.slot_coef[2 * s] = (s < db.nslots && L.coef) ? L.coef[2 * c] : 0.0;
@@ -460,19 +476,9 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.dim_up_rows = db.dim_up;
   p.norm_out = L.norm_partials;
   auto fn = k_apply<R, NV, MODE, MAXS, BLK, UPH, FUSE, GDN>;
-  // dynamic LDS above the 64 KB default must be opted into (CU total 160 KB)
-  static int max_dyn = -1;
-  if (max_dyn < 0) {
-    hipFuncAttributes fa{};
-    size_t stat = 0;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(fn)) == hipSuccess) stat = fa.sharedSizeBytes;
-    const int want = 160 * 1024 - static_cast<int>(stat);
-    max_dyn = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  want) == hipSuccess
-                  ? want
-                  : 64 * 1024 - static_cast<int>(stat);
-    (void)hipGetLastError();  // a refused opt-in is not a launch error
-  }
+  // dynamic LDS above the 64 KB default must be opted into (CU total 160 KB);
+  // once per kernel, also when host threads launch it concurrently
+  static const int max_dyn = dyn_lds_opt_in(reinterpret_cast<const void*>(fn));
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
   // fused row pass: one more workgroup for the early estimate
   return launch_ev(fn, FUSE ? grid + 1 : grid, BLK, lds, L.stream, L.ev_start, L.ev_stop, p);
@@ -651,18 +657,7 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   const int grid = colpass_grid(db);
   const size_t lds = colpass_lds_bytes(db, sizeof(R) == 8 ? 0 : 1);
   auto fn = k_colpass<R, MODE, MAXS, BLK, FUSE>;
-  static int max_dyn = -1;
-  if (max_dyn < 0) {
-    hipFuncAttributes fa{};
-    size_t stat = 0;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(fn)) == hipSuccess) stat = fa.sharedSizeBytes;
-    const int want = 160 * 1024 - static_cast<int>(stat);
-    max_dyn = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  want) == hipSuccess
-                  ? want
-                  : 64 * 1024 - static_cast<int>(stat);
-    (void)hipGetLastError();  // a refused opt-in is not a launch error
-  }
+  static const int max_dyn = dyn_lds_opt_in(reinterpret_cast<const void*>(fn));
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
   if (pgrid) *pgrid = grid;
   // fused: one more workgroup for the Krylov decision
