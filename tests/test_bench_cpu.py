@@ -28,6 +28,13 @@ def test_early_exit_cut_separates_speculative_dispatches():
     vals = work * 5 + early      # mostly working dispatches
     cut = bench.early_exit_cut(vals)
     assert max(early) < cut < min(work)
+    # a short run where fewer than a quarter of the column passes work: two
+    # working, one skipped apply (the step's last iteration) and six early
+    # exits per step, as in a counter run from the ground state
+    col = ([20923.0] * 2 + [16.0] + [10.0] * 6) * 12
+    cut = bench.early_exit_cut(col)
+    assert 16.0 < cut < 20923.0
+    assert sum(1 for x in col if x >= cut) == 24
 
 
 def test_counter_summary_scales_by_copy_and_drops_early_exits(tmp_path, monkeypatch):
