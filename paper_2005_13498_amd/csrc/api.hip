@@ -546,11 +546,12 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     }
     return HUB_OK;
   };
+  // the combine also records the (sub)step: log, observables, cleared control block
   auto finish_sub = [&](int n, int sub) -> hub_status {
-    HUB_HIP(hub::launch_combine(pi, nv, dim, W.slot_ptrs, W.st, W.ctl, W.partials_e, stream));
-    HUB_HIP(hub::launch_step_log(nv, W.st, W.ctl, dlog_c + (static_cast<size_t>(n) * S + sub) * nv,
-                                 (want_obs && sub == 0) ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr,
-                                 kObsQ, stream));
+    HUB_HIP(hub::launch_combine(pi, nv, dim, W.slot_ptrs, W.st, W.ctl, W.partials_e, n * S + sub + 1,
+                                dlog_c + (static_cast<size_t>(n) * S + sub) * nv,
+                                (want_obs && sub == 0) ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr,
+                                kObsQ, stream));
     return HUB_OK;
   };
 
@@ -567,7 +568,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     *maxed = false;
     for (int sub = sub0; sub < S; ++sub) {
       // later substeps need no step_begin: tau is set, k_combine left the
-      // |v|^2 partials and k_step_log cleared the control block
+      // |v|^2 partials and cleared the control block
       if (first) HUB_HIP(hub::launch_step_begin(pi, nv, dim, slot0, W.st, W.ctl, tau, true, W.partials_e, stream));
       first = false;
       int j = 0;
@@ -672,6 +673,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       }
       StepCtl c0 = *W.h_ctl;
       c0.abort = 0;
+      c0.halt_from = 0;
       c0.steps_done = 0;
       c0.all_done = 0;
       c0.any_maxed = 0;
@@ -760,6 +762,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       }
       StepCtl c1 = *W.h_ctl;
       c1.abort = 0;
+      c1.halt_from = 0;
       c1.all_done = 0;
       c1.any_maxed = 0;
       c1.iter = 0;

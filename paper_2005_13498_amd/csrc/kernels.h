@@ -37,6 +37,7 @@ struct StepCtl {
   int32_t abort;             // a step ended undecided: later kernels do nothing
   int32_t steps_done;        // (sub)steps logged since the host last cleared it
   int32_t eps_stop;          // fused iteration j whose row pass found the estimate for m = j below tol, else -1
+  int32_t halt_from;         // > 0: (sub)step sequence number from which combines do nothing (a vector hit m_max)
   double tol;
   double norm_inf;
 };
@@ -147,20 +148,26 @@ hipError_t launch_reorth(int prec, int nv, int64_t n, void* const* slots_dev, in
 // [n_members][n_nu] (device); lesser[m] (host) selects conj(o) for removal.
 hipError_t launch_spectral(int n_members, int n_s, const void* overlaps, const int32_t* lesser, double dt, double eps,
                            int n_nu, const double* nu, double* out, hipStream_t s);
-// v = beta0 sum_k y_k s_k u_k over the m_v vectors of each vector v (in place
-// into slot 0), and |v|^2 partials [elem_grid][nv].  If some vector is still
-// undecided the step is abandoned: ctl->abort is set and slot 0 is kept.
-hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
-                          StepCtl* ctl, double* partials, hipStream_t s);
-
-// |v|^2 partials of the step input (if norm), tau of every vector, cleared control block.
-hipError_t launch_step_begin(int prec, int nv, int64_t n, const void* v, VecState* st, StepCtl* ctl, double tau,
-                             bool norm, double* partials, hipStream_t s);
-
 struct CombineLog {
   int32_t m, status;
   double eps, beta_last;
 };
+
+// v = beta0 sum_k y_k s_k u_k over the m_v vectors of each vector v (in place
+// into slot 0), and |v|^2 partials [elem_grid][nv].  If some vector is still
+// undecided the step is abandoned: ctl->abort is set and slot 0 is kept.
+// Otherwise the first workgroup also records the step (as launch_step_log:
+// log [nv] and, if obs_log, the first apply's observables [nv][nobs]) and
+// clears the control block for the next step; seq >= 1 numbers the
+// (sub)steps of a call, and after one where a vector hit m_max the later
+// combines do nothing.
+hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
+                          StepCtl* ctl, double* partials, int seq, CombineLog* log, double* obs_log, int nobs,
+                          hipStream_t s);
+
+// |v|^2 partials of the step input (if norm), tau of every vector, cleared control block.
+hipError_t launch_step_begin(int prec, int nv, int64_t n, const void* v, VecState* st, StepCtl* ctl, double tau,
+                             bool norm, double* partials, hipStream_t s);
 
 // Copies the finished step's Krylov report and first-apply observables.
 hipError_t launch_step_log(int nv, const VecState* st, StepCtl* ctl, void* log, double* obs_log, int nobs,

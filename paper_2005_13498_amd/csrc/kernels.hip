@@ -67,11 +67,46 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, typename CT<R>::T*
   block_partials<NV>(&n2, 1, red, partials + (size_t)blockIdx.x * NV);
 }
 
+// Records a finished step (workgroup 0 of its combine, or k_step_log):
+// Krylov report into log, first-apply observables into obs_log, and a cleared
+// control block; after a step where a vector hit m_max, the combines from
+// sequence number seq + 1 on do nothing and the Lanczos kernels stay idle.
+template <int NV>
+__device__ void record_step(const VecState* st, StepCtl* ctl, CombineLog* log, double* obs_log, int nobs, int seq) {
+  const int v = threadIdx.x;
+  if (v < NV) {
+    const VecState& S = st[v];
+    if (log) {
+      log[v].m = S.m;
+      log[v].status = S.status;
+      log[v].eps = S.eps;
+      log[v].beta_last = S.m > 0 ? S.beta[S.m - 1] : 0.0;
+    }
+    if (obs_log)
+      for (int k = 0; k < nobs; ++k) obs_log[v * nobs + k] = S.obs[k];
+  }
+  if (v == 0) {
+    ctl->all_done = 0;
+    ctl->any_maxed = 0;
+    ctl->iter = 0;
+    ctl->steps_done += 1;
+    int maxed = 0;
+    for (int w = 0; w < NV; ++w) maxed |= (st[w].status == 3);
+    if (maxed && log) {  // a vector hit m_max: later enqueued steps do nothing
+      ctl->halt_from = seq + 1;
+      ctl->all_done = 1;
+    }
+  }
+}
+
 // v <- beta0 sum_{k<m_v} s_k y_k u_k into slot 0, and |v|^2 partials for the
-// next step's first apply.
+// next step's first apply; workgroup 0 then records the step (its other
+// workgroups read the control block only at their start, and the record's
+// halt applies from the next sequence number on).
 template <typename R, int NV>
 __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, void* const* slots, const VecState* st,
-                                                    StepCtl* ctl, double* partials) {
+                                                    StepCtl* ctl, double* partials, int seq, CombineLog* log,
+                                                    double* obs_log, int nobs) {
   using V = typename CT<R>::T;
   __shared__ double red[kWaves * kMaxNV];
   __shared__ double cr[kMaxNV][kMMax], ci[kMaxNV][kMMax];
@@ -79,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, void* const* slot
   const int tid = threadIdx.x;
   // A step whose launches ended before every vector was decided is abandoned
   // with slot 0 unchanged; the flag makes the rest of the enqueued work idle.
-  if (ctl->abort) return;
+  if (ctl->abort || (ctl->halt_from > 0 && seq >= ctl->halt_from)) return;
   bool undecided = false;
   for (int v = 0; v < NV; ++v) undecided |= (st[v].status == 0);
   if (undecided) {
@@ -115,6 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, void* const* slot
     n2 += (double)o.x * o.x + (double)o.y * o.y;
   }
   block_partials<NV>(&n2, 1, red, partials + (size_t)blockIdx.x * NV);
+  if (blockIdx.x == 0) record_step<NV>(st, ctl, log, obs_log, nobs, seq);
 }
 
 // |v|^2 partials of the step's input (first step of a call), tau for every
@@ -143,36 +179,12 @@ __global__ __launch_bounds__(kBlock) void k_step_begin(int64_t n, const typename
   }
 }
 
-// Records the finished step (into log) and clears the control block; does
-// nothing after an abandoned step.
+// Records the observables of the last sample time (no log): a cleared
+// control block and obs_log; nothing after an abandoned step.
 template <int NV>
 __global__ void k_step_log(const VecState* st, StepCtl* ctl, CombineLog* log, double* obs_log, int nobs) {
   if (ctl->abort) return;
-  const int v = threadIdx.x;
-  if (v < NV) {
-    const VecState& S = st[v];
-    if (log) {
-      log[v].m = S.m;
-      log[v].status = S.status;
-      log[v].eps = S.eps;
-      log[v].beta_last = S.m > 0 ? S.beta[S.m - 1] : 0.0;
-    }
-    if (obs_log)
-      for (int k = 0; k < nobs; ++k) obs_log[v * nobs + k] = S.obs[k];
-  }
-  __syncthreads();
-  if (v == 0) {
-    ctl->all_done = 0;
-    ctl->any_maxed = 0;
-    ctl->iter = 0;
-    ctl->steps_done += 1;
-    int maxed = 0;
-    for (int w = 0; w < NV; ++w) maxed |= (st[w].status == 3);
-    if (maxed && log) {  // a vector hit m_max: later enqueued steps do nothing
-      ctl->abort = 2;
-      ctl->all_done = 1;
-    }
-  }
+  record_step<NV>(st, ctl, log, obs_log, nobs, 0);
 }
 
 // Column sums (op 0) or maxima (op 1) of a [nrows][ncols] partial array,
@@ -646,14 +658,15 @@ hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, V
 }
 
 hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
-                          StepCtl* ctl, double* partials, hipStream_t s) {
+                          StepCtl* ctl, double* partials, int seq, CombineLog* log, double* obs_log, int nobs,
+                          hipStream_t s) {
   const int grid = elem_grid(n * nv);
   if (prec == 0) {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_combine<double, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
-                                         st, ctl, partials));
+                                         st, ctl, partials, seq, log, obs_log, nobs));
   } else {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_combine<float, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
-                                         st, ctl, partials));
+                                         st, ctl, partials, seq, log, obs_log, nobs));
   }
   return hipGetLastError();
 }
