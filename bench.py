@@ -46,6 +46,7 @@ def early_exit_cut(vals) -> float:
     return EARLY_EXIT_FRACTION * v[(9 * (len(v) - 1)) // 10]
 UNIT_BYTES = 4 * 853776 * 16  # read w_{j-1}, u_{j-1}; write u_j, y
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "lanczos_iter_c128_cluster3x4_counters.txt")
+STATS_FILE = os.path.join(ROOT, "profiles", "bench_cluster3x4_c128_kernel_stats.txt")
 KERNEL_SOURCES = ("paper_2005_13498_amd/csrc/apply_impl.h", "paper_2005_13498_amd/csrc/kernels_common.h",
                   "paper_2005_13498_amd/csrc/apply_c128.hip", "paper_2005_13498_amd/csrc/kernels.h",
                   "paper_2005_13498_amd/csrc/kernels.hip")
@@ -77,6 +78,35 @@ def measured_traffic():
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def traced_pair_us():
+    """Average kernel time (us) of a working fused iteration in the committed
+    rocprofv3 trace summary of this workload, or None if there is none or the
+    kernel sources changed since."""
+    try:
+        kv = {}
+        with open(STATS_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return float(kv["fused_iteration_avg_us (both kernels, working dispatches)"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def trace_figure(bytes_per: float):
+    """The same kernel pair as timed by the committed rocprofv3 trace (kernel
+    execution only; HIP events also count their own timestamping), or None."""
+    us = traced_pair_us()
+    if not us:
+        return None
+    gbs = bytes_per / (us * 1e-6) / 1e9
+    return {"avg_launch_us": us, "achieved": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "source": os.path.relpath(STATS_FILE, ROOT)}
 
 
 def _rows(path):
@@ -177,6 +207,7 @@ def summarize_stats(trace_dir: str, out: str, command: str, top: int = 16, note:
             lines.append(f"{want}: working {len(work)} avg_us {avg:.2f}; early exits {len(early)}"
                          + (f" avg_us {sum(early) / len(early):.2f}" if early else ""))
         lines.append(f"fused_iteration_avg_us (both kernels, working dispatches): {tot:.2f}")
+        lines.append(f"kernel_source_sha256_16: {kernel_source_hash()}")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -811,6 +842,7 @@ def main() -> int:
                                "+ k_colpass (up hops, Lanczos epilogue, Krylov decision)",
                      "bytes_per_launch": bytes_per, "avg_launch_us": avg_us,
                      "timed_launches": launches, "event_sampling": f"every {PROFILE_PERIOD}th H*v",
+                     "trace": trace_figure(bytes_per),
                      "kernels": "sum of both kernel times; bytes = 4 N s (read w_{j-1}, u_{j-1}; write u_j, y)"},
     }
     if args.copy_calibration:

@@ -59,3 +59,35 @@ def test_counter_summary_scales_by_copy_and_drops_early_exits(tmp_path, monkeypa
     out.write_text(txt.replace(bench.kernel_source_hash(), "0000000000000000"))
     assert bench.measured_traffic() is None
 
+
+
+def test_stats_summary_and_traced_pair_time(tmp_path, monkeypatch):
+    row, col = (f"void hub::dev::{bench.DOMINANT_KERNELS[0]}(hub::dev::KArgs)",
+                f"void hub::dev::{bench.DOMINANT_KERNELS[1]}(hub::dev::ColArgs)")
+    d = tmp_path / "trace"
+    d.mkdir()
+    with open(d / "run_kernel_stats.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "AverageNs", "TotalDurationNs", "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": row, "Calls": 6, "AverageNs": 12000, "TotalDurationNs": 72000, "Percentage": 60})
+        w.writerow({"Name": col, "Calls": 6, "AverageNs": 8000, "TotalDurationNs": 48000, "Percentage": 40})
+    # per step: two working pairs, the last column pass skipped, one early-exit pair
+    durs = [(row, 16000), (col, 14000), (row, 16000), (col, 14000), (row, 16000), (col, 3500),
+            (row, 3000), (col, 3000)] * 2
+    t = 0
+    with open(d / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, ns in durs:
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": t, "End_Timestamp": t + ns})
+            t += ns + 500
+    out = tmp_path / "stats.txt"
+    bench.summarize_stats(str(d), str(out), command="synthetic", note="one|two")
+    txt = out.read_text()
+    assert "# one" in txt and "# two" in txt
+    assert "working 6 avg_us 16.00" in txt and "working 4 avg_us 14.00" in txt
+    monkeypatch.setattr(bench, "STATS_FILE", str(out))
+    assert bench.traced_pair_us() == pytest.approx(30.0)
+    assert bench.trace_figure(4 * 853776 * 16)["avg_launch_us"] == pytest.approx(30.0)
+    out.write_text(txt.replace(bench.kernel_source_hash(), "0000000000000000"))
+    assert bench.traced_pair_us() is None and bench.trace_figure(1.0) is None
