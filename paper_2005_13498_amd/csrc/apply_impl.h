@@ -526,7 +526,9 @@ struct ColArgs {
 };
 
 // FUSE: the row pass formed u_j; reduce its norm here and take the decision.
-template <typename R, int MODE, int MAXS, int BLK, bool FUSE>
+// ONE: a single staged copy (+x and the zero row; tiles whose two copies do
+// not fit LDS): a negative hop's index src + dim_up + 1 reads +x and negates.
+template <typename R, int MODE, int MAXS, int BLK, bool FUSE, bool ONE>
 __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   using V = typename CT<R>::T;
   constexpr bool kL = MODE == M_LANCZOS || MODE == M_LANCZOS_OBS;
@@ -581,7 +583,7 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
     V v = V{0, 0};
     if (a < p.dim_up && b0 + c < p.dim_dn) v = x[(size_t)a * p.dim_dn + b0 + c];
     xs[t] = v;
-    xs[half + t] = V{-v.x, -v.y};
+    if (!ONE) xs[half + t] = V{-v.x, -v.y};
   }
   __syncthreads();
   const uint2* tab2 = reinterpret_cast<const uint2*>(p.up_tab);
@@ -602,7 +604,15 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
     for (int s = 0; s < MAXS; ++s) {
       const uint32_t w2 = (s & 3) < 2 ? ev[s >> 2].x : ev[s >> 2].y;
       const uint32_t idx = (s & 1) ? (w2 >> 16) : (w2 & 0xFFFFu);
-      const V t = xs[idx * kColW + c];
+      V t;
+      if (ONE) {  // index = src, src + dim_up + 1 (negative hop), or dim_up (the zero row)
+        const uint32_t du = static_cast<uint32_t>(p.dim_up);
+        const bool neg = idx > du;
+        t = xs[(neg ? idx - du - 1 : idx) * kColW + c];
+        if (neg) t = V{-t.x, -t.y};
+      } else {
+        t = xs[idx * kColW + c];
+      }
       const V cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
       acc = cfma(cf, t, acc);
       if (kO) ko = cfma(make_double2(p.slot_coef_obs[2 * s], p.slot_coef_obs[2 * s + 1]), make_double2(t.x, t.y), ko);
@@ -626,7 +636,7 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   }
 }
 
-template <typename R, int MODE, int MAXS, bool FUSE>
+template <typename R, int MODE, int MAXS, bool FUSE, bool ONE>
 hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   const DevBasis& db = *L.db;
   constexpr int BLK = 1024;
@@ -656,7 +666,7 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   p.partials = L.partials;
   const int grid = colpass_grid(db);
   const size_t lds = colpass_lds_bytes(db, sizeof(R) == 8 ? 0 : 1);
-  auto fn = k_colpass<R, MODE, MAXS, BLK, FUSE>;
+  auto fn = k_colpass<R, MODE, MAXS, BLK, FUSE, ONE>;
   static const int max_dyn = dyn_lds_opt_in(reinterpret_cast<const void*>(fn));
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
   if (pgrid) *pgrid = grid;
@@ -664,20 +674,26 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   return launch_ev(fn, FUSE ? grid + 1 : grid, BLK, lds, L.stream, L.ev2_start, L.ev2_stop, p);
 }
 
-template <typename R, int MODE, bool FUSE = false>
-hipError_t colpass_s(const ApplyLaunch& L, int* pgrid) {
+template <typename R, int MODE, bool FUSE, bool ONE>
+hipError_t colpass_w(const ApplyLaunch& L, int* pgrid) {
   switch (L.db->up_maxs_pad) {
-    case 4: return colpass_t<R, MODE, 4, FUSE>(L, pgrid);
-    case 8: return colpass_t<R, MODE, 8, FUSE>(L, pgrid);
-    case 12: return colpass_t<R, MODE, 12, FUSE>(L, pgrid);
-    case 16: return colpass_t<R, MODE, 16, FUSE>(L, pgrid);
-    case 20: return colpass_t<R, MODE, 20, FUSE>(L, pgrid);
-    case 24: return colpass_t<R, MODE, 24, FUSE>(L, pgrid);
-    case 32: return colpass_t<R, MODE, 32, FUSE>(L, pgrid);
-    case 48: return colpass_t<R, MODE, 48, FUSE>(L, pgrid);
-    case 64: return colpass_t<R, MODE, 64, FUSE>(L, pgrid);
+    case 4: return colpass_t<R, MODE, 4, FUSE, ONE>(L, pgrid);
+    case 8: return colpass_t<R, MODE, 8, FUSE, ONE>(L, pgrid);
+    case 12: return colpass_t<R, MODE, 12, FUSE, ONE>(L, pgrid);
+    case 16: return colpass_t<R, MODE, 16, FUSE, ONE>(L, pgrid);
+    case 20: return colpass_t<R, MODE, 20, FUSE, ONE>(L, pgrid);
+    case 24: return colpass_t<R, MODE, 24, FUSE, ONE>(L, pgrid);
+    case 32: return colpass_t<R, MODE, 32, FUSE, ONE>(L, pgrid);
+    case 48: return colpass_t<R, MODE, 48, FUSE, ONE>(L, pgrid);
+    case 64: return colpass_t<R, MODE, 64, FUSE, ONE>(L, pgrid);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename R, int MODE, bool FUSE = false>
+hipError_t colpass_s(const ApplyLaunch& L, int* pgrid) {
+  return colpass_single(*L.db, sizeof(R) == 8 ? 0 : 1) ? colpass_w<R, MODE, FUSE, true>(L, pgrid)
+                                                        : colpass_w<R, MODE, FUSE, false>(L, pgrid);
 }
 
 template <typename R, int MODE, int BLK>

@@ -542,8 +542,14 @@ int apply_chunks(const DevBasis& db, int prec, int nv) {
 
 int colpass_grid(const DevBasis& db) { return (db.dim_dn + kColW - 1) / kColW; }
 
+// +x, -x and a zero row; a single copy (+x, zero row) when both do not fit,
+// the sign then taken from the stage index
+bool colpass_single(const DevBasis& db, int prec) {
+  return 2 * (static_cast<size_t>(db.dim_up) + 1) * kColW * (prec == 0 ? 16 : 8) > 150 * 1024;
+}
 size_t colpass_lds_bytes(const DevBasis& db, int prec) {
-  return 2 * (static_cast<size_t>(db.dim_up) + 1) * kColW * (prec == 0 ? 16 : 8);  // +x, -x, zero row
+  const size_t copy = (static_cast<size_t>(db.dim_up) + 1) * kColW * (prec == 0 ? 16 : 8);
+  return colpass_single(db, prec) ? copy : 2 * copy;
 }
 
 bool apply_global_rows(const DevBasis& db, int prec, int nv) {
