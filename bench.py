@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # Fused Lanczos iteration of the 12-site complex128 vector (update of u_j +
 # two-pass H*v + epilogue): row pass without up hops that also forms u_j, and
 # the column pass; 20 padded hop slots
-DOMINANT_KERNELS = ("k_apply<double, 1, 1, 20, 256, false, true, false>", "k_colpass<double, 1, 20, 1024, true, false>")
+DOMINANT_KERNELS = ("k_apply<double, 1, 1, 20, 256, false, true, false>", "k_colpass<double, 1, 20, 1024, true, false, 4>")
 # Speculative iterations enqueued past a step's Krylov decision exit at once,
 # and the column pass of a step's last fused iteration skips its apply; a
 # dispatch below this fraction of the kernel's 90th percentile (time or bytes;

@@ -373,11 +373,11 @@ hub_status hub_set_schedule(hub_basis basis, int32_t chunk, int32_t margin);
  * Lanczos iterations that do not also accumulate observables).
  *   path 0: one pass (rows staged in LDS; up hops gathered as whole rows of
  *           x from global memory);
- *   path 1: two passes whenever 4 columns of x for all up strings fit in LDS
- *           (a row pass for the diagonal and the down hops, then a column
- *           pass that stages those columns, as +x and -x or, when two
- *           copies do not fit, as +x with the sign taken from the hop's
- *           index, and adds the up hops);
+ *   path 1: two passes whenever 4 (else 2) columns of x for all up
+ *           strings fit in LDS (a row pass for the diagonal and the down
+ *           hops, then a column pass that stages those columns, as +x and
+ *           -x or, when two copies do not fit, as +x with the sign taken
+ *           from the hop's index, and adds the up hops);
  *   path -1 (default): two passes when they fit and the vector is larger
  *           than 4 MiB, one pass otherwise.
  * Plain applies give bit-identical results on both paths; in Lanczos mode

@@ -214,7 +214,8 @@ hub_status ensure_workspace(hub_basis h, Work& W, size_t slot_bytes, int nslots,
     for (int nv = 1; nv <= kMaxNV; nv *= 2)
       pb = std::max(pb, static_cast<size_t>(hub::apply_grid(h->D, pr, nv)) * (1 + kObsQ) * nv * sizeof(double));
   // two-pass regions: column-pass partials, row-pass obs partials, row norms
-  pb = std::max(pb, (2 * static_cast<size_t>(hub::colpass_grid(h->D)) +
+  const int cgmax = std::max(hub::colpass_grid(h->D, 0), hub::colpass_grid(h->D, 1));
+  pb = std::max(pb, (2 * static_cast<size_t>(cgmax) +
                      static_cast<size_t>(h->D.dim_up) * (kObsQ + 1)) * sizeof(double));
   if (pb > W.partials_bytes) {
     if (W.partials) HUB_HIP(hipFree(W.partials));
@@ -514,7 +515,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     // a two-pass apply with observables leaves the row pass's partials after
     // the column pass's
     const bool two_obs = A.obs && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
-    const size_t cg2 = 2 * static_cast<size_t>(hub::colpass_grid(h->D));
+    const size_t cg2 = 2 * static_cast<size_t>(hub::colpass_grid(h->D, pi));
     if (two_obs) A.row_obs = W.partials + cg2;
     // From the second iteration on, the two-pass row pass also finishes the
     // previous update (u_j = w_{j-1} - alpha s u_{j-1}) and the column pass
@@ -526,7 +527,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       const bool after_obs = jj == 1 && want_obs && sub == 0 &&
                              hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
       A.alpha_partials = W.partials;
-      A.alpha_nblk = hub::colpass_grid(h->D);
+      A.alpha_nblk = hub::colpass_grid(h->D, pi);
       A.alpha_stride = after_obs ? hub::apply_nq_two_pass(true) : 1;
       A.obs_row = after_obs ? W.partials + cg2 : nullptr;
       A.norm_partials = W.partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ;

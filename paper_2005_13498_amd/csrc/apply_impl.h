@@ -501,9 +501,9 @@ hipError_t apply_s(const ApplyLaunch& L, int grid, size_t lds) {
 }
 
 // ---------------------------------------------------------------------------
-// Column pass of the two-pass apply (one vector).  A workgroup owns kColW
+// Column pass of the two-pass apply (one vector).  A workgroup owns CW
 // consecutive columns b0.. of the tile and stages them for every up string a
-// in LDS as +x, -x and a zero row (layout [copy][a][kColW]), so an up hop is
+// in LDS as +x, -x and a zero row (layout [copy][a][CW]), so an up hop is
 // one LDS read at an index that carries its fermion sign, exactly like the
 // down hops of the row pass.  Each thread finishes elements (a, b): it adds
 // the up hops (padded, class-sorted slots, coefficients in SGPRs) to the row
@@ -528,7 +528,7 @@ struct ColArgs {
 // FUSE: the row pass formed u_j; reduce its norm here and take the decision.
 // ONE: a single staged copy (+x and the zero row; tiles whose two copies do
 // not fit LDS): a negative hop's index src + dim_up + 1 reads +x and negates.
-template <typename R, int MODE, int MAXS, int BLK, bool FUSE, bool ONE>
+template <typename R, int MODE, int MAXS, int BLK, bool FUSE, bool ONE, int CW>
 __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   using V = typename CT<R>::T;
   constexpr bool kL = MODE == M_LANCZOS || MODE == M_LANCZOS_OBS;
@@ -574,12 +574,12 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   V* xs = reinterpret_cast<V*>(smem_raw);
   const int nwork = FUSE ? gridDim.x - 1 : gridDim.x;  // column blocks
   const int lb = xcd_remap(blockIdx.x, nwork);
-  const int b0 = lb * kColW;
+  const int b0 = lb * CW;
   const V* __restrict__ x = static_cast<const V*>(p.x);
   V* __restrict__ y = static_cast<V*>(p.y);
-  const int half = (p.dim_up + 1) * kColW;
+  const int half = (p.dim_up + 1) * CW;
   for (int t = threadIdx.x; t < half; t += BLK) {
-    const int a = t / kColW, c = t % kColW;
+    const int a = t / CW, c = t % CW;
     V v = V{0, 0};
     if (a < p.dim_up && b0 + c < p.dim_dn) v = x[(size_t)a * p.dim_dn + b0 + c];
     xs[t] = v;
@@ -589,8 +589,8 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   const uint2* tab2 = reinterpret_cast<const uint2*>(p.up_tab);
   constexpr int kQ2 = MAXS / 4;
   double q_alpha = 0.0, q_hop = 0.0;
-  for (int q = threadIdx.x; q < p.dim_up * kColW; q += BLK) {
-    const int a = q / kColW, c = q % kColW;
+  for (int q = threadIdx.x; q < p.dim_up * CW; q += BLK) {
+    const int a = q / CW, c = q % CW;
     if (b0 + c >= p.dim_dn) continue;
     uint2 ev[kQ2];
 #pragma unroll
@@ -608,10 +608,10 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
       if (ONE) {  // index = src, src + dim_up + 1 (negative hop), or dim_up (the zero row)
         const uint32_t du = static_cast<uint32_t>(p.dim_up);
         const bool neg = idx > du;
-        t = xs[(neg ? idx - du - 1 : idx) * kColW + c];
+        t = xs[(neg ? idx - du - 1 : idx) * CW + c];
         if (neg) t = V{-t.x, -t.y};
       } else {
-        t = xs[idx * kColW + c];
+        t = xs[idx * CW + c];
       }
       const V cf = V{static_cast<R>(p.slot_coef[2 * s]), static_cast<R>(p.slot_coef[2 * s + 1])};
       acc = cfma(cf, t, acc);
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
     }
     V out = acc;
     if (kL) {
-      const V xv = xs[a * kColW + c];
+      const V xv = xs[a * CW + c];
       if (kO) q_hop += (double)xv.x * ko.x + (double)xv.y * ko.y;
       out.x = out.x * sj - bprev * pv.x;
       out.y = out.y * sj - bprev * pv.y;
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(BLK) void k_colpass(ColArgs p) {
   }
 }
 
-template <typename R, int MODE, int MAXS, bool FUSE, bool ONE>
+template <typename R, int MODE, int MAXS, bool FUSE, bool ONE, int CW>
 hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   const DevBasis& db = *L.db;
   constexpr int BLK = 1024;
@@ -664,9 +664,11 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   p.st = L.st;
   p.ctl = L.ctl;
   p.partials = L.partials;
-  const int grid = colpass_grid(db);
-  const size_t lds = colpass_lds_bytes(db, sizeof(R) == 8 ? 0 : 1);
-  auto fn = k_colpass<R, MODE, MAXS, BLK, FUSE, ONE>;
+  const int prec = sizeof(R) == 8 ? 0 : 1;
+  if (colpass_width(db, prec) != CW || colpass_single(db, prec) != ONE) return hipErrorInvalidValue;
+  const int grid = colpass_grid(db, prec);
+  const size_t lds = colpass_lds_bytes(db, prec);
+  auto fn = k_colpass<R, MODE, MAXS, BLK, FUSE, ONE, CW>;
   static const int max_dyn = dyn_lds_opt_in(reinterpret_cast<const void*>(fn));
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
   if (pgrid) *pgrid = grid;
@@ -674,26 +676,30 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   return launch_ev(fn, FUSE ? grid + 1 : grid, BLK, lds, L.stream, L.ev2_start, L.ev2_stop, p);
 }
 
-template <typename R, int MODE, bool FUSE, bool ONE>
+template <typename R, int MODE, bool FUSE, bool ONE, int CW>
 hipError_t colpass_w(const ApplyLaunch& L, int* pgrid) {
   switch (L.db->up_maxs_pad) {
-    case 4: return colpass_t<R, MODE, 4, FUSE, ONE>(L, pgrid);
-    case 8: return colpass_t<R, MODE, 8, FUSE, ONE>(L, pgrid);
-    case 12: return colpass_t<R, MODE, 12, FUSE, ONE>(L, pgrid);
-    case 16: return colpass_t<R, MODE, 16, FUSE, ONE>(L, pgrid);
-    case 20: return colpass_t<R, MODE, 20, FUSE, ONE>(L, pgrid);
-    case 24: return colpass_t<R, MODE, 24, FUSE, ONE>(L, pgrid);
-    case 32: return colpass_t<R, MODE, 32, FUSE, ONE>(L, pgrid);
-    case 48: return colpass_t<R, MODE, 48, FUSE, ONE>(L, pgrid);
-    case 64: return colpass_t<R, MODE, 64, FUSE, ONE>(L, pgrid);
+    case 4: return colpass_t<R, MODE, 4, FUSE, ONE, CW>(L, pgrid);
+    case 8: return colpass_t<R, MODE, 8, FUSE, ONE, CW>(L, pgrid);
+    case 12: return colpass_t<R, MODE, 12, FUSE, ONE, CW>(L, pgrid);
+    case 16: return colpass_t<R, MODE, 16, FUSE, ONE, CW>(L, pgrid);
+    case 20: return colpass_t<R, MODE, 20, FUSE, ONE, CW>(L, pgrid);
+    case 24: return colpass_t<R, MODE, 24, FUSE, ONE, CW>(L, pgrid);
+    case 32: return colpass_t<R, MODE, 32, FUSE, ONE, CW>(L, pgrid);
+    case 48: return colpass_t<R, MODE, 48, FUSE, ONE, CW>(L, pgrid);
+    case 64: return colpass_t<R, MODE, 64, FUSE, ONE, CW>(L, pgrid);
     default: return hipErrorInvalidValue;
   }
 }
 
+// staging variants: kColW columns as +x and -x, kColW columns as +x alone,
+// 2 columns as +x alone (the first that fits)
 template <typename R, int MODE, bool FUSE = false>
 hipError_t colpass_s(const ApplyLaunch& L, int* pgrid) {
-  return colpass_single(*L.db, sizeof(R) == 8 ? 0 : 1) ? colpass_w<R, MODE, FUSE, true>(L, pgrid)
-                                                        : colpass_w<R, MODE, FUSE, false>(L, pgrid);
+  const int prec = sizeof(R) == 8 ? 0 : 1;
+  if (colpass_width(*L.db, prec) == 2) return colpass_w<R, MODE, FUSE, true, 2>(L, pgrid);
+  return colpass_single(*L.db, prec) ? colpass_w<R, MODE, FUSE, true, kColW>(L, pgrid)
+                                     : colpass_w<R, MODE, FUSE, false, kColW>(L, pgrid);
 }
 
 template <typename R, int MODE, int BLK>

@@ -120,8 +120,9 @@ bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs);
 // Rows whose staged copy (+x, -x) exceeds the LDS budget (16 sites): the
 // one-pass kernel then gathers the down hops from the row in global memory.
 bool apply_global_rows(const DevBasis& db, int prec, int nv);
-int colpass_grid(const DevBasis& db);
+int colpass_width(const DevBasis& db, int prec);    // columns per column-pass workgroup (kColW or 2)
 bool colpass_single(const DevBasis& db, int prec);  // one staged copy of the columns (sign from the index)
+int colpass_grid(const DevBasis& db, int prec);
 size_t colpass_lds_bytes(const DevBasis& db, int prec);
 int apply_chunks(const DevBasis& db, int prec, int nv);  // column chunks per tile row
 int apply_nq(int mode, bool obs, int nc);

@@ -540,15 +540,25 @@ int apply_chunks(const DevBasis& db, int prec, int nv) {
   return 1;
 }
 
-int colpass_grid(const DevBasis& db) { return (db.dim_dn + kColW - 1) / kColW; }
-
-// +x, -x and a zero row; a single copy (+x, zero row) when both do not fit,
-// the sign then taken from the stage index
-bool colpass_single(const DevBasis& db, int prec) {
-  return 2 * (static_cast<size_t>(db.dim_up) + 1) * kColW * (prec == 0 ? 16 : 8) > 150 * 1024;
+// Column block of the column pass: kColW columns, staged as +x and -x, or as
+// +x alone (sign from the stage index) when two copies do not fit; 2 columns
+// of one copy when 4 do not fit either.
+static size_t colpass_copy_bytes(const DevBasis& db, int prec, int w) {
+  return (static_cast<size_t>(db.dim_up) + 1) * w * (prec == 0 ? 16 : 8);
 }
+int colpass_width(const DevBasis& db, int prec) {
+  return colpass_copy_bytes(db, prec, kColW) <= 150 * 1024 ? kColW : 2;
+}
+bool colpass_single(const DevBasis& db, int prec) {
+  return 2 * colpass_copy_bytes(db, prec, colpass_width(db, prec)) > 150 * 1024;
+}
+int colpass_grid(const DevBasis& db, int prec) {
+  const int w = colpass_width(db, prec);
+  return (db.dim_dn + w - 1) / w;
+}
+
 size_t colpass_lds_bytes(const DevBasis& db, int prec) {
-  const size_t copy = (static_cast<size_t>(db.dim_up) + 1) * kColW * (prec == 0 ? 16 : 8);
+  const size_t copy = colpass_copy_bytes(db, prec, colpass_width(db, prec));
   return colpass_single(db, prec) ? copy : 2 * copy;
 }
 
@@ -567,7 +577,7 @@ bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
 }
 
 int apply_grid(const DevBasis& db, int prec, int nv) {
-  return std::max(db.dim_up * apply_chunks(db, prec, nv), colpass_grid(db));
+  return std::max(db.dim_up * apply_chunks(db, prec, nv), colpass_grid(db, prec));
 }
 
 int apply_nq_two_pass(bool obs) { return obs ? 2 : 1; }  // column pass: alpha [, up-hop obs part]
