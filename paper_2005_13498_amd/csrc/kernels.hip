@@ -572,10 +572,11 @@ bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
   if (colpass_lds_bytes(db, prec) > 150 * 1024) return false;
   if (db.two_pass == 1) return true;
   // automatic: when a vector is larger than one XCD's L2 the up-hop row
-  // gathers of the one-pass kernel stream from the Infinity Cache.  With a
-  // single staged copy (14 sites) only the Lanczos iterations gain (fused
-  // updates); a plain apply stays faster in one pass (c128: 274 vs 310 us).
-  if (mode == kPlain && colpass_single(db, prec)) return false;
+  // gathers of the one-pass kernel stream from the Infinity Cache.  With 2
+  // staged columns (complex128, 14 sites) only the Lanczos iterations gain
+  // (fused updates); a plain apply stays faster in one pass (263 vs 306 us,
+  // while complex64's 4 single-copy columns take 151 instead of 213 us).
+  if (mode == kPlain && colpass_width(db, prec) < kColW) return false;
   return static_cast<double>(db.dim) * (prec == 0 ? 16 : 8) >= 4.0 * 1024 * 1024;
 }
 
