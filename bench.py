@@ -6,8 +6,10 @@ matrix-free H*v, the FP64 recurrence and small exponential, the combine, and
 the fused observables): 12-site 3x4 periodic cluster, t = 1, U = 8, half
 filling 6/6 (dim 853,776), field along x with A0 drawn from the seeded
 uniform [0.2, 1.0], omega = 8, sigma = 0.5, t0 = 2.5; dt = 0.005, Krylov
-tol 1e-10, m_max 30; single complex128 vector started from the ground state
-of H(0).  All inputs synthetic and resident in HBM before timing.
+tol 1e-10, m_max 30; single complex128 vector.  The ground state of H(0) is
+advanced untimed to the start of a window of K steps centred on the pulse
+(t0), so the timed steps are the pulse regime whatever K is.  All inputs
+synthetic and resident in HBM before timing.
 
 Prints one JSON line (metric, value = midpoint steps/s, roofline of the H*v
 kernel measured with HIP events over the timed region, CPU-oracle baseline).
@@ -297,7 +299,7 @@ def cpu_baseline(seconds: float, member: int = -1) -> dict:
             "host_cpus": os.cpu_count(), "host_cpu_model": model}
 
 
-def batched_variants(hub, B, v0, w, steps: int) -> dict:
+def batched_variants(hub, B, v0, t_start: float, w, steps: int) -> dict:
     """Mixed precision and batching at 12 sites: the same ground state under
     8 pulse amplitudes (the seeded A0 draws), propagated by one hub_propagate
     call with 8 members in complex64 (FP64 Lanczos scalars) and in complex128
@@ -319,17 +321,17 @@ def batched_variants(hub, B, v0, w, steps: int) -> dict:
     obs = {}
     for name, dtype, prec_bytes in (("c64_batch8", torch.complex64, 8), ("c128_batch8", torch.complex128, 16)):
         v = v0.to(dtype).repeat(nv).contiguous()
-        hub.hub_propagate(B.handle, pulses, 0.0, w.dt, 5, opts, v, want_obs=False)  # warm-up
+        hub.hub_propagate(B.handle, pulses, t_start, w.dt, 5, opts, v, want_obs=False)  # warm-up
         v = v0.to(dtype).repeat(nv).contiguous()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, o, log = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, steps, opts, v)
+        st, o, log = hub.hub_propagate(B.handle, pulses, t_start, w.dt, steps, opts, v)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         # kernel time of the fused iteration: a shorter sequential run with apply timing
         hub.hub_profile_enable(B.handle, PROFILE_PERIOD // 4)
         hub.hub_profile_read(B.handle)
-        hub.hub_propagate(B.handle, pulses, 0.0, w.dt, max(50, steps // 10), opts,
+        hub.hub_propagate(B.handle, pulses, t_start, w.dt, max(50, steps // 10), opts,
                           v0.to(dtype).repeat(nv).contiguous(), want_obs=False)
         launches, kms, bpl = hub.hub_profile_read(B.handle)
         hub.hub_profile_enable(B.handle, False)
@@ -742,7 +744,7 @@ def main() -> int:
     ap.add_argument("--summarize-stats", nargs=2, metavar=("TRACE_DIR", "OUT"))
     ap.add_argument("--command", default="", help="profiling command recorded in a summary")
     ap.add_argument("--note", default="", help="comment lines (separated by |) recorded in a summary")
-    ap.add_argument("--variant", choices=("greens_ring10", "ring14_block", "ring8"),
+    ap.add_argument("--variant", choices=("greens_ring10", "ring14_block", "ring8", "hv12"),
                     help="run only this variant and print its result (for profiling it alone)")
     args = ap.parse_args()
 
@@ -769,6 +771,12 @@ def main() -> int:
 
     if args.variant:
         torch.cuda.set_device(0)
+        if args.variant == "hv12":
+            w = workloads()["cluster3x4"]
+            B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+            print(json.dumps({"hv_12site": hv_variants(hub, B, copy_bandwidth()["gbps"])}), flush=True)
+            B.close()
+            return 0
         run = {"greens_ring10": greens_variant, "ring14_block": ring14_block_variant, "ring8": ring8_variant}
         print(json.dumps({args.variant: run[args.variant](hub)}), flush=True)
         return 0
@@ -786,9 +794,15 @@ def main() -> int:
     opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
     stream = torch.cuda.current_stream()
 
-    # warmup (untimed): the same propagation from the same state, on a copy,
-    # so that the timed steps cover the pulse from t = 0
-    t_start = 0.0
+    # The timed window is centred on the pulse whatever K is: the ground state
+    # of H(0) is first advanced (untimed, part of the setup like the ground
+    # state itself) to t_s = max(0, t0 - K dt / 2), the nearest step.  W
+    # warm-up steps then run from t_s on a copy, and the K timed steps from t_s.
+    n_pre = max(0, int(round((w.pulse.t0 - 0.5 * args.steps * w.dt) / w.dt)))
+    t_start = n_pre * w.dt
+    if n_pre > 0:
+        hub.hub_propagate(B.handle, [w.pulse], 0.0, w.dt, n_pre, opts, v, want_obs=False, want_log=False,
+                          stream=stream)
     if args.warmup > 0:
         vw = v.clone()
         hub.hub_propagate(B.handle, [w.pulse], t_start, w.dt, args.warmup, opts, vw, stream=stream)
@@ -796,8 +810,11 @@ def main() -> int:
     torch.cuda.synchronize()
 
     v_start = v.clone()
+    # events on every p-th fused iteration, at least ~20 of them in the window
+    # (a step has m - 1 ~ 5 fused iterations that do work in the pulse)
+    period = max(1, min(PROFILE_PERIOD, (5 * args.steps) // 20))
     # timed region: exactly K midpoint steps
-    hub.hub_profile_enable(B.handle, PROFILE_PERIOD)
+    hub.hub_profile_enable(B.handle, period)
     hub.hub_profile_read(B.handle)  # reset counters
     hub.hub_controller_read_stats(B.handle)
     torch.cuda.synchronize()
@@ -830,8 +847,11 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "cluster3x4 12-site periodic, U=8, 6/6 (dim 853776), FP64 single vector, "
-                               "dt=0.005, tol=1e-10, ground-state start",
+                               "dt=0.005, tol=1e-10, window of K steps centred on the pulse (ground state of H(0) advanced untimed)",
                    "A0": w.pulse.A0, "omega": w.pulse.omega, "t0": w.pulse.t0, "sigma": w.pulse.sigma,
+                   "t_window": [t_start, t_start + args.steps * w.dt], "untimed_steps_before_window": n_pre,
+                   "max_abs_A_in_window": max(abs(hub.hub_pulse_A(w.pulse, t_start + (k + 0.5) * w.dt))
+                                              for k in range(args.steps)) if args.steps else 0.0,
                    "mean_krylov_m": mean_m,
                    "schedule": {"kind": "chunked, 32 steps, margin 1", "chunks": sched["chunks"],
                                 "fallback_steps": sched["fallbacks"],
@@ -841,7 +861,7 @@ def main() -> int:
                      "kernel": "fused Lanczos iteration, complex128: k_apply row pass (forms u_j, diagonal, down hops) "
                                "+ k_colpass (up hops, Lanczos epilogue, Krylov decision)",
                      "bytes_per_launch": bytes_per, "avg_launch_us": avg_us,
-                     "timed_launches": launches, "event_sampling": f"every {PROFILE_PERIOD}th H*v",
+                     "timed_launches": launches, "event_sampling": f"every {period}th fused iteration",
                      "trace": trace_figure(bytes_per),
                      "kernels": "sum of both kernel times; bytes = 4 N s (read w_{j-1}, u_{j-1}; write u_j, y)"},
     }
@@ -857,7 +877,7 @@ def main() -> int:
         var["copy"] = copy_bandwidth()
         var["ring8"] = ring8_variant(hub)
         var["hv_12site"] = hv_variants(hub, B, var["copy"]["gbps"])
-        var.update(batched_variants(hub, B, v0, w, args.steps))
+        var.update(batched_variants(hub, B, v_start, t_start, w, args.steps))
         var["synchronous_schedule"] = synchronous_variant(hub, B, w, v_start, t_start, args.steps, v, obs,
                                                           steps_per_s)
         var["controller"] = controller_variant(hub, B, w, v0, v_start, t_start, args.steps, v, obs, steps_per_s)

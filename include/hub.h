@@ -171,6 +171,21 @@ hub_status hub_apply_H(hub_basis basis, const double *A, hub_prec prec, int32_t 
 hub_status hub_observables(hub_basis basis, const double *A, hub_prec prec, int32_t nvec,
                            const void *v, hub_obs *out, double *site_docc, void *stream);
 
+/* hub_observables without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as hub_observables
+ * (bit for bit).  Its intermediate sums live in one static device array of
+ * 512 KiB per device (allocated with the library's code object, looked up when
+ * the first handle is created on that device, held until the process ends),
+ * enough for every sector of up to 14 sites; a sector that needs more (16
+ * sites) is rejected with HUB_E_INVALID before any launch.  Every buffer in it
+ * is fully written before it is read, so nothing is cleared between calls.
+ * All calls on one device share the array: calls that overlap in time on one
+ * device (other host threads, or other streams still running one) race and
+ * must be serialised by the caller.  Synchronises `stream`. */
+hub_status hub_observables_noalloc(hub_basis basis, const double *A, hub_prec prec, int32_t nvec,
+                                   const void *v, hub_obs *out, double *site_docc, void *stream);
+
 /* One Krylov step (Alg. 6): v_k <- exp(-i dt H(A_mid_k)) v_k for nvec device
  * vectors (in place).  A_mid: host [nvec].  info: host [nvec] or NULL.
  * Returns HUB_E_NOT_CONVERGED if any vector hit m_max (its result is then
@@ -358,7 +373,8 @@ hub_status hub_controller_read_stats(hub_basis basis, hub_controller_stats *out)
  *     without waiting for the host; every step of a chunk runs
  *     min(m_max, m_ref + margin) + 1 Lanczos launches, m_ref being the largest
  *     Krylov dimension of the previous chunk's steps (the first chunk:
- *     m_hint, else 8).  A step that has not decided within its launches stops
+ *     m_hint; without a hint the call's first step runs synchronously and its
+ *     dimension is used).  A step that has not decided within its launches stops
  *     the chunk on the device and is re-run with the synchronous schedule.
  *   chunk = 0: synchronous schedule, one host round trip per (sub)step plus
  *     one per iteration beyond the previous step's m.
@@ -370,9 +386,10 @@ hub_status hub_set_schedule(hub_basis basis, int32_t chunk, int32_t margin);
 
 /* ------------------------------------------------------------------------ */
 /* Choice of the H*v kernels for single vectors (plain applies and the
- * Lanczos iterations that do not also accumulate observables).
+ * Lanczos iterations that do not also accumulate observables) and for
+ * interleaved blocks of vectors.
  *   path 0: one pass (rows staged in LDS; up hops gathered as whole rows of
- *           x from global memory);
+ *           x from global memory), for single vectors and blocks alike;
  *   path 1: two passes whenever 4 (else 2) columns of x for all up
  *           strings fit in LDS (a row pass for the diagonal and the down
  *           hops, then a column pass that stages those columns, as +x and
@@ -380,10 +397,53 @@ hub_status hub_set_schedule(hub_basis basis, int32_t chunk, int32_t margin);
  *           from the hop's index, and adds the up hops);
  *   path -1 (default): two passes when they fit and the vector is larger
  *           than 4 MiB, one pass otherwise.
+ * Blocks of 2, 4 or 8 vectors (paths 1 and -1) run the two-pass block
+ * kernels where a tile row and a tile column of the whole block fit LDS: a
+ * row pass (diagonal and down hops) and a column pass (up hops, Lanczos
+ * epilogue), each staging its row or column of all vectors once.
  * Plain applies give bit-identical results on both paths; in Lanczos mode
  * the alpha_j reduction is summed in another order (deterministic either
  * way). */
 hub_status hub_set_apply_path(hub_basis basis, int32_t path);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel plan of a basis (not in the paper: which kernels the library runs).
+ * Per precision, the library chooses (a) the H*v kernels of single vectors,
+ * one pass or two passes (hub_set_apply_path); (b) for interleaved blocks
+ * of 2, 4 or 8 vectors, the two-pass block kernels or the one-pass kernel;
+ * (c) the vectors per group when a call carries many vectors, separately for
+ * hub_apply_H and hub_propagate.  Without tuning these follow built-in rules
+ * (LDS fit and vector size); hub_tune measures them on this basis's sector:
+ * plain H*v of 8 vectors in groups of 1, 2, 4, 8 on each feasible path
+ * (`reps` timed calls each, HIP events), then one midpoint step of 8 vectors
+ * per group size on the chosen paths (dt |H|_inf = 1/2, tol 1e-10, host
+ * clock), and installs the fastest choices in the handle.  Results never
+ * depend on the plan (only how the work is split into kernels).  hub_tune
+ * allocates its test vectors; hub_set_tuning installs a table from an
+ * earlier hub_tune (e.g. cached per sector shape and device), or the
+ * built-in rules again with t = NULL.  hub_apply_path 0 still forces the
+ * one-pass kernels. */
+typedef struct {
+  int32_t single_two_pass;    /* single vectors: 1 = two-pass kernels, 0 = one pass       */
+  int32_t block_two_pass[4];  /* [1], [2], [3]: groups of 2, 4, 8 on the two-pass block
+                                 kernels (1) or the one-pass kernel (0); [0] unused         */
+  int32_t apply_group;        /* vectors per group of hub_apply_H (1, 2, 4, 8)             */
+  int32_t prop_group;         /* vectors per group of hub_propagate (1, 2, 4, 8)           */
+  double apply_us[4][2];      /* measured H*v time per vector (us), groups of 1, 2, 4, 8 x
+                                 (one pass, two passes); 0 = infeasible                     */
+  double step_us[4];          /* measured midpoint step time per vector (us) per group size;
+                                 0 = infeasible                                             */
+} hub_tuning;
+
+hub_status hub_tune(hub_basis basis, hub_prec prec, int32_t reps, hub_tuning *out, void *stream);
+hub_status hub_set_tuning(hub_basis basis, hub_prec prec, const hub_tuning *t);
+
+/* The plan for nvec vectors (propagate = 1: hub_propagate, 0: hub_apply_H):
+ * n_groups, and per group (host arrays of >= nvec entries, either may be
+ * NULL) its size and kernels: 0 one pass, 1 two-pass single vector, 2
+ * two-pass block kernels. */
+hub_status hub_get_plan(hub_basis basis, hub_prec prec, int32_t nvec, int32_t propagate, int32_t *n_groups,
+                        int32_t *sizes, int32_t *kernels);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing of the matrix-free apply (for roofline reporting).  on = 0

@@ -52,7 +52,8 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_profile_read", "hub_apply_cop", "hub_dot", "hub_greens_diag",
            "hub_mlp_forward", "hub_mlp_workspace_bytes", "hub_mlp_train_step", "hub_controller_features",
            "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats",
-           "hub_set_apply_path", "hub_spectral", "hub_set_schedule")
+           "hub_set_apply_path", "hub_spectral", "hub_set_schedule", "hub_observables_noalloc",
+           "hub_tune", "hub_set_tuning", "hub_get_plan")
 
 # Controller MLP sizes (HUB_MLP_* in hub.h).
 MLP_IN, MLP_HID, MLP_OUT = 8, 64, 2
@@ -97,6 +98,12 @@ class hub_controller_stats(ctypes.Structure):
                 ("lanczos_launches", ctypes.c_int64), ("iterations", ctypes.c_int64)]
 
 
+class hub_tuning(ctypes.Structure):
+    _fields_ = [("single_two_pass", ctypes.c_int32), ("block_two_pass", ctypes.c_int32 * 4),
+                ("apply_group", ctypes.c_int32), ("prop_group", ctypes.c_int32),
+                ("apply_us", (ctypes.c_double * 2) * 4), ("step_us", ctypes.c_double * 4)]
+
+
 class hub_obs(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("norm", ctypes.c_double), ("energy_per_site", ctypes.c_double),
                 ("docc_per_site", ctypes.c_double)]
@@ -124,6 +131,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_basis_hops": ([vp, i32, P(i32), P(i32), P(i32), P(i32), P(i64)], i32),
         "hub_apply_H": ([vp, P(dbl), i32, i32, vp, vp, vp], i32),
         "hub_observables": ([vp, P(dbl), i32, i32, vp, P(hub_obs), P(dbl), vp], i32),
+        "hub_observables_noalloc": ([vp, P(dbl), i32, i32, vp, P(hub_obs), P(dbl), vp], i32),
         "hub_krylov_expm_step": ([vp, P(dbl), dbl, P(hub_krylov_opts), i32, i32, vp, P(hub_step_info), vp], i32),
         "hub_propagate": ([vp, P(hub_pulse), dbl, dbl, i32, P(hub_krylov_opts), i32, i32, vp, P(hub_obs),
                            P(hub_step_info), vp], i32),
@@ -146,6 +154,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_controller_read_stats": ([vp, P(hub_controller_stats)], i32),
         "hub_set_apply_path": ([vp, i32], i32),
         "hub_set_schedule": ([vp, i32, i32], i32),
+        "hub_tune": ([vp, i32, i32, P(hub_tuning), vp], i32),
+        "hub_set_tuning": ([vp, i32, P(hub_tuning)], i32),
+        "hub_get_plan": ([vp, i32, i32, i32, P(i32), P(i32), P(i32)], i32),
         "hub_spectral": ([i32, i32, i32, vp, P(i32), dbl, dbl, i32, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -282,15 +293,17 @@ def hub_apply_H(h, A: Sequence[float], x, y, stream=None) -> None:
                                       _stream_ptr(stream)))
 
 
-def hub_observables(h, A: Sequence[float], v, site=False, stream=None):
-    """(obs array [nvec, 4] = t, norm, energy/site, docc/site; site docc or None)."""
+def hub_observables(h, A: Sequence[float], v, site=False, stream=None, noalloc=False):
+    """(obs array [nvec, 4] = t, norm, energy/site, docc/site; site docc or None).
+    noalloc: call hub_observables_noalloc (no device allocation)."""
     A = list(np.atleast_1d(A))
     n = len(A)
     out = (hub_obs * n)()
     sd = np.zeros(n * _n_sites_cache.get(h, 16), dtype=np.float64) if site else None
-    _check(load_library().hub_observables(ctypes.c_void_p(h), _dbl_array(A), _prec_of(v), n, _dptr(v), out,
-                                          sd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if site else None,
-                                          _stream_ptr(stream)))
+    lib = load_library()
+    fn = lib.hub_observables_noalloc if noalloc else lib.hub_observables
+    _check(fn(ctypes.c_void_p(h), _dbl_array(A), _prec_of(v), n, _dptr(v), out,
+              sd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if site else None, _stream_ptr(stream)))
     arr = np.array([[o.t, o.norm, o.energy_per_site, o.docc_per_site] for o in out])
     if site:
         ns = _n_sites_cache.get(h, 16)
@@ -473,6 +486,48 @@ def hub_set_schedule(h, chunk: int, margin: int = 1) -> None:
     """Default propagation schedule: chunks of `chunk` steps without host
     synchronisation (0: one synchronisation per step)."""
     _check(load_library().hub_set_schedule(ctypes.c_void_p(h), int(chunk), int(margin)))
+
+
+def tuning_to_dict(t: hub_tuning) -> dict:
+    return {"single_two_pass": t.single_two_pass, "block_two_pass": list(t.block_two_pass),
+            "apply_group": t.apply_group, "prop_group": t.prop_group,
+            "apply_us": [list(r) for r in t.apply_us], "step_us": list(t.step_us)}
+
+
+def tuning_from_dict(d: dict) -> hub_tuning:
+    t = hub_tuning()
+    t.single_two_pass = int(d["single_two_pass"])
+    for k in range(4):
+        t.block_two_pass[k] = int(d["block_two_pass"][k])
+        t.step_us[k] = float(d.get("step_us", [0.0] * 4)[k])
+        for p in range(2):
+            t.apply_us[k][p] = float(d.get("apply_us", [[0.0, 0.0]] * 4)[k][p])
+    t.apply_group = int(d["apply_group"])
+    t.prop_group = int(d["prop_group"])
+    return t
+
+
+def hub_tune(h, prec: int, reps: int = 10, stream=None) -> dict:
+    """Measure and install the kernel plan of one precision; returns it as a dict."""
+    t = hub_tuning()
+    _check(load_library().hub_tune(ctypes.c_void_p(h), int(prec), int(reps), ctypes.byref(t), _stream_ptr(stream)))
+    return tuning_to_dict(t)
+
+
+def hub_set_tuning(h, prec: int, table) -> None:
+    """Install a plan (dict from hub_tune), or the built-in rules with None."""
+    t = tuning_from_dict(table) if table is not None else None
+    _check(load_library().hub_set_tuning(ctypes.c_void_p(h), int(prec), ctypes.byref(t) if t is not None else None))
+
+
+def hub_get_plan(h, prec: int, nvec: int, propagate: bool = True):
+    """[(group size, kernels)] with kernels 0 one pass, 1 two-pass single, 2 two-pass block."""
+    n = ctypes.c_int32()
+    sizes = (ctypes.c_int32 * max(1, nvec))()
+    kern = (ctypes.c_int32 * max(1, nvec))()
+    _check(load_library().hub_get_plan(ctypes.c_void_p(h), int(prec), int(nvec), 1 if propagate else 0,
+                                       ctypes.byref(n), sizes, kern))
+    return [(sizes[k], kern[k]) for k in range(n.value)]
 
 
 class Basis:

@@ -24,7 +24,8 @@ LIB = os.path.join(PKG, "libhub.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 HOST_SOURCES = ["basis.cpp", "host_eig.cpp"]
-HIP_SOURCES = ["apply_c128.hip", "apply_c64.hip", "kernels.hip", "mlp.hip", "api.hip"]
+HIP_SOURCES = ["apply_c128.hip", "apply_c64.hip", "block_c128.hip", "block_c64.hip", "kernels.hip", "mlp.hip",
+               "api.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
@@ -50,7 +51,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
         jobs.append([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-    with ThreadPoolExecutor(max_workers=min(6, len(jobs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:

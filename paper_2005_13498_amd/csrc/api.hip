@@ -5,7 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <functional>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <array>
 #include <cmath>
@@ -53,11 +56,18 @@ hub_status fail(hub_status s, const std::string& msg) {
 size_t elem_bytes(hub_prec p) { return p == HUB_C128 ? 16 : 8; }
 
 constexpr int kCtrlMaxChunk = 256;
+
+// Static device scratch of hub_observables_noalloc (one copy per device, held
+// until the process ends).  Host code never uses this name as an address: it
+// passes the pointer that hipGetSymbolAddress returned for the device.
+constexpr size_t kNoAllocScratchBytes = size_t(512) << 10;
 // Event pool of the apply timing: created when timing is enabled, and read
 // back (elapsed times) only when fewer than kProfLowWater events are left.
 constexpr size_t kProfPool = 8192, kProfLowWater = 512;
 
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 // One timed apply: start/stop events of its kernel(s) until they are read
 // (then returned to the pool), its kernel time, and whether it did work.
@@ -121,6 +131,12 @@ struct hub_basis_s {
   float* ctrl_hout = nullptr;
   hub_controller_stats cstats{};
   int sched_chunk = 32, sched_margin = 1;  // default chunked schedule (chunk 0: synchronous)
+  // tuned vectors per group per precision (-1: the built-in rule): hub_apply_H
+  // and hub_propagate with several vectors; force_group (> 0) overrides both
+  // while hub_tune measures
+  int apply_group[2] = {-1, -1};
+  int prop_group[2] = {-1, -1};
+  int force_group = 0;
   // profiling of the apply kernel
   bool prof = false;
   int prof_period = 1;
@@ -217,6 +233,9 @@ hub_status ensure_workspace(hub_basis h, Work& W, size_t slot_bytes, int nslots,
   const int cgmax = std::max(hub::colpass_grid(h->D, 0), hub::colpass_grid(h->D, 1));
   pb = std::max(pb, (2 * static_cast<size_t>(cgmax) +
                      static_cast<size_t>(h->D.dim_up) * (kObsQ + 1)) * sizeof(double));
+  // block two-pass: column-pass partials [dim_dn][2][nv], row-pass obs partials [dim_up][kObsQ][nv]
+  pb = std::max(pb, (2 * static_cast<size_t>(h->D.dim_dn) + static_cast<size_t>(h->D.dim_up) * kObsQ) * kMaxNV *
+                        sizeof(double));
   if (pb > W.partials_bytes) {
     if (W.partials) HUB_HIP(hipFree(W.partials));
     W.partials = nullptr;
@@ -341,7 +360,8 @@ hub_status launch_apply_timed(hub_basis h, const hub::ApplyLaunch& L, int* grid 
     HUB_HIP(hub::launch_apply(L, grid));
     return HUB_OK;
   }
-  const bool two = hub::apply_two_pass(h->D, L.prec, L.nv, L.mode, L.obs);
+  const bool two = hub::apply_two_pass(h->D, L.prec, L.nv, L.mode, L.obs) ||
+                   (L.nv > 1 && hub::block_two_pass(h->D, L.prec, L.nv));
   std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
   for (int k = 0; k < (two ? 4 : 2); ++k) {
     if (!h->ev_free.empty()) {
@@ -396,12 +416,36 @@ hub_status prof_harvest(hub_basis h, size_t from, size_t* end) {
 // Group sizes for nvec vectors: powers of two up to 8 whose staged row keeps
 // at least three apply workgroups per CU (<= 48 KB of the 160 KB LDS), or one
 // vector per group; single vectors where the two-pass kernels apply.
-std::vector<int> groups_for(hub_basis h, int nvec, int prec) {
+std::vector<int> groups_for(hub_basis h, int nvec, int prec, bool propagate = true) {
+  const int tuned = h->force_group > 0 ? h->force_group : (propagate ? h->prop_group[prec] : h->apply_group[prec]);
+  if (tuned > 0) {
+    std::vector<int> g;
+    for (int left = nvec; left > 0;) {
+      int s = tuned;
+      while (s > left) s /= 2;
+      g.push_back(s);
+      left -= s;
+    }
+    return g;
+  }
   int gmax = kMaxNV;
   while (gmax > 1 && hub::apply_lds_bytes(h->D, prec, gmax, 1) > 48 * 1024) gmax /= 2;
   // single vectors run the two-pass kernels with fused updates, which beat
   // interleaved one-pass blocks whenever they apply
   if (hub::apply_two_pass(h->D, prec, 1, hub::kLanczos, false)) gmax = 1;
+  // plain applies of blocks on the two-pass block kernels: the largest group
+  // whose staged row keeps two workgroups per CU (else one).  Propagations
+  // keep the rule above unless a tuned plan says otherwise: at 12 sites single
+  // vectors on the fused two-pass iterations, several groups on concurrent
+  // lanes, were measured faster than blocks.
+  if (nvec > 1 && !propagate) {
+    int gb = 0;
+    for (int g = kMaxNV; g >= 2 && !gb; g /= 2)
+      if (hub::block_two_pass(h->D, prec, g) && hub::block_lds_bytes(h->D, prec, g) <= 80 * 1024) gb = g;
+    for (int g = kMaxNV; g >= 2 && !gb; g /= 2)
+      if (hub::block_two_pass(h->D, prec, g)) gb = g;
+    if (gb) gmax = gb;
+  }
   std::vector<int> g;
   int left = nvec;
   while (left > 0) {
@@ -418,13 +462,26 @@ struct StepReport {
   double eps = 0.0, beta_last = 0.0;
 };
 
+// Work enqueued after every finished step of a propagation, on the group's
+// stream right after the step's combine (so it sees the new state, and like
+// every kernel of the step it must do nothing when ctl->abort is set: the
+// step is then re-run and the hook enqueued again).
+struct StepHook {
+  char* traj = nullptr;  // single vectors: the state after step n also goes to traj + (n + 1) * traj_stride
+  size_t traj_stride = 0;
+  // k0, nv: the group's first vector in the call and its size; n_done: steps
+  // finished; state: the group's vectors, interleaved [dim][nv] when nv > 1
+  std::function<hipError_t(int k0, int nv, int n_done, const void* state, const StepCtl* ctl, hipStream_t s)> after;
+};
+
 // Runs n_steps Krylov midpoint steps for one group of nv vectors stored in
 // the ABI layout at `user` (vector k at user + k*dim).  coef_mid[n][v][2*nc].
 hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps,
                      const std::vector<double>& coef_mid, double dt, const hub_krylov_opts& o,
                      bool want_obs, const std::vector<double>* coef_obs, std::vector<double>* obs_out,
                      std::vector<StepReport>* reports, hipStream_t stream, bool* not_converged,
-                     int* steps_done, const CtrlInputs* ctrl, Work& W) {
+                     int* steps_done, const CtrlInputs* ctrl, Work& W, const StepHook* hook = nullptr,
+                     int k0 = 0) {
   const size_t es = elem_bytes(prec);
   const int64_t dim = h->D.dim;
   const size_t vbytes = static_cast<size_t>(dim) * nv * es;
@@ -514,8 +571,10 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.j = jj;
     // a two-pass apply with observables leaves the row pass's partials after
     // the column pass's
-    const bool two_obs = A.obs && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
-    const size_t cg2 = 2 * static_cast<size_t>(hub::colpass_grid(h->D, pi));
+    const bool blk = nv > 1 && hub::block_two_pass(h->D, pi, nv);
+    const bool two_obs = A.obs && (blk || hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true));
+    const size_t cg2 = blk ? 2 * static_cast<size_t>(h->D.dim_dn) * nv
+                           : 2 * static_cast<size_t>(hub::colpass_grid(h->D, pi));
     if (two_obs) A.row_obs = W.partials + cg2;
     // From the second iteration on, the two-pass row pass also finishes the
     // previous update (u_j = w_{j-1} - alpha s u_{j-1}) and the column pass
@@ -549,10 +608,13 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   };
   // the combine also records the (sub)step: log, observables, cleared control block
   auto finish_sub = [&](int n, int sub) -> hub_status {
+    const bool last = sub == S - 1;
+    void* copy_to = (hook && hook->traj && nv == 1 && last) ? hook->traj + (n + 1) * hook->traj_stride : nullptr;
     HUB_HIP(hub::launch_combine(pi, nv, dim, W.slot_ptrs, W.st, W.ctl, W.partials_e, n * S + sub + 1,
                                 dlog_c + (static_cast<size_t>(n) * S + sub) * nv,
                                 (want_obs && sub == 0) ? dobs + static_cast<size_t>(n) * nv * kObsQ : nullptr,
-                                kObsQ, stream));
+                                kObsQ, stream, copy_to));
+    if (hook && hook->after && last) HUB_HIP(hook->after(k0, nv, n + 1, slot0, W.ctl, stream));
     return HUB_OK;
   };
 
@@ -562,6 +624,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   // round trip per extra iteration; kernels past the decision exit at once).
   int m_pred = o.m_hint > 0 ? std::min(o.m_hint, o.m_max) : std::min(8, o.m_max);
   bool first = true;  // the next step_begin computes |v| itself
+  int64_t sync_launches = 0;  // Lanczos launches of the synchronous steps (counted for the first step)
   *not_converged = false;
   *steps_done = 0;
   auto adaptive_step = [&](int n, int sub0, bool* maxed) -> hub_status {
@@ -576,6 +639,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       for (; j <= m_pred && j <= o.m_max; ++j) {
         hub_status r = enqueue_iter(n, sub, j);
         if (r != HUB_OK) return r;
+        ++sync_launches;
       }
       while (true) {
         HUB_HIP(hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, stream));
@@ -584,6 +648,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         if (j > o.m_max) return fail(HUB_E_DEVICE, "Krylov loop ended without a decision");
         hub_status r = enqueue_iter(n, sub, j);
         if (r != HUB_OK) return r;
+        ++sync_launches;
         ++j;
       }
       m_step_max = std::max(m_step_max, static_cast<int>(W.h_ctl->iter));
@@ -644,6 +709,33 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
       return HUB_OK;
     };
     int n = 0;
+    // Without a prediction to start from (default schedule, no m_hint) the
+    // first step runs synchronously and its Krylov dimension seeds the first
+    // chunk, instead of a fixed guess whose surplus launches every step of
+    // that chunk would pay.
+    if (!learned && o.m_hint == 0) {
+      bool mx = false;
+      sync_launches = 0;
+      hub_status r = adaptive_step(0, 0, &mx);
+      if (r != HUB_OK) return r;
+      r = fetch_logs(0, 1);
+      if (r != HUB_OK) return r;
+      HUB_HIP(hipStreamSynchronize(stream));
+      *steps_done = 1;
+      n = 1;
+      W.cstats.steps += 1;
+      W.cstats.lanczos_launches += sync_launches;
+      for (int v = 0; v < nv; ++v) {
+        double e;
+        int mm;
+        step_hist(0, v, &e, &mm);
+        W.cstats.iterations += mm;
+      }
+      if (mx) {
+        *not_converged = true;
+        n = n_steps;  // stop after this step, as the chunks would
+      }
+    }
     while (n < n_steps) {
       const int K = std::min(chunk, n_steps - n);
       // plan: features of every (step, vector) row, history up to step n-1
@@ -879,6 +971,96 @@ void fill_obs(const hub::Basis& B, const double* o /* kObsQ */, double t, hub_ob
   out->docc_per_site = o[1] / B.lat.n_sites;
 }
 
+// Observables of nvec vectors with the given device buffers: st (one
+// VecState), partials (apply_grid rows of kObsQ doubles), site_out (n_sites
+// doubles) and site_partials (elem_grid rows of n_sites doubles).  Every
+// buffer is fully written before it is read, so none needs clearing.  No
+// allocation on either side.
+hub_status observables_into(hub_basis h, const double* A, hub_prec prec, int32_t nvec, const void* v, hub_obs* out,
+                            double* site_docc, hipStream_t st, VecState* vst, double* partials, double* site_out,
+                            double* site_partials) {
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const size_t es = elem_bytes(prec);
+  const int64_t dim = h->D.dim;
+  const int nc = h->D.nc;
+  for (int k = 0; k < nvec; ++k) {
+    double cf[2 * kMaxNV * kMaxClasses] = {};
+    coef_for(h->B, A[k], cf);
+    hub::ApplyLaunch L{};
+    L.db = &h->D;
+    L.prec = pi;
+    L.nv = 1;
+    L.rows = pi == 0 ? h->rows_c128 : h->rows_c64;
+    L.mode = hub::kObsOnly;
+    L.obs = true;
+    L.x = static_cast<const char*>(v) + static_cast<size_t>(k) * dim * es;
+    L.coef = cf;
+    L.coef_obs = cf;
+    L.st = vst;
+    L.ctl = nullptr;  // observables-only applies take no Krylov decision
+    L.partials = partials;
+    L.stream = st;
+    int grid = 0;
+    HUB_HIP(hub::launch_apply(L, &grid));
+    HUB_HIP(hub::launch_finalize_obs(1, partials, grid, hub::apply_nq(hub::kObsOnly, true, nc), vst, st));
+    double o[kObsQ];
+    HUB_HIP(hipMemcpyAsync(o, reinterpret_cast<char*>(vst) + offsetof(VecState, obs), sizeof(o),
+                           hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    fill_obs(h->B, o, 0.0, &out[k]);
+    out[k].t = 0.0;
+    if (site_docc) {
+      HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, site_out, site_partials, st));
+      HUB_HIP(hipMemcpyAsync(site_docc + static_cast<size_t>(k) * h->D.n_sites, site_out,
+                             h->D.n_sites * sizeof(double), hipMemcpyDeviceToHost, st));
+      HUB_HIP(hipStreamSynchronize(st));
+    }
+  }
+  return HUB_OK;
+}
+
+// Byte offsets of the no-allocation variant's buffers in the static scratch
+// array (each 256-byte aligned).
+struct NoAllocLayout {
+  size_t st, site, partials, site_partials, total;
+};
+
+NoAllocLayout noalloc_layout(const DevBasis& D) {
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  NoAllocLayout L{};
+  L.st = 0;
+  L.site = up(sizeof(VecState));
+  L.partials = L.site + up(hub::kMaxSites * sizeof(double));
+  const size_t rows = static_cast<size_t>(std::max(hub::apply_grid(D, 0, 1), hub::apply_grid(D, 1, 1)));
+  L.site_partials = L.partials + up(rows * kObsQ * sizeof(double));
+  L.total = L.site_partials + up(static_cast<size_t>(hub::elem_grid(D.dim)) * hub::kMaxSites * sizeof(double));
+  return L;
+}
+
+// Device address of each device's copy of `scratch`, looked up once per
+// device when the first handle is created on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hub_status scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(HUB_E_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return HUB_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+  if (e != hipSuccess || !p)
+    return fail(HUB_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = p;
+  return HUB_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -965,8 +1147,17 @@ hub_status hub_basis_create(const hub_lattice* lat, int32_t n_up, int32_t n_dn, 
   D.up_nslots = B.up.nslots;
   D.up_maxs_pad = B.up.maxs_pad;
   for (int k = 0; k < 64; ++k) D.up_slot_class[k] = B.up.slot_class[k];
+  if ((s = upload(h, &D.dn_tabg, B.dn.tabg)) != HUB_OK) return cleanup(s);
+  if ((s = upload(h, &D.up_tabg, B.up.tabg)) != HUB_OK) return cleanup(s);
+  D.dn_gslots = B.dn.gslots;
+  D.up_gslots = B.up.gslots;
+  for (int k = 0; k < 8; ++k) {
+    D.dn_gclass[k] = B.dn.grp_class[k];
+    D.up_gclass[k] = B.up.grp_class[k];
+  }
 
   if ((s = work_init(h->w, false)) != HUB_OK) return cleanup(s);
+  if ((s = scratch_init(device)) != HUB_OK) return cleanup(s);
   h->rows_c128 = pick_rows(h, 0);
   h->rows_c64 = pick_rows(h, 1);
   *out = h;
@@ -1061,7 +1252,7 @@ hub_status hub_apply_H(hub_basis h, const double* A, hub_prec prec, int32_t nvec
   const size_t es = elem_bytes(prec);
   const int64_t dim = h->D.dim;
   const int nc = h->D.nc;
-  const std::vector<int> groups = groups_for(h, nvec, pi);
+  const std::vector<int> groups = groups_for(h, nvec, pi, false);
   int gmax = 1;
   for (int g : groups) gmax = std::max(gmax, g);
   s = ensure_workspace(h, static_cast<size_t>(dim) * gmax * es, 1, gmax > 1 ? static_cast<size_t>(dim) * gmax * es : 0);
@@ -1103,47 +1294,28 @@ hub_status hub_observables(hub_basis h, const double* A, hub_prec prec, int32_t 
   hub_status s = check_common(h, prec, nvec);
   if (s != HUB_OK) return s;
   if (!A || !v || !out) return fail(HUB_E_INVALID, "null argument");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int pi = prec == HUB_C128 ? 0 : 1;
-  const size_t es = elem_bytes(prec);
-  const int64_t dim = h->D.dim;
-  const int nc = h->D.nc;
   s = ensure_workspace(h, 16, 1, 0);
   if (s != HUB_OK) return s;
-  for (int k = 0; k < nvec; ++k) {
-    std::vector<double> cf(static_cast<size_t>(2) * kMaxNV * kMaxClasses, 0.0);
-    coef_for(h->B, A[k], cf.data());
-    hub::ApplyLaunch L{};
-    L.db = &h->D;
-    L.prec = pi;
-    L.nv = 1;
-    L.rows = pi == 0 ? h->rows_c128 : h->rows_c64;
-    L.mode = hub::kObsOnly;
-    L.obs = true;
-    L.x = static_cast<const char*>(v) + static_cast<size_t>(k) * dim * es;
-    L.coef = cf.data();
-    L.coef_obs = cf.data();
-    L.st = h->w.st;
-    L.ctl = h->w.ctl;
-    L.partials = h->w.partials;
-    L.stream = st;
-    int grid = 0;
-    HUB_HIP(hub::launch_apply(L, &grid));
-    HUB_HIP(hub::launch_finalize_obs(1, h->w.partials, grid, hub::apply_nq(hub::kObsOnly, true, nc), h->w.st, st));
-    double o[kObsQ];
-    HUB_HIP(hipMemcpyAsync(o, reinterpret_cast<char*>(h->w.st) + offsetof(VecState, obs), sizeof(o),
-                           hipMemcpyDeviceToHost, st));
-    HUB_HIP(hipStreamSynchronize(st));
-    fill_obs(h->B, o, 0.0, &out[k]);
-    out[k].t = 0.0;
-    if (site_docc) {
-      HUB_HIP(hub::launch_site_docc(pi, h->D, L.x, h->w.scal, h->w.partials_e, st));
-      HUB_HIP(hipMemcpyAsync(site_docc + static_cast<size_t>(k) * h->D.n_sites, h->w.scal,
-                             h->D.n_sites * sizeof(double), hipMemcpyDeviceToHost, st));
-      HUB_HIP(hipStreamSynchronize(st));
-    }
-  }
-  return HUB_OK;
+  return observables_into(h, A, prec, nvec, v, out, site_docc, static_cast<hipStream_t>(stream), h->w.st,
+                          h->w.partials, h->w.scal, h->w.partials_e);
+}
+
+hub_status hub_observables_noalloc(hub_basis h, const double* A, hub_prec prec, int32_t nvec, const void* v,
+                                   hub_obs* out, double* site_docc, void* stream) {
+  hub_status s = check_common(h, prec, nvec);
+  if (s != HUB_OK) return s;
+  if (!A || !v || !out) return fail(HUB_E_INVALID, "null argument");
+  char* base = static_cast<char*>(scratch_of(h->device));
+  if (!base) return fail(HUB_E_DEVICE, "static scratch of this device not initialised");
+  const NoAllocLayout Lo = noalloc_layout(h->D);
+  if (Lo.total > kNoAllocScratchBytes)
+    return fail(HUB_E_INVALID, "hub_observables_noalloc: the sector needs " + std::to_string(Lo.total) +
+                                   " bytes of scratch, the static buffer holds " +
+                                   std::to_string(kNoAllocScratchBytes));
+  return observables_into(h, A, prec, nvec, v, out, site_docc, static_cast<hipStream_t>(stream),
+                          reinterpret_cast<VecState*>(base + Lo.st), reinterpret_cast<double*>(base + Lo.partials),
+                          reinterpret_cast<double*>(base + Lo.site),
+                          reinterpret_cast<double*>(base + Lo.site_partials));
 }
 
 static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inout, int n_steps,
@@ -1152,7 +1324,8 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
                           double t_start, double dt, const hub_krylov_opts& o, hub_obs* obs,
                           hub_step_info* log, void* stream,
                           const std::vector<std::vector<double>>* dA_mid = nullptr /* [nvec][n_steps] */,
-                          const std::vector<std::vector<double>>* A_gauss = nullptr /* [nvec][2 n_steps] */) {
+                          const std::vector<std::vector<double>>* A_gauss = nullptr /* [nvec][2 n_steps] */,
+                          const StepHook* hook = nullptr) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int pi = prec == HUB_C128 ? 0 : 1;
   const size_t es = elem_bytes(prec);
@@ -1217,7 +1390,7 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
   auto run_one = [&](GroupRun& R, Work& W, hipStream_t s_lane) {
     char* user = static_cast<char*>(v_inout) + static_cast<size_t>(R.k0) * dim * es;
     R.s = run_group(h, prec, R.nv, user, n_steps, R.cm, dt, o, want_obs, &R.co, &R.obs_raw, &R.reps, s_lane, &R.ncv,
-                    &R.done, dA_mid ? &R.ci : nullptr, W);
+                    &R.done, dA_mid ? &R.ci : nullptr, W, hook, R.k0);
     if (R.s != HUB_OK) R.err = g_err;
     R.ran = true;
   };
@@ -1513,135 +1686,183 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
   for (int k = 0; k < n_members; ++k) grp[tb[k]].push_back(k);
   for (auto& v : grp)
     std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return members[a].start_step < members[b].start_step; });
-  // device buffers: member vectors per group, one scratch vector, op maps, overlaps
-  std::vector<void*> gbuf(n_targets, nullptr);
-  std::vector<DevOpMap> ops(n_members);
-  void* tmp = nullptr;
-  double* dover = nullptr;
-  std::vector<hipStream_t> jstreams;  // one per concurrent propagation of a step
-  hipEvent_t jready = nullptr;
+  const int n_total = max_start + n_rel;
+  const int64_t dim_s = h->D.dim;
+  // Device buffers: psi at every step (the trajectory), the members of every
+  // target sector in the ABI layout (ordered by start step), their operator
+  // maps packed per sector [member][map_len], overlap partials per sector
+  // [n_rel + 1][members][grid][2] and their totals [n_rel + 1][members][2].
+  struct Sector {
+    hub_basis T = nullptr;
+    std::vector<int> mem;
+    void* buf = nullptr;
+    int32_t* maps = nullptr;
+    int8_t* sgns = nullptr;
+    int map_len = 0, ogrid = 0;
+    bool down = false;
+    double* part = nullptr;
+    double* tot = nullptr;
+    hipStream_t stream = nullptr;
+    hub_status s = HUB_OK;
+    std::string err;
+  };
+  std::vector<Sector> secs;
+  void* traj = nullptr;
   auto cleanup = [&](hub_status r) {
-    for (void* p : gbuf)
-      if (p) (void)hipFree(p);
-    for (auto& o : ops) o.release();
-    if (tmp) (void)hipFree(tmp);
-    if (dover) (void)hipFree(dover);
-    for (hipStream_t x : jstreams) (void)hipStreamDestroy(x);
-    if (jready) (void)hipEventDestroy(jready);
+    for (Sector& S : secs) {
+      if (S.buf) (void)hipFree(S.buf);
+      if (S.maps) (void)hipFree(S.maps);
+      if (S.sgns) (void)hipFree(S.sgns);
+      if (S.part) (void)hipFree(S.part);
+      if (S.tot) (void)hipFree(S.tot);
+      if (S.stream) (void)hipStreamDestroy(S.stream);
+    }
+    if (traj) (void)hipFree(traj);
     return r;
   };
-  if (hipEventCreateWithFlags(&jready, hipEventDisableTiming) != hipSuccess)
-    return cleanup(fail(HUB_E_DEVICE, "event creation failed"));
-  int64_t maxdim = 0;
   for (int g = 0; g < n_targets; ++g) {
     if (grp[g].empty()) continue;
-    maxdim = std::max(maxdim, targets[g]->D.dim);
-    if (hipMalloc(&gbuf[g], grp[g].size() * targets[g]->D.dim * es) != hipSuccess)
+    Sector S;
+    S.T = targets[g];
+    S.mem = grp[g];
+    secs.push_back(S);
+  }
+  const size_t sbytes = static_cast<size_t>(dim_s) * es;
+  if (hipMalloc(&traj, static_cast<size_t>(n_total + 1) * sbytes) != hipSuccess)
+    return cleanup(fail(HUB_E_NOMEM, "trajectory buffer"));
+  for (Sector& S : secs) {
+    const int nm = static_cast<int>(S.mem.size());
+    const int64_t dt_ = S.T->D.dim;
+    S.ogrid = hub::overlap_grid(dt_);
+    std::vector<int32_t> maps;
+    std::vector<int8_t> sg;
+    for (int q = 0; q < nm; ++q) {
+      const hub_greens_member& m = members[S.mem[q]];
+      OpMap M;
+      if ((s = build_op_map(h, S.T, m.site, m.spin, m.dagger, M)) != HUB_OK) return cleanup(s);
+      if (q == 0) {
+        S.map_len = static_cast<int>(M.map.size());
+        S.down = M.down;
+      } else if (static_cast<int>(M.map.size()) != S.map_len || M.down != S.down) {
+        return cleanup(fail(HUB_E_INVALID, "members of one sector need operators of one spin"));
+      }
+      maps.insert(maps.end(), M.map.begin(), M.map.end());
+      sg.insert(sg.end(), M.sgn.begin(), M.sgn.end());
+    }
+    if (hipMalloc(&S.buf, static_cast<size_t>(nm) * dt_ * es) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&S.maps), maps.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&S.sgns), sg.size()) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&S.part),
+                  static_cast<size_t>(n_rel + 1) * nm * S.ogrid * 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&S.tot), static_cast<size_t>(n_rel + 1) * nm * 2 * sizeof(double)) !=
+            hipSuccess)
       return cleanup(fail(HUB_E_NOMEM, "member buffers"));
+    HUB_HIP(hipMemcpy(S.maps, maps.data(), maps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HUB_HIP(hipMemcpy(S.sgns, sg.data(), sg.size(), hipMemcpyHostToDevice));
+    if (hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking) != hipSuccess)
+      return cleanup(fail(HUB_E_DEVICE, "stream creation failed"));
   }
-  if (hipMalloc(&tmp, maxdim * es) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&dover), static_cast<size_t>(n_members) * (n_rel + 1) * 2 * sizeof(double)) !=
-          hipSuccess)
-    return cleanup(fail(HUB_E_NOMEM, "scratch buffers"));
-  for (int k = 0; k < n_members; ++k) {
-    OpMap M;
-    if ((s = build_op_map(h, targets[tb[k]], members[k].site, members[k].spin, members[k].dagger, M)) != HUB_OK)
-      return cleanup(s);
-    if ((s = upload_op(h, M, ops[k])) != HUB_OK) return cleanup(s);
-  }
-  if ((s = ensure_workspace(h, 16, 1, 0)) != HUB_OK) return cleanup(s);
-  auto slot_of = [&](int k) -> char* {
-    const auto& v = grp[tb[k]];
-    const size_t pos = static_cast<size_t>(std::find(v.begin(), v.end(), k) - v.begin());
-    return static_cast<char*>(gbuf[tb[k]]) + pos * targets[tb[k]]->D.dim * es;
-  };
-  auto op_psi = [&](int k, void* dst) -> hipError_t {
-    hub_basis T = targets[tb[k]];
-    return hub::launch_cop(pi, T->D.dim, T->D.dim_dn, h->D.dim_dn, h->D.dim, 1, ops[k].down, ops[k].map,
-                           ops[k].sgn, psi_inout, dst, st);
-  };
-  const int n_total = max_start + n_rel;
   hub_krylov_opts o1 = *opts;
-  for (int n = 0; n <= n_total; ++n) {
-    for (int k = 0; k < n_members; ++k) {
-      const int sidx = n - members[k].start_step;
-      if (sidx == 0) {
-        if (op_psi(k, slot_of(k)) != hipSuccess) return cleanup(fail(HUB_E_DEVICE, "operator kernel"));
-      }
-      if (sidx >= 0 && sidx <= n_rel) {
-        hub_basis T = targets[tb[k]];
-        if (op_psi(k, tmp) != hipSuccess ||
-            hub::launch_dots(pi, T->D.dim, 1, tmp, slot_of(k),
-                             dover + (static_cast<size_t>(k) * (n_rel + 1) + sidx) * 2, T->w.partials_e ? T->w.partials_e
-                                                                                                : h->w.partials_e,
-                             st) != hipSuccess)
-          return cleanup(fail(HUB_E_DEVICE, "overlap kernels"));
-      }
+  // 1. psi over the whole grid, its state after every step kept in traj
+  HUB_HIP(hipMemcpyAsync(traj, psi_inout, sbytes, hipMemcpyDeviceToDevice, st));
+  if (n_total > 0) {
+    std::vector<std::vector<double>> am(1, std::vector<double>(n_total));
+    for (int n = 0; n < n_total; ++n) am[0][n] = pulse_value(*pulse, t_start + n * dt + 0.5 * dt);
+    StepHook hk;
+    hk.traj = static_cast<char*>(traj);
+    hk.traj_stride = sbytes;
+    if ((s = run_all(h, prec, 1, psi_inout, n_total, am, nullptr, t_start, dt, o1, nullptr, nullptr, st, nullptr,
+                     nullptr, &hk)) != HUB_OK)
+      return cleanup(s);
+  }
+  // 2. every member from c_k psi(t'_k); overlaps after s = 0..n_rel steps,
+  // gathered from the trajectory, partials at [s][member][grid][2]
+  auto overlap_launch = [&](Sector& S, int k0, int nv, int n_done, const void* phi, bool interleaved,
+                            const StepCtl* ctl, hipStream_t s_) -> hipError_t {
+    const int nm = static_cast<int>(S.mem.size());
+    hub::OverlapArgs a{};
+    a.n_t = S.T->D.dim;
+    a.dim_dn_t = S.T->D.dim_dn;
+    a.dim_dn_s = h->D.dim_dn;
+    a.down = S.down ? 1 : 0;
+    a.map_len = S.map_len;
+    a.interleaved = interleaved ? 1 : 0;
+    for (int v = 0; v < nv; ++v) a.psi_off[v] = (members[S.mem[k0 + v]].start_step + n_done) * dim_s;
+    a.maps = S.maps + static_cast<size_t>(k0) * S.map_len;
+    a.sgns = S.sgns + static_cast<size_t>(k0) * S.map_len;
+    a.traj = traj;
+    a.phi = phi;
+    a.ctl = ctl;
+    a.partials = S.part + (static_cast<size_t>(n_done) * nm + k0) * S.ogrid * 2;
+    return hub::launch_overlaps(pi, nv, a, s_);
+  };
+  for (Sector& S : secs) {
+    const int nm = static_cast<int>(S.mem.size());
+    hub_basis T = S.T;
+    for (int q = 0; q < nm; ++q) {
+      const int k = S.mem[q];
+      const char* src = static_cast<const char*>(traj) + static_cast<size_t>(members[k].start_step) * sbytes;
+      void* dst = static_cast<char*>(S.buf) + static_cast<size_t>(q) * T->D.dim * es;
+      HUB_HIP(hub::launch_cop(pi, T->D.dim, T->D.dim_dn, h->D.dim_dn, h->D.dim, 1, S.down, S.maps + (size_t)q * S.map_len,
+                              S.sgns + static_cast<size_t>(q) * S.map_len, src, dst, st));
     }
-    if (n == n_total) break;
-    const double amid = pulse_value(*pulse, t_start + n * dt + 0.5 * dt);
-    // psi and the active members of every target sector (contiguous, batched)
-    // one step each: independent propagations, run side by side on their own
-    // streams and host threads after the overlap kernels above
-    struct Job {
-      hub_basis H;
-      int nvec;
-      void* base;
-      hub_status s = HUB_OK;
-      std::string err;
-    };
-    std::vector<Job> jobs;
-    jobs.push_back(Job{h, 1, psi_inout});
-    for (int g = 0; g < n_targets; ++g) {
-      const auto& v = grp[g];
-      int lo = -1, hi = -1;
-      for (size_t q = 0; q < v.size(); ++q) {
-        const int sidx = n - members[v[q]].start_step;
-        if (sidx >= 0 && sidx < n_rel) {
-          if (lo < 0) lo = static_cast<int>(q);
-          hi = static_cast<int>(q) + 1;
-        }
-      }
-      if (lo < 0) continue;
-      hub_basis T = targets[g];
-      if ((s = ensure_workspace(T, 16, 1, 0)) != HUB_OK) return cleanup(s);
-      jobs.push_back(Job{T, hi - lo, static_cast<char*>(gbuf[g]) + static_cast<size_t>(lo) * T->D.dim * es});
+    for (int q = 0; q < nm;) {  // the kernel takes 1, 2, 4 or 8 consecutive members
+      int w = kMaxNV;
+      while (w > nm - q) w /= 2;
+      HUB_HIP(overlap_launch(S, q, w, 0, static_cast<char*>(S.buf) + static_cast<size_t>(q) * T->D.dim * es, false,
+                             nullptr, st));
+      q += w;
     }
-    while (jstreams.size() < jobs.size()) {
-      hipStream_t x = nullptr;
-      if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
-        return cleanup(fail(HUB_E_DEVICE, "stream creation failed"));
-      jstreams.push_back(x);
-    }
-    if (hipEventRecord(jready, st) != hipSuccess) return cleanup(fail(HUB_E_DEVICE, "event record failed"));
-    for (size_t q = 0; q < jobs.size(); ++q)
-      if (hipStreamWaitEvent(jstreams[q], jready, 0) != hipSuccess)
-        return cleanup(fail(HUB_E_DEVICE, "stream wait failed"));
+  }
+  HUB_HIP(hipStreamSynchronize(st));
+  // 3. the sectors side by side (own stream and host thread each; groups of
+  // a sector run on its handle's lanes)
+  if (n_rel > 0) {
     std::vector<std::thread> threads;
-    for (size_t q = 0; q < jobs.size(); ++q)
-      threads.emplace_back([&, q]() {
-        Job& J = jobs[q];
+    for (Sector& S : secs)
+      threads.emplace_back([&, pS = &S]() {
+        Sector& S = *pS;
         if (hipSetDevice(h->device) != hipSuccess) {
-          J.s = HUB_E_DEVICE;
-          J.err = "hipSetDevice failed";
+          S.s = HUB_E_DEVICE;
+          S.err = "hipSetDevice failed";
           return;
         }
         try {
-          std::vector<std::vector<double>> am(J.nvec, std::vector<double>(1, amid));
-          J.s = run_all(J.H, prec, J.nvec, J.base, 1, am, nullptr, 0.0, dt, o1, nullptr, nullptr, jstreams[q]);
+          const int nm = static_cast<int>(S.mem.size());
+          std::vector<std::vector<double>> am(nm, std::vector<double>(n_rel));
+          for (int q = 0; q < nm; ++q)
+            for (int n = 0; n < n_rel; ++n)
+              am[q][n] = pulse_value(*pulse, t_start + (members[S.mem[q]].start_step + n) * dt + 0.5 * dt);
+          StepHook hk;
+          hk.after = [&](int k0, int nv, int n_done, const void* state, const StepCtl* ctl, hipStream_t s_) {
+            return overlap_launch(S, k0, nv, n_done, state, nv > 1, ctl, s_);
+          };
+          S.s = run_all(S.T, prec, nm, S.buf, n_rel, am, nullptr, t_start, dt, o1, nullptr, nullptr, S.stream,
+                        nullptr, nullptr, &hk);
         } catch (const std::bad_alloc&) {
-          J.s = fail(HUB_E_NOMEM, "host allocation failed");
+          S.s = fail(HUB_E_NOMEM, "host allocation failed");
         }
-        if (J.s != HUB_OK) J.err = g_err;
+        if (S.s != HUB_OK) S.err = g_err;
       });
     for (auto& t : threads) t.join();
-    for (const Job& J : jobs)
-      if (J.s != HUB_OK) return cleanup(fail(J.s, J.err));
+    for (const Sector& S : secs)
+      if (S.s != HUB_OK) return cleanup(fail(S.s, S.err));
   }
-  if (hipMemcpyAsync(overlaps, dover, static_cast<size_t>(n_members) * (n_rel + 1) * 2 * sizeof(double),
-                     hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return cleanup(fail(HUB_E_DEVICE, "overlap copy"));
+  // 4. totals and the host copy
+  std::vector<double> host;
+  for (Sector& S : secs) {
+    const int nm = static_cast<int>(S.mem.size());
+    HUB_HIP(hub::launch_reduce_sets(S.part, static_cast<int64_t>(S.ogrid) * 2, (n_rel + 1) * nm, S.ogrid, 2, S.tot, 2,
+                                    S.stream));
+    host.assign(static_cast<size_t>(n_rel + 1) * nm * 2, 0.0);
+    HUB_HIP(hipMemcpyAsync(host.data(), S.tot, host.size() * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+    HUB_HIP(hipStreamSynchronize(S.stream));
+    for (int q = 0; q < nm; ++q)
+      for (int n = 0; n <= n_rel; ++n)
+        for (int c = 0; c < 2; ++c)
+          overlaps[(static_cast<size_t>(S.mem[q]) * (n_rel + 1) + n) * 2 + c] =
+              host[(static_cast<size_t>(n) * nm + q) * 2 + c];
+  }
   return cleanup(HUB_OK);
 }
 
@@ -1967,6 +2188,180 @@ hub_status hub_spectral(int32_t device, int32_t n_members, int32_t n_s, const do
   return HUB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Kernel plan tuning.
+namespace {
+
+int gidx(int g) { return g == 1 ? 0 : (g == 2 ? 1 : (g == 4 ? 2 : 3)); }
+
+// Can group size g run on path (0 one pass, 1 two pass) for precision pi?
+bool path_feasible(const DevBasis& D, int pi, int g, int path) {
+  DevBasis T = D;
+  T.two_pass = path;
+  T.block_path = path ? -1 : 0;
+  T.tuned_single[pi] = -1;
+  for (int k = 0; k < 4; ++k) T.tuned_block[pi][k] = -1;
+  if (g == 1) return path ? hub::apply_two_pass(T, pi, 1, hub::kPlain, false) : true;
+  if (path) return hub::block_two_pass(T, pi, g);
+  return hub::apply_lds_bytes(T, pi, g, 1) <= 150 * 1024;
+}
+
+}  // namespace
+
+hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, void* stream) {
+  hub_status s = check_common(h, prec, 1);
+  if (s != HUB_OK) return s;
+  if (!out) return fail(HUB_E_INVALID, "null output");
+  if (reps < 1) return fail(HUB_E_INVALID, "reps must be >= 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const size_t es = elem_bytes(prec);
+  const int64_t dim = h->D.dim;
+  constexpr int kN = kMaxNV;  // vectors per measured call
+  void* x = nullptr;
+  void* y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const DevBasis saved = h->D;
+  const int saved_ag = h->apply_group[pi], saved_pg = h->prop_group[pi];
+  auto done = [&](hub_status r) {
+    h->D = saved;
+    h->force_group = 0;
+    if (r != HUB_OK) {
+      h->apply_group[pi] = saved_ag;
+      h->prop_group[pi] = saved_pg;
+    }
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return r;
+  };
+  if (hipMalloc(&x, static_cast<size_t>(dim) * kN * es) != hipSuccess ||
+      hipMalloc(&y, static_cast<size_t>(dim) * kN * es) != hipSuccess)
+    return done(fail(HUB_E_NOMEM, "tuning buffers"));
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return done(fail(HUB_E_DEVICE, "event creation failed"));
+  if (hub::launch_fill_probe(pi, dim * kN, x, st) != hipSuccess) return done(fail(HUB_E_DEVICE, "fill kernel"));
+  hub_tuning T{};
+  const double A[kN] = {0.5, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
+  // 1. plain H*v of kN vectors in groups of g on either path
+  for (int g : {1, 2, 4, 8})
+    for (int path = 0; path < 2; ++path) {
+      if (!path_feasible(saved, pi, g, path)) continue;
+      h->D = saved;
+      h->D.two_pass = path;
+      h->D.block_path = path ? -1 : 0;
+      h->force_group = g;
+      for (int r = 0; r < 2; ++r)
+        if ((s = hub_apply_H(h, A, prec, kN, x, y, stream)) != HUB_OK) return done(s);
+      HUB_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < reps; ++r)
+        if ((s = hub_apply_H(h, A, prec, kN, x, y, stream)) != HUB_OK) return done(s);
+      HUB_HIP(hipEventRecord(e1, st));
+      HUB_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
+      T.apply_us[gidx(g)][path] = 1e3 * ms / (static_cast<double>(reps) * kN);
+    }
+  auto best_path = [&](int g) {
+    const double* u = T.apply_us[gidx(g)];
+    if (u[0] > 0.0 && u[1] > 0.0) return u[1] < u[0] ? 1 : 0;
+    return u[1] > 0.0 ? 1 : 0;
+  };
+  T.single_two_pass = best_path(1);
+  for (int g : {2, 4, 8}) T.block_two_pass[gidx(g)] = best_path(g);
+  // install the path choices
+  h->D = saved;
+  h->D.tuned_single[pi] = T.single_two_pass;
+  for (int g : {2, 4, 8}) h->D.tuned_block[pi][gidx(g)] = T.block_two_pass[gidx(g)];
+  const DevBasis chosen = h->D;
+  double best = 0.0;
+  for (int g : {1, 2, 4, 8}) {
+    const int path = g == 1 ? T.single_two_pass : T.block_two_pass[gidx(g)];
+    const double u = T.apply_us[gidx(g)][path];
+    if (u > 0.0 && (best == 0.0 || u < best)) {
+      best = u;
+      T.apply_group = g;
+    }
+  }
+  // 2. midpoint steps of kN vectors in groups of g (the chosen paths), dt
+  // such that dt |H|_inf = 1/2, tol 1e-10: time per vector-step
+  hub_krylov_opts o{};
+  o.tol = 1e-10;
+  o.m_max = 30;
+  o.substeps = 1;
+  const double dtp = 0.5 / std::max(h->B.norm_inf, 1e-300);
+  std::vector<std::vector<double>> am(kN, std::vector<double>(3, 0.5));
+  best = 0.0;
+  for (int g : {1, 2, 4, 8}) {
+    if (g > 1 && !hub::block_two_pass(chosen, pi, g) && hub::apply_lds_bytes(chosen, pi, g, 1) > 150 * 1024) continue;
+    h->D = chosen;
+    h->force_group = g;
+    if (hub::launch_fill_probe(pi, dim * kN, x, st) != hipSuccess) return done(fail(HUB_E_DEVICE, "fill kernel"));
+    if ((s = run_all(h, prec, kN, x, 1, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream)) != HUB_OK) return done(s);
+    HUB_HIP(hipStreamSynchronize(st));
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((s = run_all(h, prec, kN, x, 2, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream)) != HUB_OK) return done(s);
+    HUB_HIP(hipStreamSynchronize(st));
+    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    T.step_us[gidx(g)] = us / (2.0 * kN);
+    if (best == 0.0 || T.step_us[gidx(g)] < best) {
+      best = T.step_us[gidx(g)];
+      T.prop_group = g;
+    }
+  }
+  h->D = chosen;
+  h->force_group = 0;
+  h->apply_group[pi] = T.apply_group;
+  h->prop_group[pi] = T.prop_group;
+  *out = T;
+  if (x) (void)hipFree(x);
+  if (y) (void)hipFree(y);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return HUB_OK;
+}
+
+hub_status hub_set_tuning(hub_basis h, hub_prec prec, const hub_tuning* t) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (prec != HUB_C128 && prec != HUB_C64) return fail(HUB_E_INVALID, "unknown precision");
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  if (!t) {  // back to the built-in rules
+    h->D.tuned_single[pi] = -1;
+    for (int k = 0; k < 4; ++k) h->D.tuned_block[pi][k] = -1;
+    h->apply_group[pi] = h->prop_group[pi] = -1;
+    return HUB_OK;
+  }
+  auto pow2 = [](int g) { return g == 1 || g == 2 || g == 4 || g == 8; };
+  if (!pow2(t->apply_group) || !pow2(t->prop_group) || (t->single_two_pass != 0 && t->single_two_pass != 1))
+    return fail(HUB_E_INVALID, "tuning: groups must be 1, 2, 4 or 8 and paths 0 or 1");
+  for (int k = 1; k < 4; ++k)
+    if (t->block_two_pass[k] != 0 && t->block_two_pass[k] != 1) return fail(HUB_E_INVALID, "tuning: block path");
+  h->D.tuned_single[pi] = t->single_two_pass;
+  for (int k = 1; k < 4; ++k) h->D.tuned_block[pi][k] = t->block_two_pass[k];
+  h->apply_group[pi] = t->apply_group;
+  h->prop_group[pi] = t->prop_group;
+  return HUB_OK;
+}
+
+hub_status hub_get_plan(hub_basis h, hub_prec prec, int32_t nvec, int32_t propagate, int32_t* n_groups,
+                        int32_t* sizes, int32_t* kernels) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (prec != HUB_C128 && prec != HUB_C64) return fail(HUB_E_INVALID, "unknown precision");
+  if (nvec < 1 || !n_groups) return fail(HUB_E_INVALID, "nvec must be >= 1 and n_groups non-null");
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const std::vector<int> g = groups_for(h, nvec, pi, propagate != 0);
+  *n_groups = static_cast<int32_t>(g.size());
+  for (size_t k = 0; k < g.size(); ++k) {
+    if (sizes) sizes[k] = g[k];
+    if (kernels) {
+      if (g[k] > 1) kernels[k] = hub::block_two_pass(h->D, pi, g[k]) ? 2 : 0;
+      else kernels[k] = hub::apply_two_pass(h->D, pi, 1, propagate ? hub::kLanczos : hub::kPlain, false) ? 1 : 0;
+    }
+  }
+  return HUB_OK;
+}
+
 hub_status hub_set_schedule(hub_basis h, int32_t chunk, int32_t margin) {
   if (!h) return fail(HUB_E_INVALID, "null basis handle");
   if (chunk < 0 || chunk > kCtrlMaxChunk) return fail(HUB_E_INVALID, "chunk must be in [0, 256]");
@@ -1980,6 +2375,7 @@ hub_status hub_set_apply_path(hub_basis h, int32_t path) {
   if (!h) return fail(HUB_E_INVALID, "null basis handle");
   if (path < -1 || path > 1) return fail(HUB_E_INVALID, "path must be -1, 0 or 1");
   h->D.two_pass = path;
+  h->D.block_path = path == 0 ? 0 : -1;
   return HUB_OK;
 }
 

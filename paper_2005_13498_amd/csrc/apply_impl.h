@@ -4,6 +4,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "coef_pack.h"
 #include "kernels_common.h"
 
 namespace hub {
@@ -387,31 +388,6 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   block_partials_seq<NV, kWavesA>(vals, nq, red, p.partials + (size_t)lb * nq * NV);
 }
 
-// Launch with optional timing events attached to the dispatch.
-template <typename K, typename A>
-hipError_t launch_ev(K fn, int grid, int blk, size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A& args) {
-  if (!e0 && !e1) {
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(blk), lds, st, args);
-    return hipGetLastError();
-  }
-  void* kargs[] = {&args};
-  return hipExtLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(blk), kargs, lds, st, e0, e1, 0);
-}
-
-// Opts kernel fn into the largest dynamic LDS a CU allows (160 KB minus its
-// static LDS); returns the dynamic LDS bytes a launch may then request.
-inline int dyn_lds_opt_in(const void* fn) {
-  hipFuncAttributes fa{};
-  size_t stat = 0;
-  if (hipFuncGetAttributes(&fa, fn) == hipSuccess) stat = fa.sharedSizeBytes;
-  const int want = 160 * 1024 - static_cast<int>(stat);
-  const int got = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess
-                      ? want
-                      : 64 * 1024 - static_cast<int>(stat);
-  (void)hipGetLastError();  // a refused opt-in is not a launch error
-  return got;
-}
-
 template <typename R, int NV, int MODE, int MAXS, int BLK, bool UPH, bool FUSE, bool GDN = false>
 hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   const DevBasis& db = *L.db;
@@ -423,6 +399,9 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.nslots = db.nslots;
   p.m_max = L.m_max;
   p.chunks = apply_chunks(db, L.prec, L.nv);
+  // The fused row pass forms u_j in place over the whole row and writes one
+  // norm partial per row: every row must belong to exactly one workgroup.
+  if (FUSE && p.chunks != 1) return hipErrorInvalidValue;
   p.tol = L.tol;
   p.norm_inf = L.norm_inf;
   p.U = db.U;
@@ -435,30 +414,11 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   p.dn_tab = db.dn_tab;
   for (int s = 0; s < 64; ++s) p.slot_class[s] = db.slot_class[s];
   // the caller's coefficient arrays hold [nv][nc] complex pairs, no more
-  const int ncoef = 2 * L.nv * db.nc;
-  if (NV > 1) {
-    for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef[k] = (L.coef && k < ncoef) ? L.coef[k] : 0.0;
-  } else {
-    for (int sl = 0; sl < 64; ++sl) {
-      const int c = db.slot_class[sl];
-      const bool ok = sl < db.nslots && L.coef_obs;
-      p.slot_coef_obs[2 * sl] = ok ? L.coef_obs[2 * c] : 0.0;
-      p.slot_coef_obs[2 * sl + 1] = ok ? L.coef_obs[2 * c + 1] : 0.0;
-    }
-  }
-  for (int k = 0; k < 2 * kMaxNV * kMaxClasses; ++k) p.coef_obs[k] = (L.coef_obs && k < ncoef) ? L.coef_obs[k] : 0.0;
-  for (int s = 0; s < 64; ++s) {
-    const int c = db.slot_class[s];
-    p.slot_coef[2 * s] = (s < db.nslots && L.coef) ? L.coef[2 * c] : 0.0;
-    p.slot_coef[2 * s + 1] = (s < db.nslots && L.coef) ? L.coef[2 * c + 1] : 0.0;
-  }
-  for (int c = 0; c < kMaxClasses; ++c)
-    for (int sg = 0; sg < 2; ++sg) {
-      const double f = sg ? -1.0 : 1.0;
-      const bool ok = c < db.nc && L.coef;
-      p.up_coef[2 * (2 * c + sg)] = ok ? f * L.coef[2 * c] : 0.0;
-      p.up_coef[2 * (2 * c + sg) + 1] = ok ? f * L.coef[2 * c + 1] : 0.0;
-    }
+  if (NV > 1) pack_block_coefs(L.coef, L.nv, db.nc, p.coef, 2 * kMaxNV * kMaxClasses);
+  else pack_slot_coefs(L.coef_obs, db.nc, db.slot_class, db.nslots, p.slot_coef_obs);
+  pack_block_coefs(L.coef_obs, L.nv, db.nc, p.coef_obs, 2 * kMaxNV * kMaxClasses);
+  pack_slot_coefs(L.coef, db.nc, db.slot_class, db.nslots, p.slot_coef);
+  pack_signed_coefs(L.coef, db.nc, kMaxClasses, p.up_coef);
   p.x = L.x;
   p.y = L.y;
   p.xprev = L.xprev;
@@ -649,15 +609,8 @@ hipError_t colpass_t(const ApplyLaunch& L, int* pgrid) {
   p.tol = L.tol;
   p.norm_inf = L.norm_inf;
   p.up_tab = db.up_tab;
-  for (int s = 0; s < 64; ++s) {
-    const int c = db.up_slot_class[s];
-    const bool ok = s < db.up_nslots && L.coef;
-    p.slot_coef[2 * s] = ok ? L.coef[2 * c] : 0.0;
-    p.slot_coef[2 * s + 1] = ok ? L.coef[2 * c + 1] : 0.0;
-    const bool oko = s < db.up_nslots && L.coef_obs;
-    p.slot_coef_obs[2 * s] = oko ? L.coef_obs[2 * c] : 0.0;
-    p.slot_coef_obs[2 * s + 1] = oko ? L.coef_obs[2 * c + 1] : 0.0;
-  }
+  pack_slot_coefs(L.coef, db.nc, db.up_slot_class, db.up_nslots, p.slot_coef);
+  pack_slot_coefs(L.coef_obs, db.nc, db.up_slot_class, db.up_nslots, p.slot_coef_obs);
   p.x = L.x;
   p.y = L.y;
   p.xprev = L.xprev;

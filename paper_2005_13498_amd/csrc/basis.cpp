@@ -124,6 +124,22 @@ static void build_spin(const Lattice& lat, int n_el, const std::vector<HopClass>
   T.slot_class.assign(64, 0);
   for (int c = 0; c < nc; ++c)
     for (int s = T.slot_begin[c]; s < T.slot_begin[c + 1] && s < 64; ++s) T.slot_class[s] = static_cast<uint8_t>(c);
+  // grouped copy: class c gets round_up(max hops of c, 4) slots
+  std::vector<int> gbeg(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) gbeg[c + 1] = gbeg[c] + ((T.slot_begin[c + 1] - T.slot_begin[c] + 3) / 4) * 4;
+  T.grp_class.assign(8, 0);
+  T.gslots = gbeg[nc] <= 32 ? gbeg[nc] : 0;
+  T.tabg.clear();
+  if (T.gslots > 0) {
+    for (int c = 0; c < nc; ++c)
+      for (int g = gbeg[c] / 4; g < gbeg[c + 1] / 4; ++g) T.grp_class[g] = static_cast<uint8_t>(c);
+    T.tabg.assign(static_cast<size_t>(T.gslots) * T.dim, static_cast<uint16_t>(T.dim));
+    for (int r = 0; r < T.dim; ++r)
+      for (int c = 0; c < nc; ++c)
+        for (int s = T.slot_begin[c]; s < T.slot_begin[c + 1]; ++s)
+          T.tabg[static_cast<size_t>(r) * T.gslots + gbeg[c] + (s - T.slot_begin[c])] =
+              T.tabc[static_cast<size_t>(r) * T.maxs_pad + s];
+  }
 }
 
 std::string build_basis(const Lattice& lat, int n_up, int n_dn, Basis& B, bool& sector_error) {

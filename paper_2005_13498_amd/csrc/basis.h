@@ -45,6 +45,13 @@ struct SpinTable {
   std::vector<uint16_t> tabc;         // [dim*maxs_pad]
   std::vector<uint8_t> slot_class;    // [64]
   int nslots = 0, maxs_pad = 8;
+  // the same entries with every class's slot range rounded up to a multiple
+  // of 4 (group g = slots 4g..4g+3 belongs to class grp_class[g]), so the
+  // block apply sums each group of staged values first and multiplies the
+  // sum by its class coefficient once; gslots = total slots (0 if > 32)
+  std::vector<uint16_t> tabg;         // [dim*gslots]
+  std::vector<uint8_t> grp_class;     // [8]
+  int gslots = 0;
 };
 
 struct Lattice {

@@ -60,7 +60,21 @@ struct DevBasis {
   uint16_t* up_tab = nullptr;    // [dim_up][up_maxs_pad] index src + sign * (dim_up + 1), pad dim_up
   uint8_t up_slot_class[64] = {0};
   int up_nslots = 0, up_maxs_pad = 8;
+  // grouped tables of the block apply (class ranges rounded up to a multiple
+  // of four slots): [dim][gslots] entries as above, class of every group
+  uint16_t* dn_tabg = nullptr;
+  uint16_t* up_tabg = nullptr;
+  uint8_t dn_gclass[8] = {0};
+  uint8_t up_gclass[8] = {0};
+  int dn_gslots = 0, up_gslots = 0;
   int two_pass = -1;             // -1 automatic, 0 never, 1 whenever it fits
+  int block_path = -1;           // blocks of vectors: -1 two-pass block kernels where they fit, 0 one pass
+  // tuned choices per precision [c128, c64] (-1 = the built-in rule), used
+  // while two_pass / block_path are automatic: single vectors two-pass (1) or
+  // one pass (0); blocks of 2, 4, 8 ([1], [2], [3]) on the two-pass block
+  // kernels (1) or the one-pass kernel (0)
+  int tuned_single[2] = {-1, -1};
+  int tuned_block[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
   int up_max_hops = 0, dn_max_hops = 0;
 };
 
@@ -112,6 +126,12 @@ struct ApplyLaunch {
 // grid_out: workgroups of the kernel that wrote the launch's partial sums.
 hipError_t launch_apply(const ApplyLaunch& L, int* grid_out = nullptr);
 int apply_grid(const DevBasis& db, int prec, int nv);    // most workgroups any apply kernel writes partials for
+// Two-pass apply of blocks of nv = 2, 4, 8 interleaved vectors (a row pass
+// and a column pass, each staging its tile row or column of the whole block
+// once in LDS): where the grouped tables and the staged row and column fit.
+// The column pass writes its partial sums for dim_dn workgroups.
+bool block_two_pass(const DevBasis& db, int prec, int nv);
+size_t block_lds_bytes(const DevBasis& db, int prec, int nv);
 // Two-pass apply (single vectors, plain and Lanczos modes): a row pass does
 // the diagonal and the down hops, a column pass stages kColW columns of x
 // for all up strings in LDS and adds the up hops (and the Lanczos epilogue).
@@ -165,7 +185,32 @@ struct CombineLog {
 // combines do nothing.
 hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
                           StepCtl* ctl, double* partials, int seq, CombineLog* log, double* obs_log, int nobs,
-                          hipStream_t s);
+                          hipStream_t s, void* copy_to = nullptr);  // copy_to: a second copy of the result (nv = 1)
+
+// Overlaps o_v = <c_v psi_v | phi_v> of nv members (same target sector and
+// spin of the operator) with source-sector states psi_v = traj + psi_off[v],
+// gathered through the members' operator maps maps/sgns [nv][map_len] (tile
+// rows for an up operator, columns for a down one).  phi: the members in the
+// target sector, interleaved [n_t][nv] or in the ABI layout [nv][n_t].
+// Partials [nv][overlap_grid(n_t)][2] (re, im); nothing after an abandoned step.
+struct OverlapArgs {
+  int64_t n_t;
+  int dim_dn_t, dim_dn_s, down, map_len, interleaved;
+  int64_t psi_off[kMaxNV];
+  const int32_t* maps;
+  const int8_t* sgns;
+  const void* traj;
+  const void* phi;
+  const StepCtl* ctl;
+  double* partials;
+};
+hipError_t launch_overlaps(int prec, int nv, const OverlapArgs& a, hipStream_t s);
+// out[s * out_stride + q] = sum over r < rows of part[s * set_stride + r * cols + q], q < cols, s < n_sets.
+hipError_t launch_reduce_sets(const double* part, int64_t set_stride, int n_sets, int rows, int cols, double* out,
+                              int64_t out_stride, hipStream_t s);
+int overlap_grid(int64_t n_t);
+// x[i] = (sin(0.618 i), cos(0.377 i + 1)) for i < n (complex of precision prec): test vectors of the tuner.
+hipError_t launch_fill_probe(int prec, int64_t n, void* x, hipStream_t s);
 
 // |v|^2 partials of the step input (if norm), tau of every vector, cleared control block.
 hipError_t launch_step_begin(int prec, int nv, int64_t n, const void* v, VecState* st, StepCtl* ctl, double tau,

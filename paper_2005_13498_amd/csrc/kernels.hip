@@ -106,7 +106,7 @@ __device__ void record_step(const VecState* st, StepCtl* ctl, CombineLog* log, d
 template <typename R, int NV>
 __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, void* const* slots, const VecState* st,
                                                     StepCtl* ctl, double* partials, int seq, CombineLog* log,
-                                                    double* obs_log, int nobs) {
+                                                    double* obs_log, int nobs, void* out2) {
   using V = typename CT<R>::T;
   __shared__ double red[kWaves * kMaxNV];
   __shared__ double cr[kMaxNV][kMMax], ci[kMaxNV][kMMax];
@@ -147,6 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, void* const* slot
     }
     const V o = V{static_cast<R>(ar), static_cast<R>(ai)};
     out[i] = o;
+    if (out2) static_cast<V*>(out2)[i] = o;
     n2 += (double)o.x * o.x + (double)o.y * o.y;
   }
   block_partials<NV>(&n2, 1, red, partials + (size_t)blockIdx.x * NV);
@@ -302,6 +303,66 @@ __global__ __launch_bounds__(kBlock) void k_dots(int64_t n, int nvec, const type
       partials[(size_t)blockIdx.x * 2 * nvec + 2 * k] = re;
       partials[(size_t)blockIdx.x * 2 * nvec + 2 * k + 1] = im;
     }
+  }
+}
+
+// Overlaps of NV members with the state they were made from (Sec. 2.5,
+// Eq. (Glg)): member v, in the target sector, with operator map map_v (tile
+// rows for an up operator, columns for a down one; -1 = no source) and signs
+// sgn_v, and psi_v the source-sector state at its time,
+//   o_v = <c_v psi_v | phi_v> = sum_y sgn_v(y) conj(psi_v[src_v(y)]) phi_v[y],
+// gathered straight from psi_v (no copy of c_v psi_v).  phi is interleaved
+// ([y][NV]) or in the ABI layout ([v][n_t]).  Partials [NV][grid][2]; the
+// kernel does nothing after an abandoned step (ctl->abort).
+template <typename R, int NV>
+__global__ __launch_bounds__(kBlock) void k_overlaps(OverlapArgs p) {
+  using V = typename CT<R>::T;
+  __shared__ double red[kWaves];
+  if (p.ctl && p.ctl->abort) return;
+  const V* psi = static_cast<const V*>(p.traj);
+  const V* phi = static_cast<const V*>(p.phi);
+  double acc[2 * NV];
+#pragma unroll
+  for (int q = 0; q < 2 * NV; ++q) acc[q] = 0.0;
+  for (int64_t y = (int64_t)blockIdx.x * kBlock + threadIdx.x; y < p.n_t; y += (int64_t)gridDim.x * kBlock) {
+    const int a = static_cast<int>(y / p.dim_dn_t), b = static_cast<int>(y % p.dim_dn_t);
+    const int r = p.down ? b : a;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int src = p.maps[v * p.map_len + r];
+      if (src < 0) continue;
+      const int64_t se = p.down ? (int64_t)a * p.dim_dn_s + src : (int64_t)src * p.dim_dn_s + b;
+      const V x = psi[p.psi_off[v] + se];
+      const V f = p.interleaved ? phi[y * NV + v] : phi[v * p.n_t + y];
+      const double sg = static_cast<double>(p.sgns[v * p.map_len + r]);
+      acc[2 * v] += sg * ((double)x.x * f.x + (double)x.y * f.y);
+      acc[2 * v + 1] += sg * ((double)x.x * f.y - (double)x.y * f.x);
+    }
+  }
+  // member v's pair goes to partials + (v grid + workgroup) 2
+#pragma unroll
+  for (int q = 0; q < 2 * NV; ++q) {
+    const double t = block_sum(acc[q], red);
+    if (threadIdx.x == 0) p.partials[((size_t)(q >> 1) * gridDim.x + blockIdx.x) * 2 + (q & 1)] = t;
+  }
+}
+
+// Deterministic test vector: x[i] = (sin(0.618 i), cos(0.377 i + 1)).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fill_probe(int64_t n, typename CT<R>::T* x) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    x[i] = typename CT<R>::T{static_cast<R>(sin(0.618 * (double)i)), static_cast<R>(cos(0.377 * (double)i + 1.0))};
+}
+
+// out[s * out_stride + q] = sum over r < rows of part[s * set_stride + r * cols + q]
+// for q < cols, one workgroup per set s (fixed order).
+__global__ __launch_bounds__(kBlock) void k_reduce_sets(const double* part, int64_t set_stride, int rows, int cols,
+                                                        double* out, int64_t out_stride) {
+  __shared__ double red[kWaves];
+  const double* P = part + (int64_t)blockIdx.x * set_stride;
+  for (int q = 0; q < cols; ++q) {
+    const double s = reduce_column(P, rows, cols, q, red);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * out_stride + q] = s;
   }
 }
 
@@ -521,6 +582,8 @@ using namespace dev;
 
 hipError_t launch_apply_c128(const ApplyLaunch& L, int grid, size_t lds, int* pgrid);
 hipError_t launch_apply_c64(const ApplyLaunch& L, int grid, size_t lds, int* pgrid);
+hipError_t launch_block_c128(const ApplyLaunch& L, int* pgrid);
+hipError_t launch_block_c64(const ApplyLaunch& L, int* pgrid);
 
 int elem_grid(int64_t n) {
   // four workgroups per CU at most (16 waves) for these memory-bound passes;
@@ -533,7 +596,9 @@ int apply_chunks(const DevBasis& db, int prec, int nv) {
   // Several column chunks per row would keep more up-hop gathers in flight
   // (measured: at most ~15% faster for plain applies at 12 sites, and slower
   // inside the Lanczos loop, whose first phase sums the previous kernel's
-  // partials in every workgroup) -- one chunk per row
+  // partials in every workgroup) -- one chunk per row.  The fused Lanczos row
+  // pass requires one chunk (it updates and sums whole rows); its launcher
+  // refuses anything else.
   (void)db;
   (void)prec;
   (void)nv;
@@ -571,6 +636,7 @@ bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
   if (obs && mode != kLanczos) return false;
   if (colpass_lds_bytes(db, prec) > 150 * 1024) return false;
   if (db.two_pass == 1) return true;
+  if (db.tuned_single[prec] >= 0) return db.tuned_single[prec] == 1;
   // automatic: when a vector is larger than one XCD's L2 the up-hop row
   // gathers of the one-pass kernel stream from the Infinity Cache.  With 2
   // staged columns (complex128, 14 sites) only the Lanczos iterations gain
@@ -581,7 +647,22 @@ bool apply_two_pass(const DevBasis& db, int prec, int nv, int mode, bool obs) {
 }
 
 int apply_grid(const DevBasis& db, int prec, int nv) {
-  return std::max(db.dim_up * apply_chunks(db, prec, nv), colpass_grid(db, prec));
+  return std::max({db.dim_up * apply_chunks(db, prec, nv), colpass_grid(db, prec), db.dim_dn});
+}
+
+static bool block_slots_ok(int g) { return g == 8 || g == 12 || g == 16 || g == 20 || g == 24; }
+
+size_t block_lds_bytes(const DevBasis& db, int prec, int nv) {
+  const size_t es = prec == 0 ? 16 : 8;
+  return (static_cast<size_t>(std::max(db.dim_up, db.dim_dn)) + 1) * nv * es;
+}
+
+bool block_two_pass(const DevBasis& db, int prec, int nv) {
+  if (!(nv == 2 || nv == 4 || nv == 8) || db.block_path == 0 || !db.dn_tabg || !db.up_tabg) return false;
+  const int gi = nv == 2 ? 1 : (nv == 4 ? 2 : 3);
+  if (db.block_path == -1 && db.tuned_block[prec][gi] == 0) return false;
+  if (!block_slots_ok(db.dn_gslots) || !block_slots_ok(db.up_gslots)) return false;
+  return block_lds_bytes(db, prec, nv) <= 150 * 1024;
 }
 
 int apply_nq_two_pass(bool obs) { return obs ? 2 : 1; }  // column pass: alpha [, up-hop obs part]
@@ -600,6 +681,12 @@ size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows) {
 }
 
 hipError_t launch_apply(const ApplyLaunch& L, int* grid_out) {
+  if (L.nv > 1 && L.mode != kObsOnly && block_two_pass(*L.db, L.prec, L.nv)) {
+    int pgrid = 0;
+    const hipError_t e = L.prec == 0 ? launch_block_c128(L, &pgrid) : launch_block_c64(L, &pgrid);
+    if (grid_out) *grid_out = pgrid;
+    return e;
+  }
   const int grid = L.db->dim_up * apply_chunks(*L.db, L.prec, L.nv);
   int pgrid = grid;
   const size_t lds = apply_lds_bytes(*L.db, L.prec, L.nv, L.rows);
@@ -679,16 +766,45 @@ hipError_t launch_update(int prec, int nv, int64_t n, void* w, const void* uj, V
 
 hipError_t launch_combine(int prec, int nv, int64_t n, void* const* slots_dev, const VecState* st,
                           StepCtl* ctl, double* partials, int seq, CombineLog* log, double* obs_log, int nobs,
-                          hipStream_t s) {
+                          hipStream_t s, void* copy_to) {
   const int grid = elem_grid(n * nv);
   if (prec == 0) {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_combine<double, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
-                                         st, ctl, partials, seq, log, obs_log, nobs));
+                                         st, ctl, partials, seq, log, obs_log, nobs, copy_to));
   } else {
     HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_combine<float, NVC>), dim3(grid), dim3(kBlock), 0, s, n, slots_dev,
-                                         st, ctl, partials, seq, log, obs_log, nobs));
+                                         st, ctl, partials, seq, log, obs_log, nobs, copy_to));
   }
   return hipGetLastError();
+}
+
+hipError_t launch_overlaps(int prec, int nv, const OverlapArgs& a, hipStream_t s) {
+  const int grid = overlap_grid(a.n_t);
+  if (prec == 0) {
+    HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_overlaps<double, NVC>), dim3(grid), dim3(kBlock), 0, s, a));
+  } else {
+    HUB_NV_SWITCH(nv, hipLaunchKernelGGL((k_overlaps<float, NVC>), dim3(grid), dim3(kBlock), 0, s, a));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_sets(const double* part, int64_t set_stride, int n_sets, int rows, int cols, double* out,
+                              int64_t out_stride, hipStream_t s) {
+  if (n_sets < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_sets, dim3(n_sets), dim3(kBlock), 0, s, part, set_stride, rows, cols, out, out_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_probe(int prec, int64_t n, void* x, hipStream_t s) {
+  const int grid = elem_grid(n);
+  if (prec == 0) hipLaunchKernelGGL(k_fill_probe<double>, dim3(grid), dim3(kBlock), 0, s, n, static_cast<double2*>(x));
+  else hipLaunchKernelGGL(k_fill_probe<float>, dim3(grid), dim3(kBlock), 0, s, n, static_cast<float2*>(x));
+  return hipGetLastError();
+}
+
+int overlap_grid(int64_t n_t) {
+  const int64_t g = (n_t + 4 * kBlock - 1) / (4 * kBlock);
+  return static_cast<int>(g < 1 ? 1 : (g > 256 ? 256 : g));
 }
 
 hipError_t launch_step_log(int nv, const VecState* st, StepCtl* ctl, void* log, double* obs_log, int nobs,

@@ -3,6 +3,8 @@
 
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace hub {
@@ -216,6 +218,31 @@ __device__ inline void krylov_end_at(int j, double b, VecState& S, StepCtl* ctl,
   ctl->all_done = 1;
   ctl->any_maxed = 0;
   ctl->iter = j;
+}
+
+// Launch with optional timing events attached to the dispatch.
+template <typename K, typename A>
+hipError_t launch_ev(K fn, int grid, int blk, size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A& args) {
+  if (!e0 && !e1) {
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(blk), lds, st, args);
+    return hipGetLastError();
+  }
+  void* kargs[] = {&args};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(blk), kargs, lds, st, e0, e1, 0);
+}
+
+// Opts kernel fn into the largest dynamic LDS a CU allows (160 KB minus its
+// static LDS); returns the dynamic LDS bytes a launch may then request.
+inline int dyn_lds_opt_in(const void* fn) {
+  hipFuncAttributes fa{};
+  size_t stat = 0;
+  if (hipFuncGetAttributes(&fa, fn) == hipSuccess) stat = fa.sharedSizeBytes;
+  const int want = 160 * 1024 - static_cast<int>(stat);
+  const int got = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess
+                      ? want
+                      : 64 * 1024 - static_cast<int>(stat);
+  (void)hipGetLastError();  // a refused opt-in is not a launch error
+  return got;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,220 @@
+"""Full-size parity of the headline paths against the oracle.
+
+* 12-site 3x4 periodic cluster at half filling (dim 853,776), the workload's
+  pulse (A0 = first seeded draw, omega = 8, t0 = 2.5, sigma = 0.5), dt =
+  0.005: 40 midpoint steps across the pulse peak, t in [2.4, 2.6], where
+  |A| reaches 0.64 and the Krylov dimension is largest.  The start vector is
+  a low-energy state of H(2.4) computed on the CPU (the lowest Ritz vector of
+  a 40-dimensional Krylov space of the oracle's H from a seeded vector): the
+  oracle's full ground-state solve at this size takes minutes, and the
+  trajectory check does not depend on which start vector both sides share.
+  psi, d(t) and E(t) against the exact-exponential stepper of Eq.
+  (time-stepping): complex128 within 1e-10 (Krylov tol 1e-13, as the
+  8-site workload test), complex64 within 1e-5 on the observables.
+* 12-site observables of a vector against the oracle's.
+* 14-site ring at U = 0 and half filling (7/7): midpoint steps from the
+  product of two Slater determinants (orbitals of the ring with seeded
+  on-site disorder, so that the state is not an eigenstate of H(A)),
+  through the two-pass Lanczos iterations whose column pass stages
+  one copy of its columns (complex64 with 4 columns, complex128 with 2),
+  against the free-fermion closed form, exact for the many-body midpoint
+  stepper at any size.
+* The a-posteriori estimate of Alg. 6 (Sec. 3.4): per-step Krylov dimension
+  m, estimate eps and last off-diagonal beta of the device against the
+  oracle's literal Alg. 6 on the 8-site ring, at tolerances chosen between
+  two consecutive estimates that differ by more than a factor 30, so the
+  stopping iteration is not decided by rounding.
+"""
+import numpy as np
+import pytest
+
+import paper_2005_13498_amd as hub
+from synth import workloads, ring, PulseParams, random_state
+from oracle import (HubbardOracle, to_canonical, from_canonical, pulse_A, observables,
+                    midpoint_step_exact, krylov_step_alg6)
+from oracle import freefermion as ff
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+C2_T_START = 2.4
+C2_STEPS = 40
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _low_energy_state(H, seed, k=40):
+    """Lowest Ritz vector of the k-dimensional Krylov space of H from a seeded
+    complex vector (Lanczos with full reorthogonalisation), normalised."""
+    v = random_state(H.shape[0], seed=seed)[0]
+    V = np.zeros((H.shape[0], k), dtype=np.complex128)
+    T = np.zeros((k, k))
+    V[:, 0] = v
+    for j in range(k):
+        w = H @ V[:, j]
+        w -= V[:, : j + 1] @ (V[:, : j + 1].conj().T @ w)
+        w -= V[:, : j + 1] @ (V[:, : j + 1].conj().T @ w)
+        T[j, j] = float(np.real(np.vdot(V[:, j], H @ V[:, j])))
+        if j + 1 < k:
+            b = np.linalg.norm(w)
+            T[j, j + 1] = T[j + 1, j] = b
+            V[:, j + 1] = w / b
+    evals, evecs = np.linalg.eigh(T)
+    x = V @ evecs[:, 0]
+    return x / np.linalg.norm(x)
+
+
+@pytest.fixture(scope="module")
+def c2_reference():
+    """Oracle trajectory of the 12-site workload across the pulse peak."""
+    w = workloads()["cluster3x4"]
+    ham = HubbardOracle(w.lattice, w.U, w.n_up, w.n_dn)
+    psi0 = _low_energy_state(ham.H(pulse_A(w.pulse, C2_T_START)), seed=2024)
+    v = psi0.copy()
+    obs = []
+    for k in range(C2_STEPS):
+        t = C2_T_START + k * w.dt
+        n, e, d, _ = observables(ham, v, pulse_A(w.pulse, t))
+        obs.append((t, n, e, d))
+        v = midpoint_step_exact(ham, v, t, w.dt, w.pulse)
+    t = C2_T_START + C2_STEPS * w.dt
+    n, e, d, _ = observables(ham, v, pulse_A(w.pulse, t))
+    obs.append((t, n, e, d))
+    return w, ham, psi0, v, np.array(obs)
+
+
+def test_cluster3x4_trajectory_through_pulse_c128(c2_reference):
+    w, ham, psi0, psi_ref, obs_ref = c2_reference
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
+    try:
+        v = torch.from_numpy(to_canonical(psi0, ham.states, 12)).to(DEV)
+        st, obs, log = hub.hub_propagate(B.handle, [w.pulse], C2_T_START, w.dt, C2_STEPS,
+                                         hub.make_opts(tol=1e-13, m_max=30), v)
+        got = from_canonical(v.cpu().numpy(), ham.states, 12)
+        assert _rel(got, psi_ref) < 1e-10
+        o = obs[:, 0, :]
+        assert np.max(np.abs(o[:, 0] - obs_ref[:, 0])) < 1e-12
+        for col in (2, 3):  # E/N_s, d
+            err = np.max(np.abs(o[:, col] - obs_ref[:, col])) / np.max(np.abs(obs_ref[:, col]))
+            assert err < 1e-10, (col, err)
+        assert np.max(np.abs(o[:, 1] - obs_ref[:, 1])) < 1e-12
+        # the window is the pulse regime: the field is strong and m is large
+        assert max(abs(pulse_A(w.pulse, t)) for t in obs_ref[:, 0]) > 0.6
+        assert (log[:, 0, 2] == 1).all() and log[:, 0, 0].max() >= 8
+    finally:
+        B.close()
+
+
+def test_cluster3x4_trajectory_through_pulse_c64(c2_reference):
+    w, ham, psi0, psi_ref, obs_ref = c2_reference
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
+    try:
+        v = torch.from_numpy(to_canonical(psi0, ham.states, 12)).to(DEV).to(torch.complex64)
+        st, obs, log = hub.hub_propagate(B.handle, [w.pulse], C2_T_START, w.dt, C2_STEPS,
+                                         hub.make_opts(tol=1e-8, m_max=30), v)
+        o = obs[:, 0, :]
+        assert np.max(np.abs(o[:, 2] - obs_ref[:, 2])) < 1e-5
+        assert np.max(np.abs(o[:, 3] - obs_ref[:, 3])) < 1e-5
+        assert np.max(np.abs(o[:, 1] - 1.0)) < 1e-5
+        got = from_canonical(v.to(torch.complex128).cpu().numpy(), ham.states, 12)
+        assert _rel(got, psi_ref) < 1e-4
+    finally:
+        B.close()
+
+
+def test_cluster3x4_observables_match_oracle(c2_reference):
+    w, ham, psi0, psi_ref, obs_ref = c2_reference
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
+    try:
+        xs = [psi_ref, 1.3 * random_state(ham.dim, seed=77)[0]]
+        As = [pulse_A(w.pulse, C2_T_START + C2_STEPS * w.dt), -0.83]
+        x = torch.from_numpy(np.concatenate([to_canonical(v, ham.states, 12) for v in xs])).to(DEV)
+        out, site = hub.hub_observables(B.handle, As, x, site=True)
+        for k in range(2):
+            n_ref, e_ref, d_ref, s_ref = observables(ham, xs[k], As[k])
+            assert out[k, 1] == pytest.approx(n_ref, rel=1e-13)
+            assert out[k, 2] == pytest.approx(e_ref, rel=1e-12, abs=1e-13)
+            assert out[k, 3] == pytest.approx(d_ref, rel=1e-12)
+            assert np.allclose(site[k, :12], s_ref, rtol=1e-12, atol=1e-15)
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("dtype,tol,bar", [(torch.complex64, 1e-7, 1e-5), (torch.complex128, 1e-12, 1e-9)])
+def test_ring14_free_fermions_single_copy_column_pass(dtype, tol, bar):
+    """U = 0, 14-site ring, 7/7: the automatic path runs the fused two-pass
+    iterations whose column pass stages one copy (the sign from the hop's
+    index): 4 columns for complex64, 2 for complex128."""
+    lat = ring(14)
+    p = PulseParams(0, 1.2, 5.0, 0.25, 0.15)
+    # A Slater determinant of the ring's own orbitals (plane waves) is an
+    # eigenstate of H(A) for every A; the ground orbitals of the ring with
+    # seeded on-site disorder give one that evolves (m > 1 every step).
+    eps = np.random.default_rng(14).uniform(-1.0, 1.0, 14)
+    phi, _, gap = ff.ground_orbitals(lat.with_onsite(eps), 7, 0.0)
+    assert gap > 0.5
+    B = hub.Basis(lat, 0.0, 7, 7)
+    try:
+        # the canonical order: strings of 7 bits among 14 as increasing integers
+        strings = np.array([s for s in range(1 << 14) if bin(s).count("1") == 7], dtype=np.uint32)
+        up, dn = hub.hub_basis_states(B.handle)
+        assert np.array_equal(up, strings) and np.array_equal(dn, strings)
+        occ = lambda s: [i for i in range(14) if (int(s) >> i) & 1]
+        det_up = np.array([np.linalg.det(phi[occ(s), :]) for s in up])
+        det_dn = np.array([np.linalg.det(phi[occ(s), :]) for s in dn])
+        v = torch.outer(torch.from_numpy(det_up).to(DEV), torch.from_numpy(det_dn).to(DEV)).reshape(-1)
+        v = v.to(dtype).contiguous()
+        dt, n = 0.02, 8
+        st, obs, log = hub.hub_propagate(B.handle, [p], 0.0, dt, n, hub.make_opts(tol=tol, m_max=30), v)
+        phis = [phi.copy(), phi.copy()]
+        emax = 0.0
+        for k in range(n + 1):
+            E, d, _ = ff.observables(lat, phis, pulse_A(p, k * dt))
+            emax = max(emax, abs(obs[k, 0, 2] - E), abs(obs[k, 0, 3] - d))
+            if k < n:
+                phis = ff.step(lat, phis, k * dt, dt, p)
+        assert emax < bar, emax
+        assert np.max(np.abs(obs[:, 0, 1] - 1.0)) < bar
+        assert max(abs(pulse_A(p, k * dt)) for k in range(n)) > 0.45
+        assert (log[:, 0, 0] >= 3).all()
+    finally:
+        B.close()
+        torch.cuda.empty_cache()
+
+
+def test_krylov_estimate_matches_alg6():
+    """Device m, eps and beta_m of single Krylov steps against the literal
+    Alg. 6 (no reorthogonalisation on either side) on the 8-site ring."""
+    lat = ring(8)
+    ham = HubbardOracle(lat, 8.0, 4, 4)
+    H_inf = float(np.max(np.abs(ham.H(0.3)).sum(axis=1)))
+    B = hub.Basis(lat, 8.0, 4, 4)
+    checked = 0
+    try:
+        for seed, A, tau in [(3, 0.3, 0.01), (4, -0.7, 0.02), (5, 1.1, 0.05), (6, 0.0, 0.005)]:
+            x = random_state(ham.dim, seed=seed)[0]
+            apply = lambda u, A=A: ham.apply(A, u)
+            # the estimate of every Krylov dimension j (N_max = j, no stop)
+            eps = [krylov_step_alg6(apply, x, tau, j, 0.0, H_inf)[1]["eps"] for j in range(1, 21)]
+            for m in range(3, 20):
+                e_m, e_prev = eps[m - 1], eps[m - 2]
+                if not (e_prev > 30 * e_m and 1e-11 < e_m < 1e-4):
+                    continue
+                tol = np.sqrt(e_m * e_prev)
+                res, info = krylov_step_alg6(apply, x, tau, 30, tol, H_inf)
+                assert info["m"] == m and info["converged"] and not info["breakdown"]
+                xd = torch.from_numpy(to_canonical(x, ham.states, 8)).to(DEV)
+                st, di = hub.hub_krylov_expm_step(B.handle, [A], tau,
+                                                  hub.make_opts(tol=tol, m_max=30), xd)
+                assert int(di[0, 0]) == m, (seed, m, di[0])
+                assert di[0, 2] == 1 and di[0, 3] == 0
+                assert di[0, 4] == pytest.approx(info["eps"], rel=1e-3)
+                assert di[0, 5] == pytest.approx(info["betas"][m - 1], rel=1e-10)
+                assert _rel(from_canonical(xd.cpu().numpy(), ham.states, 8), res) < 1e-12
+                checked += 1
+        assert checked >= 8
+    finally:
+        B.close()

@@ -196,9 +196,12 @@ def test_propagate_ring8_workload_parity():
     st, e0, gap = hub.hub_ground_state(B.handle, A0, v, hub.make_opts(tol=1e-13, m_max=60))
     assert e0 == pytest.approx(E0, abs=1e-11 * abs(E0))
     g_c = to_canonical(g, ham.states, 8)
-    v0 = v.cpu().numpy()
-    # start both from the GPU ground state so that the phases agree
-    psi = from_canonical(v0, ham.states, 8)
+    # the GPU ground state equals the oracle's up to a global phase; both
+    # sides then start from the oracle's
+    got0 = v.cpu().numpy()
+    assert abs(abs(np.vdot(got0, g_c)) - 1.0) < 1e-12
+    psi = g.copy()
+    v = _to_dev(g_c)
     n = w.n_steps
     _, obs_ref = _prop_ref(ham, psi, w, n)
     st, obs, log = hub.hub_propagate(B.handle, [w.pulse], 0.0, w.dt, n, hub.make_opts(tol=1e-13, m_max=30), v)
