@@ -299,6 +299,17 @@ def cpu_baseline(seconds: float, member: int = -1) -> dict:
             "host_cpus": os.cpu_count(), "host_cpu_model": model}
 
 
+def plan_label(hub, B, prec: int, nvec: int, propagate: bool) -> str:
+    """What the library runs for nvec vectors: group sizes and their kernels."""
+    names = {0: "one-pass kernel", 1: "two-pass single-vector kernels", 2: "two-pass block kernels"}
+    plan = hub.hub_get_plan(B.handle, prec, nvec, propagate)
+    parts = {}
+    for g, k in plan:
+        parts.setdefault((g, k), 0)
+        parts[(g, k)] += 1
+    return "; ".join(f"{c} group(s) of {g} on the {names[k]}" for (g, k), c in sorted(parts.items()))
+
+
 def batched_variants(hub, B, v0, t_start: float, w, steps: int) -> dict:
     """Mixed precision and batching at 12 sites: the same ground state under
     8 pulse amplitudes (the seeded A0 draws), propagated by one hub_propagate
@@ -336,7 +347,9 @@ def batched_variants(hub, B, v0, t_start: float, w, steps: int) -> dict:
         launches, kms, bpl = hub.hub_profile_read(B.handle)
         hub.hub_profile_enable(B.handle, False)
         us = kms / max(launches, 1) * 1e3
-        res[name] = {"member_steps_per_s": nv * steps / el, "ms_per_step": el / steps * 1e3,
+        res[name] = {"kernels": plan_label(hub, B, hub.HUB_C128 if dtype == torch.complex128 else hub.HUB_C64, nv,
+                                           True),
+                     "member_steps_per_s": nv * steps / el, "ms_per_step": el / steps * 1e3,
                      "timed_avg_launch_us": us, "timed_gbps": bpl / (us * 1e-6) / 1e9 if launches else 0.0,
                      "timed_bytes_per_launch": bpl, "mean_krylov_m": float(np.mean(log[:, :, 0]))}
         obs[name] = o
@@ -350,47 +363,92 @@ def batched_variants(hub, B, v0, t_start: float, w, steps: int) -> dict:
     return res
 
 
-def controller_variant(hub, B, w, v0, v_start, t_start: float, steps: int, v_plain, obs_plain, plain_steps_per_s):
-    """Learned controller at 12 sites: trained on adaptive logs of four other
-    seeded amplitudes (A0 draws 2..5, 1000 steps from the ground state,
-    untimed), then the timed
-    workload again from the same start vector with the controlled schedule.
-    Reports steps/s, the schedule counters, and that vector and observables
-    are bit-identical to the run with the default schedule."""
+def controller_c5_variant(hub) -> dict:
+    """The learned Krylov controller as configured.  Training rows from the
+    plain adaptive method (tol 1e-8, default schedule, untimed): the 10-site
+    ring (5/5) under 12 seeded U-groups x 8 pulses, 1500 steps of 0.01, and
+    the 12-site cluster (6/6) under 4 U-groups x 8 pulses, 1500 steps of
+    0.005, from the ground state of H(0) at each U; U ~ U[4, 12], A0 ~
+    U[0.2, 1.2], omega ~ U[U/2, 2U], pulses centred at t0 = 1.5 with sigma =
+    0.5.  Full-batch Adam on the GPU kernels.  Evaluation on held-out 12-site
+    pulses (4 draws of another seed, 1000 steps of 0.005 from the ground state,
+    tol 1e-8): steps/s with the learned controller (chunk 16, margin 1), the
+    default chunked schedule and the synchronous one, launches per step,
+    fallback rate, and bit-identity of the states and logs with the
+    synchronous schedule."""
     import numpy as np
     import torch
-    from synth import PulseParams
+    from synth import ring, cluster_2d, controller_groups
     from paper_2005_13498_amd import controller as ctl
 
-    opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
-    chunk, margin = 16, 1
+    tol, chunk, margin = 1e-8, 16, 1
     t0 = time.perf_counter()
-    pulses = [PulseParams(0, a, w.pulse.omega, w.pulse.t0, w.pulse.sigma) for a in w.extra["A0_batch"][1:5]]
-    X, Y = ctl.collect_rows(B, v0, pulses, 0.0, w.dt, 1000, opts, chunk=chunk)
-    params, hist = ctl.train(X, Y, steps=600, lr=3e-3, seed=0)
+    X1, Y1 = ctl.group_runs(hub, ring(10), 5, 5, controller_groups(12, 8, 13500), 1.5, 0.5, 0.01, 1500, tol, chunk)
+    X2, Y2 = ctl.group_runs(hub, cluster_2d(3, 4), 6, 6, controller_groups(4, 8, 13501), 1.5, 0.5, 0.005, 1500, tol,
+                            chunk)
+    X, Y = np.concatenate([X1, X2]), np.concatenate([Y1, Y2])
+    t_rows = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, hist = ctl.train(X, Y, steps=1500, lr=3e-3, seed=0, report_every=500)
     t_train = time.perf_counter() - t0
-    hub.hub_controller_load(B.handle, params)
-    hub.hub_controller_enable(B.handle, True, chunk, margin)
-    v = v_start.clone()
-    hub.hub_propagate(B.handle, [w.pulse], t_start, w.dt, 10, opts, v.clone())  # warm-up of the schedule
-    hub.hub_controller_read_stats(B.handle)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st, obs, log = hub.hub_propagate(B.handle, [w.pulse], t_start, w.dt, steps, opts, v)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
-    stats = hub.hub_controller_read_stats(B.handle)
-    hub.hub_controller_enable(B.handle, False)
-    same = bool(torch.equal(v, v_plain)) and bool(np.array_equal(obs, obs_plain))
-    print(f"[bench] controller: {steps / el:.0f} steps/s, fallbacks {stats['fallbacks']}, "
-          f"bit-identical {same}", file=sys.stderr, flush=True)
-    return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3,
-            "speedup_vs_default": steps / el / plain_steps_per_s, "bit_identical_to_default": same,
-            "chunk": chunk, "margin": margin, "fallbacks": stats["fallbacks"], "chunks": stats["chunks"],
-            "lanczos_launches_per_step": stats["lanczos_launches"] / max(1, stats["steps"]),
-            "krylov_m_per_step": stats["iterations"] / max(1, stats["steps"]),
-            "train_rows": int(len(X)), "train_loss_first_last": [hist[0][1], hist[-1][1]],
-            "train_seconds_untimed": t_train}
+    print(f"[bench] controller: {len(X)} rows in {t_rows:.1f} s, trained in {t_train:.1f} s, loss "
+          f"{hist[0][1]:.3f} -> {hist[-1][1]:.4f}", file=sys.stderr, flush=True)
+    res = {"train_rows": int(len(X)), "rows_10site": int(len(X1)), "rows_12site": int(len(X2)),
+           "rows_seconds_untimed": t_rows, "train_seconds_untimed": t_train,
+           "train_loss_first_last": [hist[0][1], hist[-1][1]], "tol": tol, "chunk": chunk, "margin": margin}
+    lat = cluster_2d(3, 4)
+    n, dt = 1000, 0.005
+    opts = hub.make_opts(tol=tol, m_max=30)
+    tot = {k: {"seconds": 0.0, "steps": 0, "fallbacks": 0, "launches": 0, "m": 0.0} for k in
+           ("learned", "default", "synchronous")}
+    same = True
+    for U, mem in controller_groups(4, 1, 13599):
+        B = hub.Basis(lat, U, 6, 6)
+        g = torch.empty(B.dim, dtype=torch.complex128, device="cuda:0")
+        hub.hub_ground_state(B.handle, 0.0, g, hub.make_opts(tol=1e-10, m_max=60), allow_degenerate=True)
+        pulse = (0, mem[0][0], mem[0][1], 1.5, 0.5, 0.0)
+        hub.hub_controller_load(B.handle, params)
+        ref = None
+        for name in ("synchronous", "default", "learned"):
+            if name == "learned":
+                hub.hub_controller_enable(B.handle, True, chunk, margin)
+            else:
+                hub.hub_controller_enable(B.handle, False)
+                hub.hub_set_schedule(B.handle, 0 if name == "synchronous" else 32, 0 if name == "synchronous" else 1)
+            hub.hub_propagate(B.handle, [pulse], 0.0, dt, 100, opts, g.clone(), want_obs=False)  # warm-up
+            v = g.clone()
+            hub.hub_controller_read_stats(B.handle)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, obs, log = hub.hub_propagate(B.handle, [pulse], 0.0, dt, n, opts, v)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            s = hub.hub_controller_read_stats(B.handle)
+            T = tot[name]
+            T["seconds"] += el
+            T["steps"] += n
+            T["fallbacks"] += s["fallbacks"]
+            T["launches"] += s["lanczos_launches"]
+            T["m"] += float(np.sum(log[:, 0, 0]))
+            if ref is None:
+                ref = (v, obs, log)
+            else:
+                same &= bool(torch.equal(v, ref[0])) and bool(np.array_equal(obs, ref[1])) and \
+                    bool(np.array_equal(log, ref[2]))
+        hub.hub_controller_enable(B.handle, False)
+        B.close()
+    for name, T in tot.items():
+        res[name] = {"steps_per_s": T["steps"] / T["seconds"], "mean_krylov_m": T["m"] / T["steps"]}
+        if name != "synchronous":
+            res[name]["lanczos_launches_per_step"] = T["launches"] / T["steps"]
+            res[name]["fallback_rate"] = T["fallbacks"] / T["steps"]
+    res["speedup_learned_vs_default"] = res["learned"]["steps_per_s"] / res["default"]["steps_per_s"]
+    res["speedup_learned_vs_synchronous"] = res["learned"]["steps_per_s"] / res["synchronous"]["steps_per_s"]
+    res["bit_identical_to_synchronous"] = same
+    print(f"[bench] controller (12 sites, held out): learned {res['learned']['steps_per_s']:.0f}, default "
+          f"{res['default']['steps_per_s']:.0f}, synchronous {res['synchronous']['steps_per_s']:.0f} steps/s; "
+          f"fallback rate {res['learned']['fallback_rate']:.3f}; bit-identical {same}", file=sys.stderr, flush=True)
+    return res
 
 
 def synchronous_variant(hub, B, w, v_start, t_start: float, steps: int, v_plain, obs_plain, plain_steps_per_s):
@@ -568,7 +626,8 @@ def hv_variants(hub, B, copy_gbps: float, reps: int = 100) -> dict:
         xs = [torch.randn(nv * N, dtype=dtype, device="cuda:0", generator=g) for _ in range(npairs)]
         ys = [torch.empty_like(xs[0]) for _ in range(npairs)]
         A = [0.5] * nv
-        res = {"bytes_per_apply": pair, "buffers_rotated": npairs}
+        res = {"bytes_per_apply": pair, "buffers_rotated": npairs,
+               "kernels": plan_label(hub, B, hub.HUB_C128 if dtype == torch.complex128 else hub.HUB_C64, nv, False)}
         for mode in ("in_cache", "hbm_rotating"):
             for r in range(10):  # untimed: same access pattern as the timed loop
                 k = 0 if mode == "in_cache" else r % npairs
@@ -599,8 +658,10 @@ def greens_variant(hub) -> dict:
     dim 63,504) from its ground state under the ring pulse; 64 members (c and
     c^dag of both spins at sites 0, 3, 6, 9 from t' = 0.5, 1.0, 1.5, 2.0) in
     the four N -/+ 1 sectors (dim 52,920 each), 400 relative steps of 0.01
-    each.  complex64 and complex128 runs (Krylov tol 1e-8): member-steps/s and
-    the complex64 overlaps' largest deviation from complex128."""
+    each.  complex64 and complex128 runs (Krylov tol 1e-8) on both member
+    steppers (persistent one-launch, per-sector batches): member-steps/s, the
+    complex64 overlaps' largest deviation from complex128 and the largest
+    difference between the steppers."""
     import numpy as np
     import torch
     from synth import workloads
@@ -617,20 +678,66 @@ def greens_variant(hub) -> dict:
     opts = hub.make_opts(tol=1e-8, m_max=w.m_max)
     res = {"members": len(members), "relative_steps": n_rel, "member_dim": int(T[0].dim)}
     outs = {}
-    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
-        psi = g.to(dtype).clone()
-        hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, 8, opts, members[:4],
-                            psi.clone())  # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        o = hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, n_rel, opts, members, psi)
-        el = time.perf_counter() - t0
-        outs[name] = o
-        res[name] = {"seconds": el, "member_steps_per_s": len(members) * n_rel / el}
-    res["max_abs_overlap_err_c64_vs_c128"] = float(np.max(np.abs(outs["c64"] - outs["c128"])))
-    print(f"[bench] greens: c64 {res['c64']['member_steps_per_s']:.0f} member-steps/s, c128 "
-          f"{res['c128']['member_steps_per_s']:.0f}; |dG| {res['max_abs_overlap_err_c64_vs_c128']:.1e}",
-          file=sys.stderr, flush=True)
+    for path, pname in ((1, "persistent_members"), (0, "per_sector")):
+        hub.hub_set_greens_path(B.handle, path)
+        r = res[pname] = {}
+        for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+            psi = g.to(dtype).clone()
+            hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, 8, opts, members[:4],
+                                psi.clone())  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, n_rel, opts, members, psi)
+            el = time.perf_counter() - t0
+            outs[(pname, name)] = o
+            r[name] = {"seconds": el, "member_steps_per_s": len(members) * n_rel / el}
+        r["max_abs_overlap_err_c64_vs_c128"] = float(np.max(np.abs(outs[(pname, "c64")] - outs[(pname, "c128")])))
+        print(f"[bench] greens ({pname}): c64 {r['c64']['member_steps_per_s']:.0f} member-steps/s, c128 "
+              f"{r['c128']['member_steps_per_s']:.0f}; |dG| {r['max_abs_overlap_err_c64_vs_c128']:.1e}",
+              file=sys.stderr, flush=True)
+    hub.hub_set_greens_path(B.handle, -1)
+    res["max_abs_overlap_diff_between_steppers_c128"] = float(
+        np.max(np.abs(outs[("persistent_members", "c128")] - outs[("per_sector", "c128")])))
+    for t in T:
+        t.close()
+    B.close()
+    return res
+
+
+def greens_scaling_variant(hub) -> dict:
+    """Member count against stepper: the 10-site ring's Green's-function
+    members (c and c^dag of both spins at all 10 sites, t' on a grid from
+    0.1) at 256 and 1024 members, 50 relative steps of 0.01, complex64, on
+    the persistent member stepper and on the per-sector batches."""
+    import numpy as np
+    import torch
+    from synth import workloads
+
+    w = workloads()["ring10_greens"]
+    B = hub.Basis(w.lattice, w.U, 5, 5)
+    T = [hub.Basis(w.lattice, w.U, *sec) for sec in ((4, 5), (6, 5), (5, 4), (5, 6))]
+    g = torch.empty(B.dim, dtype=torch.complex64, device="cuda:0")
+    g.copy_(torch.from_numpy(np.random.default_rng(5).normal(size=B.dim) + 0j).to("cuda:0"))
+    g /= torch.linalg.vector_norm(g)
+    opts = hub.make_opts(tol=1e-8, m_max=w.m_max)
+    n_rel = 50
+    res = {"relative_steps": n_rel, "member_dim": int(T[0].dim), "dtype": "c64"}
+    for n_tp in (8, 32):
+        members = [(site, spin, dagger, 10 * (k + 1))
+                   for spin, dagger in ((0, 1), (1, 1), (0, 0), (1, 0)) for site in range(10) for k in range(n_tp)]
+        members = members[:(256 if n_tp == 8 else 1024)]
+        r = res[f"members_{len(members)}"] = {}
+        for path, pname in ((1, "persistent_members"), (0, "per_sector")):
+            hub.hub_set_greens_path(B.handle, path)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, n_rel, opts, members, g.clone())
+            el = time.perf_counter() - t0
+            r[pname] = {"seconds": el, "member_steps_per_s": len(members) * n_rel / el}
+            print(f"[bench] greens {len(members)} members ({pname}): {len(members) * n_rel / el:.0f} member-steps/s",
+                  file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+    hub.hub_set_greens_path(B.handle, -1)
     for t in T:
         t.close()
     B.close()
@@ -676,12 +783,13 @@ def ring14_block_variant(hub, steps: int = 10) -> dict:
         obs128.append(o[:, 0, :])
         del x
     obs128 = np.stack(obs128, axis=1)
-    res["c64_block8"] = {"seconds": el64, "member_steps_per_s": len(pulses) * steps / el64,
+    res["c64_8members"] = {"kernels": plan_label(hub, B, hub.HUB_C64, len(pulses), True),
+                         "seconds": el64, "member_steps_per_s": len(pulses) * steps / el64,
                          "mean_krylov_m": float(np.mean(log64[:, :, 0]))}
     res["c128_single"] = {"seconds": el128, "member_steps_per_s": len(pulses) * steps / el128}
     res["max_abs_docc_err"] = float(np.max(np.abs(obs64[:, :, 3] - obs128[:, :, 3])))
     res["max_abs_energy_per_site_err"] = float(np.max(np.abs(obs64[:, :, 2] - obs128[:, :, 2])))
-    print(f"[bench] ring14 block: c64x8 {res['c64_block8']['member_steps_per_s']:.1f} member-steps/s, c128 "
+    print(f"[bench] ring14: c64 8 members {res['c64_8members']['member_steps_per_s']:.1f} member-steps/s, c128 "
           f"{res['c128_single']['member_steps_per_s']:.1f}; |dd| {res['max_abs_docc_err']:.1e}",
           file=sys.stderr, flush=True)
     B.close()
@@ -744,7 +852,8 @@ def main() -> int:
     ap.add_argument("--summarize-stats", nargs=2, metavar=("TRACE_DIR", "OUT"))
     ap.add_argument("--command", default="", help="profiling command recorded in a summary")
     ap.add_argument("--note", default="", help="comment lines (separated by |) recorded in a summary")
-    ap.add_argument("--variant", choices=("greens_ring10", "ring14_block", "ring8", "hv12"),
+    ap.add_argument("--variant", choices=("greens_ring10", "greens_scaling", "ring14_block", "ring8", "hv12",
+                                          "controller"),
                     help="run only this variant and print its result (for profiling it alone)")
     args = ap.parse_args()
 
@@ -777,7 +886,9 @@ def main() -> int:
             print(json.dumps({"hv_12site": hv_variants(hub, B, copy_bandwidth()["gbps"])}), flush=True)
             B.close()
             return 0
-        run = {"greens_ring10": greens_variant, "ring14_block": ring14_block_variant, "ring8": ring8_variant}
+        run = {"greens_ring10": greens_variant, "greens_scaling": greens_scaling_variant,
+               "ring14_block": ring14_block_variant, "ring8": ring8_variant,
+               "controller": controller_c5_variant}
         print(json.dumps({args.variant: run[args.variant](hub)}), flush=True)
         return 0
 
@@ -880,7 +991,7 @@ def main() -> int:
         var.update(batched_variants(hub, B, v_start, t_start, w, args.steps))
         var["synchronous_schedule"] = synchronous_variant(hub, B, w, v_start, t_start, args.steps, v, obs,
                                                           steps_per_s)
-        var["controller"] = controller_variant(hub, B, w, v0, v_start, t_start, args.steps, v, obs, steps_per_s)
+        var["controller"] = controller_c5_variant(hub)
         var["cfet4"] = cfet4_variant(hub, B, w, v_start, t_start, args.steps, v, elapsed)
         var["large_tiles"] = large_tile_variant(hub)
         var["greens_ring10"] = greens_variant(hub)

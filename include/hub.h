@@ -251,13 +251,18 @@ hub_status hub_dot(hub_basis basis, hub_prec prec, int32_t nvec, const void *x, 
  *     o_k(s) = < op_k psi(t'_k + s dt) | phi_k(t'_k + s dt) >,  s = 0..n_rel,
  * so that G^<(t', t'+s) = i o(s) for c and G^>(t'+s, t') = -i o(s) for c^dag.
  * targets: host array of n_targets basis handles covering the members'
- * sectors (matched by particle numbers); members sharing a sector are
- * propagated together.  Each step, psi and the members of every sector are
- * propagated side by side (own streams and host threads, after the work on
- * `stream`), so the handles must be distinct and not in use elsewhere during
- * the call.  psi_inout: device vector of `basis` in precision
- * `prec`, advanced in place to t_start + (max start_step + n_rel) dt.
- * overlaps: host [n_members][n_rel + 1][2].  Synchronises `stream`. */
+ * sectors (matched by particle numbers).  psi is propagated first over the
+ * whole grid, its state after every step kept on the device; the members then
+ * run on one of two steppers (hub_set_greens_path): per sector, members
+ * sharing a sector are propagated together as the vectors of hub_propagate
+ * (the sectors side by side, own streams and host threads, after the work on
+ * `stream`, so the handles must be distinct and not in use elsewhere during
+ * the call); or the persistent member stepper, one launch in which every
+ * member runs all its steps in a workgroup of its own.  psi_inout: device
+ * vector of `basis` in precision `prec`, advanced in place to t_start + (max
+ * start_step + n_rel) dt.  overlaps: host [n_members][n_rel + 1][2].
+ * HUB_E_NOT_CONVERGED when a member's step hits m_max (on the persistent
+ * stepper that member's later overlaps are NaN).  Synchronises `stream`. */
 typedef struct {
   int32_t site, spin, dagger, start_step;
 } hub_greens_member;
@@ -267,6 +272,22 @@ hub_status hub_greens_diag(hub_basis basis, int32_t n_targets, const hub_basis *
                            const hub_krylov_opts *opts, hub_prec prec, int32_t n_members,
                            const hub_greens_member *members, void *psi_inout, double *overlaps,
                            void *stream);
+
+/* Stepper of hub_greens_diag's members (set on the source basis, not in the
+ * paper: how the library schedules the same steps).  path 0: per target
+ * sector, the members as a batch of hub_propagate vectors (one launch per
+ * Lanczos pass); path 1: the persistent member stepper, one launch for all
+ * members, each member a workgroup that runs its Lanczos iterations
+ * (three-term recurrence, Alg. 6's estimate), its combines and its overlaps
+ * for every step, staging tile rows and tile columns in LDS; it needs
+ * opts.reorth = 0, opts.substeps = 1 and target sectors with at most 32
+ * grouped hop slots per string and a tile row and column of at most 144 KiB,
+ * else hub_greens_diag returns HUB_E_INVALID.  path -1 (default): 1 where it
+ * applies, every target sector has at most 2^18 states and there are at
+ * least 4 members per compute unit (one workgroup per member runs well below
+ * a compute unit's share of the bandwidth), else 0.  Both give the same
+ * overlaps up to rounding.  Errors: HUB_E_INVALID. */
+hub_status hub_set_greens_path(hub_basis basis, int32_t path);
 
 /* Broadened spectral functions, Eq. (A_noneq_broad), from the overlaps of
  * hub_greens_diag on the stepper grid s_k = k dt, k < n_s:
@@ -292,11 +313,12 @@ const char *hub_last_error(void);
 /* ------------------------------------------------------------------------ */
 /* Learned Krylov controller.  Not in the paper: a schedule optimisation on
  * top of Alg. 6 that never changes results.  A small FP32 MLP
- *     x (8) -> 64 -> GELU -> 64 -> GELU -> 2,   GELU(z) = z (1 + erf(z/sqrt2)) / 2
+ *     x (8) -> 64 -> GELU -> 64 -> GELU -> 1,   GELU(z) = z (1 + erf(z/sqrt2)) / 2
  * predicts, for each step of a chunk of upcoming midpoint steps, o[0] =
- * log2 of the Krylov dimension m the adaptive step will use and o[1] = log2
- * of the substep count (trained but not used by the scheduler: in this
- * library one substep is always the cheapest choice).  Features of the row
+ * log2 of the Krylov dimension m the adaptive step will use.  (Splitting a
+ * step into substeps would change the results, not only the schedule, and
+ * at the steps these workloads take, tau |H|_inf ~ 1/2, one Krylov solve is
+ * always cheaper, so the network predicts no substep count.)  Features of the row
  * for step n, whose history ends at step h <= n - 1 (the last step finished
  * when the chunk was planned):
  *     x[0] = A(t_mid_n)            x[1] = A'(t_mid_n) / 10
@@ -306,7 +328,7 @@ const char *hub_last_error(void);
  *               step h-k, floored at 1e-40; log10(tol)/10 before step 0)
  *     x[7] = m_h / 10              (m_hint / 10, or 0.8, before step 0)
  * Parameters (HUB_MLP_NPARAM floats, row-major, output unit first):
- *     W1[64][8], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
+ *     W1[64][8], b1[64], W2[64][64], b2[64], W3[1][64], b3[1].
  * When enabled on a handle, hub_propagate plans `chunk` steps at a time: one
  * MLP launch predicts m for each, each step gets ceil(2^o[0]) + margin + 1
  * Lanczos launches (capped by m_max + 1) without host synchronisation, and
@@ -316,11 +338,11 @@ const char *hub_last_error(void);
  * Results are therefore bit-identical to the adaptive schedule. */
 #define HUB_MLP_IN 8
 #define HUB_MLP_HID 64
-#define HUB_MLP_OUT 2
+#define HUB_MLP_OUT 1
 #define HUB_MLP_NPARAM (HUB_MLP_HID * HUB_MLP_IN + HUB_MLP_HID + HUB_MLP_HID * HUB_MLP_HID + HUB_MLP_HID + \
                         HUB_MLP_OUT * HUB_MLP_HID + HUB_MLP_OUT)
 
-/* out[r][2] = MLP(feats[r][8]) for r < n_rows.  params, feats, out: device
+/* out[r][0] = MLP(feats[r][8]) for r < n_rows.  params, feats, out: device
  * pointers on `device`.  Asynchronous on stream. */
 hub_status hub_mlp_forward(int32_t device, const float *params, int32_t n_rows, const float *feats,
                            float *out, void *stream);
@@ -332,7 +354,7 @@ int64_t hub_mlp_workspace_bytes(int32_t n_rows);
  * count t >= 1, learning rate lr) on the mean squared error
  *     L = (1/n_rows) sum_r sum_o (out[r][o] - targets[r][o])^2.
  * params, adam_m, adam_v (HUB_MLP_NPARAM floats each, updated in place),
- * feats [n_rows][8], targets [n_rows][2], loss (1 float: L before the
+ * feats [n_rows][8], targets [n_rows][1], loss (1 float: L before the
  * update) and workspace (hub_mlp_workspace_bytes) are device pointers.
  * Gradient partial sums are reduced in a fixed order (deterministic).
  * Asynchronous on stream. */
@@ -343,7 +365,7 @@ hub_status hub_mlp_train_step(int32_t device, float *params, float *adam_m, floa
 /* Training rows from a finished run of one vector (host arrays): for each
  * step n in [0, n_steps), feats[n] as above with history end
  * h = n - 1 - (n mod chunk) (the planning point of n's chunk when chunks
- * start at multiples of `chunk`), and targets[n] = (log2 m_n, 0).  log is
+ * start at multiples of `chunk`), and targets[n] = log2 m_n.  log is
  * that vector's hub_step_info of the run (n_steps entries, stride 1). */
 hub_status hub_controller_features(const hub_pulse *pulse, double t_start, double dt, int32_t n_steps,
                                    double norm_inf, const hub_krylov_opts *opts, const hub_step_info *log,

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-The controller is a plain multilayer perceptron 8 -> 64 -> 64 -> 2 with the
+The controller is a plain multilayer perceptron 8 -> 64 -> 64 -> 1 with the
 exact (erf) GELU on both hidden layers and a linear output, trained by Adam
 on the mean squared error.  Written from the textbook definitions:
 
@@ -13,7 +13,8 @@ on the mean squared error.  Written from the textbook definitions:
         theta <- theta - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
 
 Parameters are one flat vector: W1[64][8], b1[64], W2[64][64], b2[64],
-W3[2][64], b3[2] (row-major, output unit first).
+W3[1][64], b3[1] (row-major, output unit first).  The output is log2 of the
+Krylov dimension of a step.
 
 Features of a step n whose history ends at step h (the last finished step
 when n was planned): the vector potential at the step's midpoint and its time
@@ -28,7 +29,7 @@ import math
 
 import numpy as np
 
-N_IN, N_HID, N_OUT = 8, 64, 2
+N_IN, N_HID, N_OUT = 8, 64, 1
 SHAPES = [("W1", (N_HID, N_IN)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
           ("W3", (N_OUT, N_HID)), ("b3", (N_OUT,))]
 N_PARAM = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -117,7 +118,7 @@ def pulse_dA(pulse, t: float) -> float:
 
 def features(pulse, t_start: float, dt: float, norm_inf: float, tol: float, m_hint: int, substeps: int,
              m_used, err_est, chunk: int):
-    """Training rows (X [n, 8], Y [n, 2]) of one vector's finished run."""
+    """Training rows (X [n, 8], Y [n, 1]) of one vector's finished run."""
     from .hamiltonian import pulse_A
     n_steps = len(m_used)
     X = np.zeros((n_steps, N_IN))

@@ -53,10 +53,10 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_mlp_forward", "hub_mlp_workspace_bytes", "hub_mlp_train_step", "hub_controller_features",
            "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats",
            "hub_set_apply_path", "hub_spectral", "hub_set_schedule", "hub_observables_noalloc",
-           "hub_tune", "hub_set_tuning", "hub_get_plan")
+           "hub_tune", "hub_set_tuning", "hub_get_plan", "hub_set_greens_path")
 
 # Controller MLP sizes (HUB_MLP_* in hub.h).
-MLP_IN, MLP_HID, MLP_OUT = 8, 64, 2
+MLP_IN, MLP_HID, MLP_OUT = 8, 64, 1
 MLP_NPARAM = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
 
 
@@ -153,6 +153,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_controller_enable": ([vp, i32, i32, i32], i32),
         "hub_controller_read_stats": ([vp, P(hub_controller_stats)], i32),
         "hub_set_apply_path": ([vp, i32], i32),
+        "hub_set_greens_path": ([vp, i32], i32),
         "hub_set_schedule": ([vp, i32, i32], i32),
         "hub_tune": ([vp, i32, i32, P(hub_tuning), vp], i32),
         "hub_set_tuning": ([vp, i32, P(hub_tuning)], i32),
@@ -413,7 +414,7 @@ def _device_of(t) -> int:
 
 
 def hub_mlp_forward(params, feats, out, stream=None) -> None:
-    """out[r, :2] = MLP(feats[r, :8]); float32 device tensors."""
+    """out[r, 0] = MLP(feats[r, :8]); float32 device tensors."""
     _check(load_library().hub_mlp_forward(_device_of(params), _dptr(params), int(feats.shape[0]), _dptr(feats),
                                           _dptr(out), _stream_ptr(stream)))
 
@@ -480,6 +481,12 @@ def hub_spectral(overlaps, lesser, dt: float, eps: float, nu, out, stream=None) 
 def hub_set_apply_path(h, path: int) -> None:
     """-1 automatic, 0 one-pass, 1 two-pass H*v kernels for single vectors."""
     _check(load_library().hub_set_apply_path(ctypes.c_void_p(h), int(path)))
+
+
+def hub_set_greens_path(h, path: int) -> None:
+    """hub_greens_diag's member stepper: -1 automatic, 0 per-sector batches,
+    1 the persistent one-launch member stepper."""
+    _check(load_library().hub_set_greens_path(ctypes.c_void_p(h), int(path)))
 
 
 def hub_set_schedule(h, chunk: int, margin: int = 1) -> None:

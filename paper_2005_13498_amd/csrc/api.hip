@@ -25,6 +25,7 @@
 #include "basis.h"
 #include "host_eig.h"
 #include "kernels.h"
+#include "members.h"
 #include "mlp.h"
 
 using hub::CombineLog;
@@ -137,6 +138,8 @@ struct hub_basis_s {
   int apply_group[2] = {-1, -1};
   int prop_group[2] = {-1, -1};
   int force_group = 0;
+  // Green's functions: -1 automatic, 0 per-sector groups, 1 persistent members
+  int greens_path = -1;
   // profiling of the apply kernel
   bool prof = false;
   int prof_period = 1;
@@ -1651,6 +1654,157 @@ hub_status hub_dot(hub_basis h, hub_prec prec, int32_t nvec, const void* x, cons
   return HUB_OK;
 }
 
+namespace {
+
+// LDS staging of the persistent member stepper; the largest target sector and
+// the fewest members (per compute unit) for which it is the automatic choice:
+// one workgroup per member runs far below a compute unit's share of the
+// bandwidth, so it pays only once there are several members per unit, and
+// larger sectors fill the GPU one apply at a time.
+constexpr size_t kMembersLds = 144 << 10;
+constexpr int64_t kMembersAutoDim = 1 << 18;
+constexpr int kMembersAutoPerCU = 4;
+
+// Members of one target sector in hub_greens_diag.
+struct GreensSector {
+  hub_basis T = nullptr;
+  std::vector<int> mem;  // member indices, ordered by start step
+  void* buf = nullptr;
+  int32_t* maps = nullptr;  // [member][map_len]
+  int8_t* sgns = nullptr;
+  int map_len = 0, ogrid = 0;
+  bool down = false;
+  double* part = nullptr;
+  double* tot = nullptr;
+  hipStream_t stream = nullptr;
+  hub_status s = HUB_OK;
+  std::string err;
+};
+
+// Steps 2-4 of hub_greens_diag on the persistent member stepper: every
+// member's Krylov slots and row-pass buffer, c_k psi(t'_k) into its slot 0,
+// one launch for all members and steps, overlaps straight into the ABI
+// layout [member][n_rel + 1][2].
+hub_status greens_members(hub_basis h, const std::vector<GreensSector>& secs, const hub_greens_member* members,
+                          int n_members, const void* traj, int n_total, int n_rel, double t_start, double dt,
+                          const hub_pulse& pulse, const hub_krylov_opts& o, hub_prec prec, double* overlaps,
+                          hipStream_t st) {
+  const int pi = prec == HUB_C128 ? 0 : 1;
+  const size_t es = elem_bytes(prec);
+  const int m_max = o.m_max;
+  std::vector<void*> bufs;
+  auto done = [&](hub_status r) {
+    for (void* p : bufs) (void)hipFree(p);
+    return r;
+  };
+  // a failed HIP call frees the buffers before it returns
+#define MEMBERS_HIP(call)                                                                                  \
+  do {                                                                                                     \
+    const hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess)                                                                                  \
+      return done(fail(e_ == hipErrorOutOfMemory ? HUB_E_NOMEM : HUB_E_DEVICE,                             \
+                       std::string(#call) + ": " + hipGetErrorString(e_)));                                \
+  } while (0)
+  auto alloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes == 0 ? 16 : bytes) != hipSuccess) return nullptr;
+    bufs.push_back(p);
+    return p;
+  };
+  std::vector<hub::MemberSector> hs(secs.size());
+  std::vector<hub::MemberDesc> hd(n_members);
+  std::vector<std::vector<double>> ctabs;
+  ctabs.reserve(secs.size());
+  size_t lds = 0;
+  double* out = static_cast<double*>(alloc(static_cast<size_t>(n_members) * (n_rel + 1) * 2 * sizeof(double)));
+  int32_t* stat = static_cast<int32_t*>(alloc(static_cast<size_t>(n_members) * std::max(n_rel, 1) * 2 * sizeof(int32_t)));
+  if (!out || !stat) return done(fail(HUB_E_NOMEM, "member outputs"));
+  for (size_t g = 0; g < secs.size(); ++g) {
+    const GreensSector& S = secs[g];
+    const DevBasis& TD = S.T->D;
+    hub::MemberSector& M = hs[g];
+    M.dim_up = TD.dim_up;
+    M.dim_dn = TD.dim_dn;
+    M.gs_up = TD.up_gslots;
+    M.gs_dn = TD.dn_gslots;
+    M.up_bits = TD.up_bits;
+    M.dn_bits = TD.dn_bits;
+    M.eps_up = TD.eps_up;
+    M.eps_dn = TD.eps_dn;
+    M.up_tab = TD.up_tabg;
+    M.dn_tab = TD.dn_tabg;
+    std::memcpy(M.up_gclass, TD.up_gclass, sizeof(M.up_gclass));
+    std::memcpy(M.dn_gclass, TD.dn_gclass, sizeof(M.dn_gclass));
+    M.U = TD.U;
+    M.norm_inf = S.T->B.norm_inf;
+    M.nc = TD.nc;
+    M.row_block = static_cast<int>(std::min<size_t>(TD.dim_up, kMembersLds / ((TD.dim_dn + 1) * es)));
+    M.col_block = static_cast<int>(std::min<size_t>(TD.dim_dn, kMembersLds / ((TD.dim_up + 1) * es)));
+    lds = std::max({lds, static_cast<size_t>(M.row_block) * (TD.dim_dn + 1) * es,
+                    static_cast<size_t>(M.col_block) * (TD.dim_up + 1) * es});
+    ctabs.emplace_back(static_cast<size_t>(std::max(n_total, 1)) * 2 * TD.nc, 0.0);  // alive until the sync
+    std::vector<double>& ct = ctabs.back();
+    for (int n = 0; n < n_total; ++n)
+      coef_for(S.T->B, pulse_value(pulse, t_start + n * dt + 0.5 * dt), ct.data() + static_cast<size_t>(n) * 2 * TD.nc);
+    double* dct = static_cast<double*>(alloc(ct.size() * sizeof(double)));
+    if (!dct) return done(fail(HUB_E_NOMEM, "coefficient table"));
+    MEMBERS_HIP(hipMemcpyAsync(dct, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    M.coef_tab = dct;
+    // Krylov slots (m_max + 1 vectors) and the row-pass buffer of each member
+    const size_t vb = static_cast<size_t>(TD.dim) * es;
+    const int nm = static_cast<int>(S.mem.size());
+    char* mb = static_cast<char*>(alloc(static_cast<size_t>(nm) * (m_max + 2) * vb));
+    if (!mb) return done(fail(HUB_E_NOMEM, "member Krylov slots"));
+    for (int q = 0; q < nm; ++q) {
+      const int k = S.mem[q];
+      hub::MemberDesc& D = hd[k];
+      D.sector = static_cast<int>(g);
+      D.start = members[k].start_step;
+      D.slots = mb + static_cast<size_t>(q) * (m_max + 2) * vb;
+      D.z = static_cast<char*>(D.slots) + static_cast<size_t>(m_max + 1) * vb;
+      D.map = S.maps + static_cast<size_t>(q) * S.map_len;
+      D.sgn = S.sgns + static_cast<size_t>(q) * S.map_len;
+      D.down = S.down ? 1 : 0;
+      D.out = out + static_cast<size_t>(k) * (n_rel + 1) * 2;
+      D.status = stat + static_cast<size_t>(k) * std::max(n_rel, 1) * 2;
+      D.m_used = D.status + std::max(n_rel, 1);
+      MEMBERS_HIP(hub::launch_cop(pi, TD.dim, TD.dim_dn, h->D.dim_dn, h->D.dim, 1, S.down, D.map, D.sgn,
+                              static_cast<const char*>(traj) + static_cast<size_t>(D.start) * h->D.dim * es, D.slots,
+                              st));
+    }
+  }
+  auto* dsec = static_cast<hub::MemberSector*>(alloc(hs.size() * sizeof(hub::MemberSector)));
+  auto* dmem = static_cast<hub::MemberDesc*>(alloc(hd.size() * sizeof(hub::MemberDesc)));
+  if (!dsec || !dmem) return done(fail(HUB_E_NOMEM, "member descriptors"));
+  MEMBERS_HIP(hipMemcpyAsync(dsec, hs.data(), hs.size() * sizeof(hub::MemberSector), hipMemcpyHostToDevice, st));
+  MEMBERS_HIP(hipMemcpyAsync(dmem, hd.data(), hd.size() * sizeof(hub::MemberDesc), hipMemcpyHostToDevice, st));
+  hub::MembersArgs A{};
+  A.sectors = dsec;
+  A.members = dmem;
+  A.n_rel = n_rel;
+  A.m_max = m_max;
+  A.tol = o.tol;
+  A.tau = dt;
+  A.traj = traj;
+  A.traj_stride = h->D.dim;
+  A.dim_dn_s = h->D.dim_dn;
+  const hipError_t e = hub::launch_members(pi, n_members, A, lds, st);
+  if (e != hipSuccess) return done(fail(HUB_E_DEVICE, std::string("member stepper: ") + hipGetErrorString(e)));
+  std::vector<int32_t> hstat(static_cast<size_t>(n_members) * std::max(n_rel, 1) * 2);
+  MEMBERS_HIP(hipMemcpyAsync(overlaps, out, static_cast<size_t>(n_members) * (n_rel + 1) * 2 * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  MEMBERS_HIP(hipMemcpyAsync(hstat.data(), stat, hstat.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MEMBERS_HIP(hipStreamSynchronize(st));
+  bool maxed = false;
+  for (int k = 0; k < n_members; ++k)
+    for (int r = 0; r < n_rel; ++r) maxed |= hstat[static_cast<size_t>(k) * std::max(n_rel, 1) * 2 + r] == 3;
+  if (maxed) return done(fail(HUB_E_NOT_CONVERGED, "a member's Krylov step reached m_max before the tolerance"));
+  return done(HUB_OK);
+#undef MEMBERS_HIP
+}
+
+}  // namespace
+
 hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targets, const hub_pulse* pulse,
                            double t_start, double dt, int32_t n_rel, const hub_krylov_opts* opts, hub_prec prec,
                            int32_t n_members, const hub_greens_member* members, void* psi_inout, double* overlaps,
@@ -1688,24 +1842,31 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
     std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return members[a].start_step < members[b].start_step; });
   const int n_total = max_start + n_rel;
   const int64_t dim_s = h->D.dim;
+  // The persistent member stepper (one launch, a workgroup per member) needs
+  // the three-term recurrence with one solve per step and the grouped hop
+  // tables of every target sector, with a tile row and a tile column in LDS.
+  bool members_fit = opts->reorth == 0 && opts->substeps == 1;
+  bool members_small = true;
+  for (int k = 0; k < n_members && members_fit; ++k) {
+    const hub::Basis& TB = targets[tb[k]]->B;
+    const DevBasis& TD = targets[tb[k]]->D;
+    members_fit = (TD.dn_gslots > 0 || TB.dn.max_hops == 0) && (TD.up_gslots > 0 || TB.up.max_hops == 0) &&
+                  (TD.dim_dn + 1) * es <= kMembersLds && (TD.dim_up + 1) * es <= kMembersLds;
+    members_small &= TD.dim <= kMembersAutoDim;
+  }
+  if (h->greens_path == 1 && !members_fit)
+    return fail(HUB_E_INVALID, "the persistent member stepper needs reorth 0, substeps 1 and grouped hop tables");
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || n_cu < 1)
+    n_cu = 256;
+  const bool members_many = n_members >= kMembersAutoPerCU * n_cu;
+  const bool use_members =
+      h->greens_path == 1 || (h->greens_path == -1 && members_fit && members_small && members_many);
   // Device buffers: psi at every step (the trajectory), the members of every
   // target sector in the ABI layout (ordered by start step), their operator
   // maps packed per sector [member][map_len], overlap partials per sector
   // [n_rel + 1][members][grid][2] and their totals [n_rel + 1][members][2].
-  struct Sector {
-    hub_basis T = nullptr;
-    std::vector<int> mem;
-    void* buf = nullptr;
-    int32_t* maps = nullptr;
-    int8_t* sgns = nullptr;
-    int map_len = 0, ogrid = 0;
-    bool down = false;
-    double* part = nullptr;
-    double* tot = nullptr;
-    hipStream_t stream = nullptr;
-    hub_status s = HUB_OK;
-    std::string err;
-  };
+  using Sector = GreensSector;
   std::vector<Sector> secs;
   void* traj = nullptr;
   auto cleanup = [&](hub_status r) {
@@ -1749,7 +1910,7 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
       maps.insert(maps.end(), M.map.begin(), M.map.end());
       sg.insert(sg.end(), M.sgn.begin(), M.sgn.end());
     }
-    if (hipMalloc(&S.buf, static_cast<size_t>(nm) * dt_ * es) != hipSuccess ||
+    if ((!use_members && hipMalloc(&S.buf, static_cast<size_t>(nm) * dt_ * es) != hipSuccess) ||
         hipMalloc(reinterpret_cast<void**>(&S.maps), maps.size() * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&S.sgns), sg.size()) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&S.part),
@@ -1774,6 +1935,11 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
     if ((s = run_all(h, prec, 1, psi_inout, n_total, am, nullptr, t_start, dt, o1, nullptr, nullptr, st, nullptr,
                      nullptr, &hk)) != HUB_OK)
       return cleanup(s);
+  }
+  if (use_members) {
+    s = greens_members(h, secs, members, n_members, traj, n_total, n_rel, t_start, dt, *pulse, o1, prec, overlaps,
+                       st);
+    return cleanup(s);
   }
   // 2. every member from c_k psi(t'_k); overlaps after s = 0..n_rel steps,
   // gathered from the trajectory, partials at [s][member][grid][2]
@@ -2130,7 +2296,6 @@ hub_status hub_controller_features(const hub_pulse* pulse, double t_start, doubl
     ctrl_features(pulse_value(*pulse, tm), pulse_deriv(*pulse, tm), tau * norm_inf, eh, m_last, opts->tol,
                   opts->m_hint, feats + static_cast<size_t>(n) * HUB_MLP_IN);
     targets[static_cast<size_t>(n) * HUB_MLP_OUT] = static_cast<float>(std::log2(std::max(1, log[n].m_used)));
-    targets[static_cast<size_t>(n) * HUB_MLP_OUT + 1] = 0.0f;
   }
   return HUB_OK;
 }
@@ -2376,6 +2541,13 @@ hub_status hub_set_apply_path(hub_basis h, int32_t path) {
   if (path < -1 || path > 1) return fail(HUB_E_INVALID, "path must be -1, 0 or 1");
   h->D.two_pass = path;
   h->D.block_path = path == 0 ? 0 : -1;
+  return HUB_OK;
+}
+
+hub_status hub_set_greens_path(hub_basis h, int32_t path) {
+  if (!h) return fail(HUB_E_INVALID, "null basis handle");
+  if (path < -1 || path > 1) return fail(HUB_E_INVALID, "path must be -1, 0 or 1");
+  h->greens_path = path;
   return HUB_OK;
 }
 

@@ -189,29 +189,28 @@ __global__ void k_step_log(const VecState* st, StepCtl* ctl, CombineLog* log, do
 }
 
 // Column sums (op 0) or maxima (op 1) of a [nrows][ncols] partial array,
-// one workgroup, fixed order.
+// one workgroup per column, fixed order.
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* partials, int nrows, int ncols, double* out,
                                                      int op) {
   __shared__ double red[kWaves];
-  for (int t = 0; t < ncols; ++t) {
-    double s = 0.0;  // the maxima are of non-negative partials
-    for (int b = threadIdx.x; b < nrows; b += blockDim.x) {
-      const double x = partials[(size_t)b * ncols + t];
-      s = op ? fmax(s, x) : s + x;
+  const int t = blockIdx.x;
+  double s = 0.0;  // the maxima are of non-negative partials
+  for (int b = threadIdx.x; b < nrows; b += blockDim.x) {
+    const double x = partials[(size_t)b * ncols + t];
+    s = op ? fmax(s, x) : s + x;
+  }
+  if (op) {
+    s = wave_max(s);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = 0.0;
+      for (int k = 0; k < kWaves; ++k) m = fmax(m, red[k]);
+      out[t] = m;
     }
-    if (op) {
-      s = wave_max(s);
-      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-      __syncthreads();
-      if (lane == 0) red[w] = s;
-      __syncthreads();
-      double r = 0.0;
-      for (int k = 0; k < kWaves; ++k) r = fmax(r, red[k]);
-      s = r;
-      __syncthreads();
-    } else {
-      s = block_sum(s, red);
-    }
+  } else {
+    s = block_sum(s, red);
     if (threadIdx.x == 0) out[t] = s;
   }
 }
@@ -478,21 +477,44 @@ __global__ __launch_bounds__(kBlock) void k_spectral(int n_s, const double2* __r
 }
 
 // ------------------------------- BLAS-1 ------------------------------------
+// <v_k, w> partials for k < kv: workgroup column blockIdx.y takes the chunk
+// of (up to) 8 vectors k0 = 8 blockIdx.y.., each in registers; partials
+// [gridDim.x][2 kv].
 __global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, const double2* const* vecs, int kv,
                                                      const double2* w, double* partials) {
-  __shared__ double red[kWaves * 2 * 64];
-  double acc[2 * 64];
-  const int K = min(kv, 64);
-  for (int k = 0; k < 2 * K; ++k) acc[k] = 0.0;
+  __shared__ double red[kWaves * 16];
+  const int k0 = blockIdx.y * 8;
+  const int K = min(8, kv - k0);
+  const double2* vp[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) vp[k] = k < K ? vecs[k0 + k] : nullptr;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     const double2 b = w[i];
-    for (int k = 0; k < K; ++k) {
-      const double2 a = vecs[k][i];
-      acc[2 * k] += a.x * b.x + a.y * b.y;  // conj(a) * b
-      acc[2 * k + 1] += a.x * b.y - a.y * b.x;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k < K) {
+        const double2 a = vp[k][i];
+        acc[2 * k] += a.x * b.x + a.y * b.y;  // conj(a) * b
+        acc[2 * k + 1] += a.x * b.y - a.y * b.x;
+      }
     }
   }
-  block_partials<1>(acc, 2 * K, red, partials + (size_t)blockIdx.x * 2 * K);
+  // workgroup sums (fixed order), 2 K values for this chunk
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0) red[wv * 16 + q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * K) {
+    double t = 0.0;
+    for (int k = 0; k < kWaves; ++k) t += red[k * 16 + threadIdx.x];
+    partials[(size_t)blockIdx.x * 2 * kv + 2 * k0 + threadIdx.x] = t;
+  }
 }
 
 __global__ void k_multiaxpy(int64_t n, const double2* const* vecs, int kv, const double2* coef, double2* w) {
@@ -833,7 +855,8 @@ hipError_t launch_finalize_obs(int nv, const double* partials, int nrows, int nq
 }
 
 hipError_t launch_finalize(const double* partials, int nrows, int ncols, double* out, int op, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nrows, ncols, out, op);
+  if (ncols < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(ncols), dim3(kBlock), 0, s, partials, nrows, ncols, out, op);
   return hipGetLastError();
 }
 
@@ -893,7 +916,7 @@ hipError_t launch_multidot(int64_t n, const double2* const* vecs, int k, const d
                            double* partials, hipStream_t s) {
   if (k > 64) return hipErrorInvalidValue;
   const int grid = elem_grid(n);
-  hipLaunchKernelGGL(k_multidot, dim3(grid), dim3(kBlock), 0, s, n, vecs, k, w, partials);
+  hipLaunchKernelGGL(k_multidot, dim3(grid, (k + 7) / 8), dim3(kBlock), 0, s, n, vecs, k, w, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize(partials, grid, 2 * k, reinterpret_cast<double*>(out), 0, s);

@@ -1,0 +1,59 @@
+// Persistent member stepper of the Green's-function runs (members.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace hub {
+
+// Hop tables of one target sector (device pointers of its basis): the
+// grouped tables (class ranges of whole groups of four slots) and the class
+// of every group.
+struct MemberSector {
+  int dim_up, dim_dn, gs_up, gs_dn;  // grouped slots per up / down string (multiples of 4, <= 32)
+  const uint32_t* up_bits;
+  const uint32_t* dn_bits;
+  const double* eps_up;  // null without on-site energies
+  const double* eps_dn;
+  const uint16_t* up_tab;  // [dim_up][gs_up]
+  const uint16_t* dn_tab;  // [dim_dn][gs_dn]
+  uint8_t up_gclass[8], dn_gclass[8];
+  double U, norm_inf;
+  int nc;                  // hop classes
+  const double* coef_tab;  // [n_total][2 nc]: coefficient of every class at each global step's midpoint
+  int row_block, col_block;  // tile rows / tile columns staged in LDS at a time
+};
+
+// One member: its sector, first global step, Krylov slots ((m_max + 1)
+// vectors of the sector's dimension; slot 0 holds the member's state on entry
+// and exit), one scratch vector, its operator map into the source sector and
+// its outputs.
+struct MemberDesc {
+  int sector, start;
+  void* slots;
+  void* z;
+  const int32_t* map;  // [dim of the operated spin] source rank or -1
+  const int8_t* sgn;
+  int down;
+  double* out;     // [n_rel + 1][2] overlaps
+  int32_t* status;  // [n_rel] 1 converged, 2 invariant subspace, 3 m_max (the member stops there)
+  int32_t* m_used;  // [n_rel]
+};
+
+struct MembersArgs {
+  const MemberSector* sectors;  // device
+  const MemberDesc* members;    // device [n_members]
+  int n_rel, m_max;
+  double tol, tau;
+  const void* traj;     // device: the source-sector state before the first and after every step
+  int64_t traj_stride;  // elements between two recorded states
+  int dim_dn_s;         // source sector's dim_dn
+};
+
+// One workgroup per member (1024 threads, `lds` bytes of staging).
+hipError_t launch_members(int prec, int n_members, const MembersArgs& a, size_t lds, hipStream_t s);
+
+}  // namespace hub

@@ -83,7 +83,9 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(const float* __restri
   for (int r = wave; r < n_rows; r += nw) {
     float z1, h1, z2, h2, o[kOut];
     forward_row(S, feats + (size_t)r * kIn, z1, h1, z2, h2, o);
-    if (lane < kOut) out[(size_t)r * kOut + lane] = lane == 0 ? o[0] : o[1];
+#pragma unroll
+    for (int q = 0; q < kOut; ++q)
+      if (lane == q) out[(size_t)r * kOut + q] = o[q];
   }
 }
 
@@ -154,7 +156,9 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_grad(const float* __restrict_
   G[oB2 + lane] = gb2;
 #pragma unroll
   for (int q = 0; q < kOut; ++q) G[oW3 + q * kHid + lane] = gw3[q];
-  if (lane < kOut) G[oB3 + lane] = lane == 0 ? gb3[0] : gb3[1];  // equal on every lane
+#pragma unroll
+  for (int q = 0; q < kOut; ++q)
+    if (lane == q) G[oB3 + q] = gb3[q];  // equal on every lane
   if (lane == 0) G[kP] = loss;                                   // equal on every lane
 }
 

@@ -3,9 +3,9 @@
     from paper_2005_13498_amd import tuning
     plan = tuning.ensure(basis, hub.HUB_C64)   # cached table, else measure and cache
 
-A table entry is keyed by the lattice's sites and bonds, U's sign class does
-not matter (the kernels are data-independent), the sector (n_up, n_dn), the
-precision and the GPU name.  TABLE (tuning_mi355x.json beside this module)
+A table entry is keyed by the lattice's name, sites and bonds, the sector's
+tile shape (up strings x down strings), the precision and the GPU name; U
+and the pulse do not enter (the kernels' work does not depend on them).  TABLE (tuning_mi355x.json beside this module)
 holds the plans measured for the workloads of the benchmark; `python -m
 paper_2005_13498_amd.tuning` re-measures them on the current GPU and
 rewrites it.
@@ -58,14 +58,15 @@ def ensure(basis, prec: int, path: str = TABLE, write: bool = False, reps: int =
     return ent, "measured"
 
 
-def main() -> int:
-    """Measure the plans of the benchmark's sectors and rewrite TABLE."""
+def main(out: str = TABLE) -> int:
+    """Measure the plans of the benchmark's sectors and write them to `out`
+    (default TABLE)."""
     import torch
     from . import Basis
     from synth import workloads, ring
 
     torch.cuda.set_device(0)
-    tab = load()
+    tab = load(out)
     dev = device_name()
     tab[dev] = {}
     wl = workloads()
@@ -81,7 +82,7 @@ def main() -> int:
                   flush=True)
         B.close()
         torch.cuda.empty_cache()
-    with open(TABLE, "w") as f:
+    with open(out, "w") as f:
         json.dump(tab, f, indent=1, sort_keys=True)
     return 0
 
@@ -89,4 +90,4 @@ def main() -> int:
 if __name__ == "__main__":
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-    raise SystemExit(main())
+    raise SystemExit(main(sys.argv[1] if len(sys.argv) > 1 else TABLE))

@@ -110,3 +110,32 @@ def cluster_2d(lx: int, ly: int, t: float = 1.0, periodic: bool = True,
     pos = tuple((float(x), float(y)) for y in range(ly) for x in range(lx))
     kind = "pbc" if periodic else "obc"
     return Lattice(f"cluster{lx}x{ly}{kind}", lx * ly, tuple(bonds), None, pos)
+
+
+def ring_nnn(n: int, t: float = 1.0, t2: float = 0.4) -> Lattice:
+    """Periodic ring with nearest (t) and next-nearest (t2) neighbour bonds,
+    field along the ring (minimum-image displacements)."""
+    if n < 5:
+        raise ValueError("next-nearest bonds need at least 5 sites")
+    bonds = []
+    for i in range(n):
+        for step, amp in ((1, t), (2, t2)):
+            j = (i + step) % n
+            bonds.append((i, j, amp, _min_image(i - j, n)))
+    pos = tuple((float(i), 0.0) for i in range(n))
+    return Lattice(f"ring{n}nnn", n, tuple(bonds), None, pos)
+
+
+def random_graph(n: int, n_bonds: int, seed: int, amplitudes=(1.0, 0.5), displacements=(-1.0, 0.0, 1.0)) -> Lattice:
+    """Seeded graph of n sites and n_bonds distinct bonds between arbitrary
+    site pairs (the paper's hopping matrix allows any pair), amplitudes and
+    field displacements drawn from the given small sets, random on-site
+    energies in [-0.5, 0.5]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    pick = rng.choice(len(pairs), size=n_bonds, replace=False)
+    bonds = tuple((pairs[k][0], pairs[k][1], float(rng.choice(amplitudes)), float(rng.choice(displacements)))
+                  for k in sorted(pick))
+    onsite = tuple(float(e) for e in rng.uniform(-0.5, 0.5, n))
+    return Lattice(f"graph{n}_{n_bonds}_{seed}", n, bonds, onsite, tuple((float(i), 0.0) for i in range(n)))

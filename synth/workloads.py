@@ -68,6 +68,18 @@ def controller_draws(n: int, seed: int = SEED + 1):
     return out
 
 
+def controller_groups(n_groups: int, members: int, seed: int):
+    """Seeded draws for controller runs in groups sharing U (one basis per
+    group): U ~ U[4, 12] per group, then per member A0 ~ U[0.2, 1.2] and
+    omega ~ U[U/2, 2U]; [(U, [(A0, omega), ...]), ...]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_groups):
+        U = float(rng.uniform(4.0, 12.0))
+        out.append((U, [(float(rng.uniform(0.2, 1.2)), float(rng.uniform(0.5 * U, 2.0 * U))) for _ in range(members)]))
+    return out
+
+
 def random_state(dim: int, seed: int = 1, nvec: int = 1) -> np.ndarray:
     """Complex standard-normal vectors, each normalised to 1; shape (nvec, dim)."""
     rng = np.random.default_rng(seed)

@@ -35,11 +35,12 @@ def test_gelu_closed_forms():
 def test_forward_hand_built_networks():
     # all-zero weights: out = b3 whatever the input
     P = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
-    P["b3"] = np.array([2.5, -1.0])
+    P["b3"] = np.array([2.5])
     X = np.random.default_rng(0).normal(size=(5, 8))
     out, _ = mlp.forward(mlp.pack(P), X)
-    assert np.allclose(out, [[2.5, -1.0]] * 5, atol=0)
-    # one path: x[2] -> unit 5 (layer 1) -> unit 3 (layer 2) -> output 0; x[6] -> unit 7 -> unit 9 -> output 1
+    assert np.allclose(out, [[2.5]] * 5, atol=0)
+    # two paths into the output: x[2] -> unit 5 (layer 1) -> unit 3 (layer 2) and
+    # x[6] -> unit 7 -> unit 9
     P = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
     P["W1"][5, 2] = 1.5
     P["W1"][7, 6] = -0.5
@@ -48,27 +49,26 @@ def test_forward_hand_built_networks():
     P["W2"][9, 7] = 1.0
     P["b2"][3] = -0.1
     P["W3"][0, 3] = 3.0
-    P["W3"][1, 9] = -2.0
-    P["b3"][:] = [0.5, 0.125]
+    P["W3"][0, 9] = -2.0
+    P["b3"][:] = [0.5]
     x = np.zeros((1, 8))
     x[0, 2], x[0, 6] = 0.8, 1.2
     out, _ = mlp.forward(mlp.pack(P), x)
     h15 = mlp.gelu(1.5 * 0.8 + 0.25)
     h17 = mlp.gelu(-0.5 * 1.2)
     # units other than 5 and 7 carry gelu(0) = 0, so only the two paths contribute
-    assert abs(out[0, 0] - (3.0 * mlp.gelu(2.0 * h15 - 0.1) + 0.5)) < 1e-14
-    assert abs(out[0, 1] - (-2.0 * mlp.gelu(1.0 * h17) + 0.125)) < 1e-14
+    assert abs(out[0, 0] - (3.0 * mlp.gelu(2.0 * h15 - 0.1) - 2.0 * mlp.gelu(1.0 * h17) + 0.5)) < 1e-14
 
 
 def test_gradient_matches_finite_differences():
     rng = np.random.default_rng(1)
     theta = rng.normal(scale=0.3, size=mlp.N_PARAM)
     X = rng.normal(size=(7, 8))
-    Y = rng.normal(size=(7, 2))
+    Y = rng.normal(size=(7, 1))
     L, g = mlp.loss_and_grad(theta, X, Y)
     assert abs(L - mlp.loss(theta, X, Y)) < 1e-14
     idx = np.concatenate([rng.choice(mlp.N_PARAM, 40, replace=False),
-                          [0, 511, 512, 575, 576, 4671, 4672, 4735, 4736, 4863, 4864, 4865]])
+                          [0, 511, 512, 575, 576, 4671, 4672, 4735, 4736, 4799, 4800]])
     h = 1e-6
     for k in idx:
         e = np.zeros(mlp.N_PARAM)
@@ -153,4 +153,4 @@ def test_controller_argument_checks():
     finally:
         hub.hub_basis_destroy(h)
     assert hub.hub_mlp_workspace_bytes(1000) > 0
-    assert hub.MLP_NPARAM == mlp.N_PARAM == 4866
+    assert hub.MLP_NPARAM == mlp.N_PARAM == 4801

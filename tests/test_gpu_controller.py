@@ -29,7 +29,7 @@ def test_mlp_forward_matches_oracle():
     rng = np.random.default_rng(11)
     theta = rng.normal(scale=0.3, size=mlp.N_PARAM)
     X = rng.normal(size=(1000, 8))
-    out = torch.zeros((1000, 2), dtype=torch.float32, device=DEV)
+    out = torch.zeros((1000, hub.MLP_OUT), dtype=torch.float32, device=DEV)
     hub.hub_mlp_forward(_dev(theta), _dev(X), out)
     ref, _ = mlp.forward(theta.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))
     got = out.cpu().numpy().astype(np.float64)
@@ -41,7 +41,7 @@ def test_mlp_gradient_and_adam_match_oracle(n_rows):
     rng = np.random.default_rng(12 + n_rows)
     theta = (rng.normal(scale=0.3, size=mlp.N_PARAM)).astype(np.float32).astype(np.float64)
     X = rng.normal(size=(n_rows, 8)).astype(np.float32).astype(np.float64)
-    Y = rng.normal(size=(n_rows, 2)).astype(np.float32).astype(np.float64)
+    Y = rng.normal(size=(n_rows, hub.MLP_OUT)).astype(np.float32).astype(np.float64)
     P, m, v = _dev(theta), torch.zeros(mlp.N_PARAM, device=DEV), torch.zeros(mlp.N_PARAM, device=DEV)
     loss = torch.zeros(1, device=DEV)
     ws = torch.empty(hub.hub_mlp_workspace_bytes(n_rows) // 4 + 1, device=DEV)
@@ -88,7 +88,7 @@ def trained(ring8):
 def test_training_lowers_loss_and_predicts_m(trained):
     params, hist, X, Y = trained
     assert hist[-1][1] < 0.1 * hist[0][1], hist
-    out = torch.zeros((len(X), 2), device=DEV)
+    out = torch.zeros((len(X), hub.MLP_OUT), device=DEV)
     hub.hub_mlp_forward(_dev(params), _dev(X), out)
     m_pred = np.ceil(np.exp2(out.cpu().numpy()[:, 0]) - 1e-6)
     m_true = np.exp2(Y[:, 0])

@@ -59,10 +59,11 @@ def test_dot_batched():
     B.close()
 
 
-def _greens_case(lat, U, nu, nd, members, n_rel, dt, pulse, prec, tol, seed=9):
+def _greens_case(lat, U, nu, nd, members, n_rel, dt, pulse, prec, tol, seed=9, path=-1):
     ham = HubbardOracle(lat, U, nu, nd)
     psi0 = random_state(ham.dim, seed=seed)[0]
     B = hub.Basis(lat, U, nu, nd)
+    hub.hub_set_greens_path(B.handle, path)
     sectors = sorted({((nu + (1 if m[2] else -1), nd) if m[1] == 0 else (nu, nd + (1 if m[2] else -1)))
                       for m in members})
     T = [hub.Basis(lat, U, *sec) for sec in sectors]
@@ -80,25 +81,140 @@ def _greens_case(lat, U, nu, nd, members, n_rel, dt, pulse, prec, tol, seed=9):
         t.close()
 
 
-def test_greens_diag_c128_matches_oracle():
+# path 0: members batched per sector; path 1: the persistent member stepper
+_PATHS = pytest.mark.parametrize("path", [0, 1])
+
+
+@_PATHS
+def test_greens_diag_c128_matches_oracle(path):
     members = [(0, 0, 0, 0), (2, 1, 1, 3), (3, 0, 0, 2), (1, 0, 1, 0), (4, 1, 0, 1), (5, 1, 0, 2)]
     p = PulseParams(0, 0.6, 6.0, 0.2, 0.2)
-    for k, got, ref in _greens_case(ring(6), 4.0, 3, 3, members, 12, 0.05, p, hub.HUB_C128, 1e-13):
+    for k, got, ref in _greens_case(ring(6), 4.0, 3, 3, members, 12, 0.05, p, hub.HUB_C128, 1e-13, path=path):
         assert np.max(np.abs(got - ref)) < 1e-10, (k, np.max(np.abs(got - ref)))
 
 
-def test_greens_diag_c64_within_1e5():
+@_PATHS
+def test_greens_diag_c64_within_1e5(path):
     members = [(0, 0, 0, 0), (2, 1, 1, 3), (3, 0, 1, 2), (4, 1, 0, 1)]
     p = PulseParams(0, 0.6, 6.0, 0.2, 0.2)
-    for k, got, ref in _greens_case(ring(8), 8.0, 4, 4, members, 20, 0.02, p, hub.HUB_C64, 1e-8):
+    for k, got, ref in _greens_case(ring(8), 8.0, 4, 4, members, 20, 0.02, p, hub.HUB_C64, 1e-8, path=path):
         assert np.max(np.abs(got - ref)) < 1e-5, (k, np.max(np.abs(got - ref)))
 
 
-def test_greens_ring10_workload_sampled():
+@_PATHS
+def test_greens_ring10_workload_sampled(path):
     """10-site ring, U = 8, 5/5 (dim 63,504), members in the (4,5), (6,5),
     (5,4), (5,6) sectors (dim 52,920) with staggered starts, complex64 apply
     with FP64 Lanczos scalars; first 15 relative steps against the oracle."""
     w = workloads()["ring10_greens"]
     members = [(0, 0, 0, 0), (3, 0, 1, 5), (6, 1, 0, 10), (9, 1, 1, 0)]
-    for k, got, ref in _greens_case(w.lattice, w.U, 5, 5, members, 15, w.dt, w.pulse, hub.HUB_C64, 1e-8):
+    for k, got, ref in _greens_case(w.lattice, w.U, 5, 5, members, 15, w.dt, w.pulse, hub.HUB_C64, 1e-8,
+                                    path=path):
         assert np.max(np.abs(got - ref)) < 1e-5, (k, np.max(np.abs(got - ref)))
+
+
+_STARTS = (50, 100)
+_SIXTEEN = [(site, spin, dagger, st) for spin, dagger in ((0, 1), (1, 1), (0, 0), (1, 0))
+            for site in (0, 6) for st in _STARTS]
+_N_REL16 = 30
+
+
+@pytest.fixture(scope="module")
+def sixteen_reference():
+    """Oracle overlaps of the 16 members: psi propagated once to each t',
+    each member from there (shared by both precisions)."""
+    w = workloads()["ring10_greens"]
+    ham = HubbardOracle(w.lattice, w.U, 5, 5)
+    psi0 = random_state(ham.dim, seed=10)[0]
+    from oracle.stepper import midpoint_step_exact
+    psi_at = {}
+    v = psi0.copy()
+    for n in range(max(_STARTS) + 1):
+        if n in _STARTS:
+            psi_at[n] = v.copy()
+        v = midpoint_step_exact(ham, v, n * w.dt, w.dt, w.pulse)
+    oh = {}
+    ref = []
+    for site, spin, dagger, st in _SIXTEEN:
+        sec = (5 + (1 if dagger else -1), 5) if spin == 0 else (5, 5 + (1 if dagger else -1))
+        if sec not in oh:
+            oh[sec] = HubbardOracle(w.lattice, w.U, *sec)
+        ref.append(greens_diag(ham, psi_at[st], w.pulse, st * w.dt, w.dt, 0, _N_REL16, site, spin, bool(dagger),
+                               ham_target=oh[sec]))
+    return w, ham, psi0, ref
+
+
+@_PATHS
+@pytest.mark.parametrize("prec,tol,bar", [(hub.HUB_C64, 1e-8, 1e-5), (hub.HUB_C128, 1e-13, 1e-10)])
+def test_greens_ring10_sixteen_members(sixteen_reference, prec, tol, bar, path):
+    """The 10-site ring workload from a seeded state: all four operators (c
+    and c^dag of both spins) at sites 0 and 6, from t' = 0.5 and 1.0 (16
+    members, four per sector with two start times each), 30 relative steps;
+    every member and step against the oracle."""
+    w, ham, psi0, ref = sixteen_reference
+    lat, U = w.lattice, w.U
+    B = hub.Basis(lat, U, 5, 5)
+    hub.hub_set_greens_path(B.handle, path)
+    T = [hub.Basis(lat, U, *sec) for sec in [(4, 5), (6, 5), (5, 4), (5, 6)]]
+    try:
+        dtype = torch.complex128 if prec == hub.HUB_C128 else torch.complex64
+        psi = _dev(to_canonical(psi0, ham.states, 10), dtype)
+        got = hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, _N_REL16,
+                                  hub.make_opts(tol=tol, m_max=30), _SIXTEEN, psi)
+        for k in range(len(_SIXTEEN)):
+            assert np.max(np.abs(got[k] - ref[k])) < bar, (k, np.max(np.abs(got[k] - ref[k])))
+    finally:
+        B.close()
+        for t in T:
+            t.close()
+
+
+def test_greens_member_stepper_stops_at_m_max():
+    """m_max too small for the tolerance in the members' steps only: at U = 0
+    psi = (plane wave k = 1 up) x (plane wave k = 2 down) on the 6-site ring
+    is an eigenstate of H(A) for every A (one Lanczos vector per step),
+    while the member c^dag_{1,up} psi needs more than three Krylov vectors
+    for a step of 0.5.  Both steppers report HUB_E_NOT_CONVERGED."""
+    lat = ring(6)
+    B = hub.Basis(lat, 0.0, 1, 1)
+    T = [hub.Basis(lat, 0.0, 2, 1)]
+    up, dn = hub.hub_basis_states(B.handle)
+    site = lambda s: int(s).bit_length() - 1
+    pw = lambda k, strings: np.array([np.exp(2j * np.pi * k * site(s) / 6) for s in strings]) / np.sqrt(6)
+    psi = _dev(np.outer(pw(1, up), pw(2, dn)).ravel(), torch.complex128)
+    try:
+        for path in (0, 1):
+            hub.hub_set_greens_path(B.handle, path)
+            with pytest.raises(hub.HubError) as e:
+                hub.hub_greens_diag(B.handle, [t.handle for t in T], PulseParams(0, 0.6, 6.0, 0.2, 0.2), 0.0, 0.5, 6,
+                                    hub.make_opts(tol=1e-14, m_max=3), [(1, 0, 1, 2)], psi.clone())
+            assert e.value.status == hub.HUB_E_NOT_CONVERGED
+    finally:
+        B.close()
+        for t in T:
+            t.close()
+
+
+def test_greens_member_stepper_needs_three_term_recurrence():
+    """Forcing the persistent stepper with full reorthogonalisation is an
+    error; the automatic choice falls back to the per-sector path."""
+    lat = ring(6)
+    p = PulseParams(0, 0.6, 6.0, 0.2, 0.2)
+    B = hub.Basis(lat, 4.0, 3, 3)
+    T = [hub.Basis(lat, 4.0, 2, 3)]
+    psi = _dev(random_state(B.dim, seed=4)[0], torch.complex128)
+    opts = hub.make_opts(tol=1e-12, m_max=30, reorth=1)
+    try:
+        hub.hub_set_greens_path(B.handle, 1)
+        with pytest.raises(hub.HubError) as e:
+            hub.hub_greens_diag(B.handle, [T[0].handle], p, 0.0, 0.05, 4, opts, [(1, 0, 0, 0)], psi.clone())
+        assert e.value.status == hub.HUB_E_INVALID
+        hub.hub_set_greens_path(B.handle, -1)
+        a = hub.hub_greens_diag(B.handle, [T[0].handle], p, 0.0, 0.05, 4, opts, [(1, 0, 0, 0)], psi.clone())
+        hub.hub_set_greens_path(B.handle, 0)
+        b = hub.hub_greens_diag(B.handle, [T[0].handle], p, 0.0, 0.05, 4, opts, [(1, 0, 0, 0)], psi.clone())
+        assert np.array_equal(a, b)
+    finally:
+        B.close()
+        for t in T:
+            t.close()
