@@ -284,8 +284,8 @@ hub_status hub_greens_diag(hub_basis basis, int32_t n_targets, const hub_basis *
  * grouped hop slots per string and a tile row and column of at most 144 KiB,
  * else hub_greens_diag returns HUB_E_INVALID.  path -1 (default): 1 where it
  * applies, every target sector has at most 2^18 states and there are at
- * least 4 members per compute unit (one workgroup per member runs well below
- * a compute unit's share of the bandwidth), else 0.  Both give the same
+ * least as many members as compute units (one workgroup per member runs well
+ * below a compute unit's share of the bandwidth), else 0.  Both give the same
  * overlaps up to rounding.  Errors: HUB_E_INVALID. */
 hub_status hub_set_greens_path(hub_basis basis, int32_t path);
 

@@ -1658,12 +1658,13 @@ namespace {
 
 // LDS staging of the persistent member stepper; the largest target sector and
 // the fewest members (per compute unit) for which it is the automatic choice:
-// one workgroup per member runs far below a compute unit's share of the
-// bandwidth, so it pays only once there are several members per unit, and
-// larger sectors fill the GPU one apply at a time.
+// one workgroup per member runs well below a compute unit's share of the
+// bandwidth, so it pays only once every unit has a member (10-site sectors:
+// 64 members 0.6x, 256 members 1.45x the per-sector batches), and larger
+// sectors fill the GPU one apply at a time.
 constexpr size_t kMembersLds = 144 << 10;
 constexpr int64_t kMembersAutoDim = 1 << 18;
-constexpr int kMembersAutoPerCU = 4;
+constexpr int kMembersAutoPerCU = 1;
 
 // Members of one target sector in hub_greens_diag.
 struct GreensSector {
