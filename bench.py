@@ -310,6 +310,31 @@ def plan_label(hub, B, prec: int, nvec: int, propagate: bool) -> str:
     return "; ".join(f"{c} group(s) of {g} on the {names[k]}" for (g, k), c in sorted(parts.items()))
 
 
+def tuned_run(hub, B, prec: int, pulses, t_start: float, dt: float, steps: int, opts, v):
+    """The same propagation under the committed tuning table's plan for this
+    sector (measured with hub_tune on the GPU): (entry, plan label, seconds,
+    obs) or None when the table has no entry for this sector and GPU."""
+    import torch
+    from paper_2005_13498_amd import tuning
+
+    tab = tuning.load()
+    ent = tab.get(tuning.device_name(), {}).get(tuning.key(B, prec))
+    if ent is None:
+        return None
+    hub.hub_set_tuning(B.handle, prec, ent)
+    try:
+        label = plan_label(hub, B, prec, len(pulses), True)
+        hub.hub_propagate(B.handle, pulses, t_start, dt, 2, opts, v.clone(), want_obs=False)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, o, _ = hub.hub_propagate(B.handle, pulses, t_start, dt, steps, opts, v)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        hub.hub_set_tuning(B.handle, prec, None)
+    return ent, label, el, o
+
+
 def batched_variants(hub, B, v0, t_start: float, w, steps: int) -> dict:
     """Mixed precision and batching at 12 sites: the same ground state under
     8 pulse amplitudes (the seeded A0 draws), propagated by one hub_propagate
@@ -359,6 +384,14 @@ def batched_variants(hub, B, v0, t_start: float, w, steps: int) -> dict:
     res["c64_vs_c128"] = {"max_abs_docc_err": float(np.max(np.abs(d64 - d128))),
                           "max_abs_energy_per_site_err": float(np.max(np.abs(e64 - e128))),
                           "max_abs_norm_drift": float(np.max(np.abs(obs["c64_batch8"][:, :, 1] - 1.0)))}
+    tr = tuned_run(hub, B, hub.HUB_C64, pulses, t_start, w.dt, steps, opts, v0.to(torch.complex64).repeat(nv).contiguous())
+    if tr is not None:
+        ent, label, el, o = tr
+        res["c64_batch8_tuned"] = {"kernels": label, "prop_group": ent["prop_group"],
+                                   "member_steps_per_s": nv * steps / el,
+                                   "max_abs_docc_diff_vs_default_plan": float(np.max(np.abs(o[:, :, 3] - d64)))}
+        print(f"[bench] c64_batch8 on the tuned plan ({label}): {nv * steps / el:.0f} member-steps/s",
+              file=sys.stderr, flush=True)
     res["speedup_c64_batch8_vs_plain_c128"] = None  # filled by the caller
     return res
 
@@ -704,7 +737,7 @@ def greens_variant(hub) -> dict:
     return res
 
 
-def greens_scaling_variant(hub) -> dict:
+def greens_scaling_variant(hub, paths=((1, "persistent_members"), (0, "per_sector"))) -> dict:
     """Member count against stepper: the 10-site ring's Green's-function
     members (c and c^dag of both spins at all 10 sites, t' on a grid from
     0.1) at 256 and 1024 members, 50 relative steps of 0.01, complex64, on
@@ -727,7 +760,7 @@ def greens_scaling_variant(hub) -> dict:
                    for spin, dagger in ((0, 1), (1, 1), (0, 0), (1, 0)) for site in range(10) for k in range(n_tp)]
         members = members[:(256 if n_tp == 8 else 1024)]
         r = res[f"members_{len(members)}"] = {}
-        for path, pname in ((1, "persistent_members"), (0, "per_sector")):
+        for path, pname in paths:
             hub.hub_set_greens_path(B.handle, path)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -787,6 +820,16 @@ def ring14_block_variant(hub, steps: int = 10) -> dict:
                          "seconds": el64, "member_steps_per_s": len(pulses) * steps / el64,
                          "mean_krylov_m": float(np.mean(log64[:, :, 0]))}
     res["c128_single"] = {"seconds": el128, "member_steps_per_s": len(pulses) * steps / el128}
+    tr = tuned_run(hub, B, hub.HUB_C64, pulses, 0.0, w.dt, steps, opts,
+                   x0.to(torch.complex64).repeat(len(pulses)).contiguous())
+    if tr is not None:
+        ent, label, el, o = tr
+        res["c64_8members_tuned"] = {"kernels": label, "prop_group": ent["prop_group"], "seconds": el,
+                                     "member_steps_per_s": len(pulses) * steps / el,
+                                     "max_abs_docc_diff_vs_default_plan": float(np.max(np.abs(o[:, :, 3] - obs64[:, :, 3])))}
+        print(f"[bench] ring14 c64 8 members on the tuned plan ({label}): "
+              f"{len(pulses) * steps / el:.1f} member-steps/s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     res["max_abs_docc_err"] = float(np.max(np.abs(obs64[:, :, 3] - obs128[:, :, 3])))
     res["max_abs_energy_per_site_err"] = float(np.max(np.abs(obs64[:, :, 2] - obs128[:, :, 2])))
     print(f"[bench] ring14: c64 8 members {res['c64_8members']['member_steps_per_s']:.1f} member-steps/s, c128 "
@@ -852,8 +895,8 @@ def main() -> int:
     ap.add_argument("--summarize-stats", nargs=2, metavar=("TRACE_DIR", "OUT"))
     ap.add_argument("--command", default="", help="profiling command recorded in a summary")
     ap.add_argument("--note", default="", help="comment lines (separated by |) recorded in a summary")
-    ap.add_argument("--variant", choices=("greens_ring10", "greens_scaling", "ring14_block", "ring8", "hv12",
-                                          "controller"),
+    ap.add_argument("--variant", choices=("greens_ring10", "greens_scaling", "greens_persistent", "ring14_block",
+                                          "ring8", "hv12", "controller"),
                     help="run only this variant and print its result (for profiling it alone)")
     args = ap.parse_args()
 
@@ -887,6 +930,7 @@ def main() -> int:
             B.close()
             return 0
         run = {"greens_ring10": greens_variant, "greens_scaling": greens_scaling_variant,
+               "greens_persistent": lambda h: greens_scaling_variant(h, ((1, "persistent_members"),)),
                "ring14_block": ring14_block_variant, "ring8": ring8_variant,
                "controller": controller_c5_variant}
         print(json.dumps({args.variant: run[args.variant](hub)}), flush=True)

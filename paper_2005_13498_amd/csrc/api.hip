@@ -1662,7 +1662,7 @@ namespace {
 // bandwidth, so it pays only once every unit has a member (10-site sectors:
 // 64 members 0.6x, 256 members 1.45x the per-sector batches), and larger
 // sectors fill the GPU one apply at a time.
-constexpr size_t kMembersLds = 144 << 10;
+constexpr size_t kMembersLds = 148 << 10;  // tables + staging per member workgroup
 constexpr int64_t kMembersAutoDim = 1 << 18;
 constexpr int kMembersAutoPerCU = 1;
 
@@ -1739,10 +1739,14 @@ hub_status greens_members(hub_basis h, const std::vector<GreensSector>& secs, co
     M.U = TD.U;
     M.norm_inf = S.T->B.norm_inf;
     M.nc = TD.nc;
-    M.row_block = static_cast<int>(std::min<size_t>(TD.dim_up, kMembersLds / ((TD.dim_dn + 1) * es)));
-    M.col_block = static_cast<int>(std::min<size_t>(TD.dim_dn, kMembersLds / ((TD.dim_up + 1) * es)));
-    lds = std::max({lds, static_cast<size_t>(M.row_block) * (TD.dim_dn + 1) * es,
-                    static_cast<size_t>(M.col_block) * (TD.dim_up + 1) * es});
+    const size_t tab = hub::members_table_lds(TD.dim_up, TD.dim_dn, TD.up_gslots, TD.dn_gslots,
+                                              TD.eps_up != nullptr || TD.eps_dn != nullptr, S.map_len);
+    const size_t stage = kMembersLds - tab;  // the caller checked that a tile row and column fit
+    M.tab_lds = static_cast<int>(tab);
+    M.row_block = static_cast<int>(std::min<size_t>(TD.dim_up, stage / ((TD.dim_dn + 1) * es)));
+    M.col_block = static_cast<int>(std::min<size_t>(TD.dim_dn, stage / ((TD.dim_up + 1) * es)));
+    lds = std::max({lds, tab + static_cast<size_t>(M.row_block) * (TD.dim_dn + 1) * es,
+                    tab + static_cast<size_t>(M.col_block) * (TD.dim_up + 1) * es});
     ctabs.emplace_back(static_cast<size_t>(std::max(n_total, 1)) * 2 * TD.nc, 0.0);  // alive until the sync
     std::vector<double>& ct = ctabs.back();
     for (int n = 0; n < n_total; ++n)
@@ -1851,8 +1855,11 @@ hub_status hub_greens_diag(hub_basis h, int32_t n_targets, const hub_basis* targ
   for (int k = 0; k < n_members && members_fit; ++k) {
     const hub::Basis& TB = targets[tb[k]]->B;
     const DevBasis& TD = targets[tb[k]]->D;
+    const int map_len = members[k].spin == 0 ? TD.dim_up : TD.dim_dn;
+    const size_t tab = hub::members_table_lds(TD.dim_up, TD.dim_dn, TD.up_gslots, TD.dn_gslots,
+                                              TD.eps_up != nullptr || TD.eps_dn != nullptr, map_len);
     members_fit = (TD.dn_gslots > 0 || TB.dn.max_hops == 0) && (TD.up_gslots > 0 || TB.up.max_hops == 0) &&
-                  (TD.dim_dn + 1) * es <= kMembersLds && (TD.dim_up + 1) * es <= kMembersLds;
+                  tab + (TD.dim_dn + 1) * es <= kMembersLds && tab + (TD.dim_up + 1) * es <= kMembersLds;
     members_small &= TD.dim <= kMembersAutoDim;
   }
   if (h->greens_path == 1 && !members_fit)

@@ -25,6 +25,7 @@ struct MemberSector {
   int nc;                  // hop classes
   const double* coef_tab;  // [n_total][2 nc]: coefficient of every class at each global step's midpoint
   int row_block, col_block;  // tile rows / tile columns staged in LDS at a time
+  int tab_lds;               // LDS bytes of the tables before the staging area (members_table_lds)
 };
 
 // One member: its sector, first global step, Krylov slots ((m_max + 1)
@@ -53,7 +54,19 @@ struct MembersArgs {
   int dim_dn_s;         // source sector's dim_dn
 };
 
-// One workgroup per member (1024 threads, `lds` bytes of staging).
+// LDS bytes a member workgroup keeps its sector's tables, strings, on-site
+// energies and its operator map in (16-byte aligned pieces, in the kernel's
+// order): gs_dn / 4 words of 8 bytes per down string, gs_up / 4 per up string,
+// the strings, the energies when present, the map and its signs.
+inline size_t members_table_lds(int dim_up, int dim_dn, int gs_up, int gs_dn, bool eps, int map_len) {
+  auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
+  size_t t = a16(size_t(dim_dn) * (gs_dn / 4) * 8) + a16(size_t(dim_up) * (gs_up / 4) * 8) + a16(size_t(dim_up) * 4) +
+             a16(size_t(dim_dn) * 4);
+  if (eps) t += a16(size_t(dim_up) * 8) + a16(size_t(dim_dn) * 8);
+  return t + a16(size_t(map_len) * 4) + a16(size_t(map_len));
+}
+
+// One workgroup per member (512 threads, `lds` bytes: tables and staging).
 hipError_t launch_members(int prec, int n_members, const MembersArgs& a, size_t lds, hipStream_t s);
 
 }  // namespace hub

@@ -1,4 +1,6 @@
-"""The parameter set of the paper's Fig. (frequencies) (Sec. 4): half-filled
+"""The parameter sets of the paper's Sec. 4 figures.
+
+Fig. (frequencies): half-filled
 8-site open chain, U = 4, the phase pulse of Eq. (vt) with t_p = 6,
 sigma = 2, a = 0.8, b = cos(omega t_p) (so f(0) = 1), time step 0.005, from
 the ground state, for omega = 3.5 and omega = 11, up to t = 16 (after the
@@ -15,7 +17,21 @@ pulse).
   absorbed during the pulse and returned afterwards.  The thresholds below
   are loose bounds on the oracle's own trajectory (omega = 3.5: d rises by
   0.165 and E/N_s by 1.32; omega = 11: E/N_s rises by 0.32 during the pulse
-  and ends 0.008 above the start)."""
+  and ends 0.008 above the start).
+
+Fig. (site-resolved double occupation): the 14-site chain at half filling,
+U = 3.5, omega = 7 pi / 4, t_p = 6, sigma = 2, a = 0.8 (dim 11,778,624), from
+the GPU ground state through the pulse peak to t = 8.  The oracle cannot
+propagate 14 sites in a test, so this case checks what holds at any size
+(parity unpinned): the norm, the site-resolved double occupation summing to
+the average, and the rise the figure shows, bounded by the oracle's own
+8- and 10-site runs of the same pulse (d = 0.106 / 0.108 at t = 0, 0.235 /
+0.237 at t = 8).
+
+Fig. (spectral functions), left and right columns: the 8-site chain, U = 6,
+omega = 9, t_p = 8, sigma = 2, a = 0.2 and 0.6: the two-time Green's-function
+overlaps of c and c^dag members started at t' = 8 and 12, on both member
+steppers, against the oracle within 1e-10 (complex128)."""
 import math
 
 import numpy as np
@@ -70,3 +86,73 @@ def test_fig_frequencies_chain8(chain8, omega):
             assert dE.max() > 0.1 and abs(dE[-1]) < 0.05 and abs(dd[-1]) < 0.02
     finally:
         B.close()
+
+
+def test_fig_site_docc_chain14():
+    """Fig. (site-resolved double occupation) at its own size: 14-site chain,
+    U = 3.5, omega = 7 pi / 4, from the ground state to t = 8 (steps of 0.02)."""
+    omega = 7 * math.pi / 4
+    pulse = PulseParams(1, 0.8, omega, 6.0, 2.0, math.cos(omega * 6.0))
+    lat = chain(14)
+    B = hub.Basis(lat, 3.5, 7, 7)
+    try:
+        g = torch.empty(B.dim, dtype=torch.complex128, device=DEV)
+        hub.hub_ground_state(B.handle, 0.0, g, hub.make_opts(tol=1e-10, m_max=60))
+        obs0, site0 = hub.hub_observables(B.handle, [0.0], g, site=True)
+        st, obs, log = hub.hub_propagate(B.handle, [pulse], 0.0, 0.02, 400, hub.make_opts(tol=1e-10, m_max=30), g)
+        obs8, site8 = hub.hub_observables(B.handle, [hub.hub_pulse_A(pulse, 8.0)], g, site=True)
+        assert np.max(np.abs(obs[:, 0, 1] - 1.0)) < 1e-9
+        for o, sd in ((obs0, site0), (obs8, site8)):
+            assert abs(sd[0].sum() / 14 - o[0, 3]) < 1e-12
+        d0, d8 = obs[0, 0, 3], obs[-1, 0, 3]
+        assert abs(d0 - obs0[0, 3]) < 1e-12 and abs(d8 - obs8[0, 3]) < 1e-12
+        assert 0.100 < d0 < 0.115, d0
+        assert 0.20 < d8 < 0.27, d8
+        assert np.all(log[:, 0, 2] + log[:, 0, 3] > 0)  # every step converged (or broke down exactly)
+    finally:
+        B.close()
+
+
+_FIG12_STARTS = (400, 600)
+_FIG12_MEMBERS = [(3, 0, 0, 400), (3, 0, 1, 400), (0, 1, 0, 600), (0, 1, 1, 600)]
+
+
+@pytest.fixture(scope="module", params=[0.2, 0.6])
+def fig12_reference(request):
+    from oracle.greens import greens_diag
+    a = request.param
+    pulse = PulseParams(1, a, 9.0, 8.0, 2.0, math.cos(9.0 * 8.0))
+    lat, dt, n_rel = chain(8), 0.02, 100
+    ham = HubbardOracle(lat, 6.0, 4, 4)
+    _, _, g = ground_state(ham, 0.0)
+    psi_at, v = {}, g.copy()
+    for n in range(max(_FIG12_STARTS) + 1):
+        if n in _FIG12_STARTS:
+            psi_at[n] = v.copy()
+        v = midpoint_step_exact(ham, v, n * dt, dt, pulse)
+    oh, ref = {}, []
+    for site, spin, dagger, st in _FIG12_MEMBERS:
+        sec = (4 + (1 if dagger else -1), 4) if spin == 0 else (4, 4 + (1 if dagger else -1))
+        oh.setdefault(sec, HubbardOracle(lat, 6.0, *sec))
+        ref.append(greens_diag(ham, psi_at[st], pulse, st * dt, dt, 0, n_rel, site, spin, bool(dagger),
+                               ham_target=oh[sec]))
+    return lat, ham, g, pulse, dt, n_rel, ref
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_fig_spectral_chain8_greens(fig12_reference, path):
+    lat, ham, g, pulse, dt, n_rel, ref = fig12_reference
+    B = hub.Basis(lat, 6.0, 4, 4)
+    hub.hub_set_greens_path(B.handle, path)
+    T = [hub.Basis(lat, 6.0, *sec) for sec in ((3, 4), (5, 4), (4, 3), (4, 5))]
+    try:
+        psi = torch.from_numpy(to_canonical(g, ham.states, 8)).to(DEV)
+        got = hub.hub_greens_diag(B.handle, [t.handle for t in T], pulse, 0.0, dt, n_rel,
+                                  hub.make_opts(tol=1e-13, m_max=30), _FIG12_MEMBERS, psi)
+        for k in range(len(_FIG12_MEMBERS)):
+            assert np.max(np.abs(got[k] - ref[k])) < 1e-10, (k, np.max(np.abs(got[k] - ref[k])))
+            assert np.max(np.abs(ref[k])) > 0.05
+    finally:
+        B.close()
+        for t in T:
+            t.close()
