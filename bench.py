@@ -777,7 +777,7 @@ def greens_scaling_variant(hub, paths=((1, "persistent_members"), (0, "per_secto
     return res
 
 
-def ring14_block_variant(hub, steps: int = 10) -> dict:
+def ring14_block_variant(hub, steps: int = 40) -> dict:
     """14-site ring (7/7, dim 11,778,624; vectors far beyond the Infinity
     Cache): a complex64 block of 8 pulse amplitudes (A0 = 0.1 .. 0.8) in one
     hub_propagate call against complex128 single-vector calls, from a seeded

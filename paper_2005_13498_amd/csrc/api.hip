@@ -423,9 +423,11 @@ std::vector<int> groups_for(hub_basis h, int nvec, int prec, bool propagate = tr
   const int tuned = h->force_group > 0 ? h->force_group : (propagate ? h->prop_group[prec] : h->apply_group[prec]);
   if (tuned > 0) {
     std::vector<int> g;
+    // a tuned size smaller where neither the block kernels nor the one-pass
+    // kernel can take a group of that size
     for (int left = nvec; left > 0;) {
       int s = tuned;
-      while (s > left) s /= 2;
+      while (s > left || (s > 1 && !hub::block_two_pass(h->D, prec, s) && !hub::apply_fits(h->D, prec, s))) s /= 2;
       g.push_back(s);
       left -= s;
     }
@@ -892,6 +894,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
   }
   // observables at the last sample time reached (after n_steps steps, or
   // after the step that stopped at m_max)
+  bool split_obs = false;
   if (want_obs) {
     StepCtl c2 = StepCtl{};  // clear a stop flag left by the last step
     *W.h_ctl = c2;
@@ -905,12 +908,30 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     A.coef_obs = A.coef;
     A.j = 0;
     int ogrid = 0;
-    HUB_HIP(hub::launch_apply(A, &ogrid));
-    HUB_HIP(hub::launch_finalize_obs(nv, W.partials, ogrid, hub::apply_nq(hub::kObsOnly, true, nc), W.st, stream));
+    if (nv > 1 && !hub::apply_fits(h->D, pi, nv)) {
+      // the group's row does not fit the one-pass kernel (blocks on the
+      // two-pass block kernels): back to the caller's layout first, then the
+      // observables of one vector at a time
+      HUB_HIP(hub::launch_interleave(pi, nv, dim, slot0, user, false, stream));
+      split_obs = true;
+      for (int v = 0; v < nv; ++v) {
+        hub::ApplyLaunch A1 = A;
+        A1.nv = 1;
+        A1.x = static_cast<const char*>(user) + static_cast<size_t>(v) * dim * es;
+        A1.coef = A.coef + static_cast<size_t>(v) * 2 * nc;
+        A1.coef_obs = A1.coef;
+        HUB_HIP(hub::launch_apply(A1, &ogrid));
+        HUB_HIP(hub::launch_finalize_obs(1, W.partials, ogrid, hub::apply_nq(hub::kObsOnly, true, nc), W.st + v,
+                                         stream));
+      }
+    } else {
+      HUB_HIP(hub::launch_apply(A, &ogrid));
+      HUB_HIP(hub::launch_finalize_obs(nv, W.partials, ogrid, hub::apply_nq(hub::kObsOnly, true, nc), W.st, stream));
+    }
     HUB_HIP(hub::launch_step_log(nv, W.st, W.ctl, nullptr, dobs + static_cast<size_t>(*steps_done) * nv * kObsQ,
                                  kObsQ, stream));
   }
-  if (nv > 1) HUB_HIP(hub::launch_interleave(pi, nv, dim, slot0, user, false, stream));
+  if (nv > 1 && !split_obs) HUB_HIP(hub::launch_interleave(pi, nv, dim, slot0, user, false, stream));
 
   // copy logs back
   const int nd = *steps_done;

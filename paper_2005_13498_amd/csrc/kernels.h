@@ -150,6 +150,9 @@ int apply_nq(int mode, bool obs, int nc);
 // observables the row pass writes its kObsQ columns to ApplyLaunch.row_obs.
 int apply_nq_two_pass(bool obs);
 size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows);
+// Whether the one-pass kernel can stage a tile row of nv interleaved vectors
+// (single vectors always have a path: two passes or rows read from memory).
+bool apply_fits(const DevBasis& db, int prec, int nv);
 int elem_grid(int64_t n);  // grid of the elementwise kernels (update, combine, norms)
 
 // u_{j+1} = w - alpha_j s_j u_j in place; alpha_j from the apply's partials;

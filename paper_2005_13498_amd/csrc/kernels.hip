@@ -702,6 +702,10 @@ size_t apply_lds_bytes(const DevBasis& db, int prec, int nv, int rows) {
   return 2 * (static_cast<size_t>(db.dim_dn) + 1) * nv * elem;  // +x and -x copies with zero slots
 }
 
+bool apply_fits(const DevBasis& db, int prec, int nv) {
+  return nv == 1 || apply_lds_bytes(db, prec, nv, 1) <= 150 * 1024;
+}
+
 hipError_t launch_apply(const ApplyLaunch& L, int* grid_out) {
   if (L.nv > 1 && L.mode != kObsOnly && block_two_pass(*L.db, L.prec, L.nv)) {
     int pgrid = 0;

@@ -115,9 +115,14 @@ def test_block_propagation_matches_exact(dtype, bar):
         B.close()
 
 
+def _block_plan(group):
+    return {"single_two_pass": 1, "block_two_pass": [0, 1, 1, 1], "apply_group": group, "prop_group": group}
+
+
 def test_block_propagation_cluster3x4_c64_vs_c128():
-    """12 sites: 8 members in complex64 (one block) against complex128 single
-    vectors of the same pulses, 6 steps in the pulse."""
+    """12 sites: 8 members in complex64 as one block on the two-pass block
+    kernels (forced plan) against complex128 single vectors of the same
+    pulses, 6 steps in the pulse."""
     w = workloads()["cluster3x4"]
     B = hub.Basis(w.lattice, w.U, 6, 6)
     try:
@@ -127,6 +132,8 @@ def test_block_propagation_cluster3x4_c64_vs_c128():
         v0 /= torch.linalg.vector_norm(v0)
         blk = v0.to(torch.complex64).repeat(8).contiguous()
         n = 6
+        hub.hub_set_tuning(B.handle, hub.HUB_C64, _block_plan(8))
+        assert hub.hub_get_plan(B.handle, hub.HUB_C64, 8, True) == [(8, 2)]
         st, o64, _ = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, n, hub.make_opts(tol=1e-8, m_max=30), blk)
         for k in (0, 4, 7):
             v = v0.clone()
@@ -136,3 +143,31 @@ def test_block_propagation_cluster3x4_c64_vs_c128():
             assert np.max(np.abs(o64[:, k, 2:] - o128[:, 0, 2:])) < 1e-5
     finally:
         B.close()
+
+
+def test_block_propagation_ring14_c64_vs_c128():
+    """14 sites (dim 11,778,624): 4 members in complex64 as one block of 4 on
+    the two-pass block kernels (the plan the tuner picks there) against
+    complex128 single vectors, 3 steps in the pulse."""
+    w = workloads()["ring14_block"]
+    B = hub.Basis(w.lattice, w.U, 7, 7)
+    try:
+        pulses = [PulseParams(0, a, w.pulse.omega, 0.02, 0.03) for a in (0.2, 0.5, 0.8, 1.1)]
+        g = torch.Generator(device=DEV).manual_seed(4)
+        v0 = torch.randn(B.dim, dtype=torch.complex128, device=DEV, generator=g)
+        v0 /= torch.linalg.vector_norm(v0)
+        blk = v0.to(torch.complex64).repeat(4).contiguous()
+        n = 3
+        hub.hub_set_tuning(B.handle, hub.HUB_C64, _block_plan(4))
+        assert hub.hub_get_plan(B.handle, hub.HUB_C64, 4, True) == [(4, 2)]
+        st, o64, _ = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, n, hub.make_opts(tol=1e-8, m_max=30), blk)
+        for k in (0, 3):
+            v = v0.clone()
+            st, o128, _ = hub.hub_propagate(B.handle, [pulses[k]], 0.0, w.dt, n, hub.make_opts(tol=1e-12, m_max=30), v)
+            got = blk[k * B.dim:(k + 1) * B.dim].to(torch.complex128)
+            assert float(torch.linalg.vector_norm(got - v)) < 2e-5
+            assert np.max(np.abs(o64[:, k, 2:] - o128[:, 0, 2:])) < 1e-5
+            del v, got
+    finally:
+        B.close()
+        torch.cuda.empty_cache()

@@ -72,3 +72,29 @@ def test_every_plan_matches_oracle(group, block):
             assert _rel(from_canonical(got[k], ham.states, 8), v) < 1e-10
     finally:
         B.close()
+
+
+def test_tuned_group_shrinks_where_no_kernel_fits():
+    """14 sites, complex64: a plan asking for groups of 8 gets groups of 4,
+    the largest block whose tile row fits LDS (the one-pass kernel cannot
+    stage 8 vectors of a 3,432-element row either); a block of 4 propagates
+    with observables at every sample time, the last row taken one vector
+    at a time."""
+    from synth import ring
+    B = hub.Basis(ring(14), 8.0, 7, 7)
+    try:
+        hub.hub_set_tuning(B.handle, hub.HUB_C64, {"single_two_pass": 1, "block_two_pass": [0, 1, 1, 1],
+                                                   "apply_group": 8, "prop_group": 8})
+        assert hub.hub_get_plan(B.handle, hub.HUB_C64, 8, True) == [(4, 2), (4, 2)]
+        g = torch.Generator(device=DEV).manual_seed(7)
+        v0 = torch.randn(B.dim, dtype=torch.complex128, device=DEV, generator=g)
+        v0 /= torch.linalg.vector_norm(v0)
+        x = v0.to(torch.complex64).repeat(4).contiguous()
+        pulses = [PulseParams(0, a, 8.0, 0.01, 0.02) for a in (0.3, 0.6, 0.9, 1.2)]
+        st, obs, log = hub.hub_propagate(B.handle, pulses, 0.0, 0.01, 2, hub.make_opts(tol=1e-8, m_max=30), x)
+        o1, _ = hub.hub_observables(B.handle, [hub.hub_pulse_A(p, 0.02) for p in pulses], x)
+        assert np.max(np.abs(obs[-1, :, 1:] - o1[:, 1:])) < 1e-6
+        assert np.max(np.abs(obs[:, :, 1] - 1.0)) < 1e-5
+    finally:
+        B.close()
+        torch.cuda.empty_cache()
