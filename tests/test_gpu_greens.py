@@ -169,6 +169,21 @@ def test_greens_ring10_sixteen_members(sixteen_reference, prec, tol, bar, path):
             t.close()
 
 
+@_PATHS
+def test_greens_onsite_energies_and_a_spin_without_hops(path):
+    """On-site energies (seeded, both spins) and sectors whose down spin is
+    empty (one string, no hops): 6-site ring, psi in (2, 0), members c_up
+    into (1, 0) and c^dag_down into (2, 1); then psi in (3, 2) with members in
+    all four neighbouring sectors.  Both steppers against the oracle (c128,
+    1e-10)."""
+    lat = ring(6).with_onsite(list(np.random.default_rng(66).uniform(-1.0, 1.0, 6)))
+    p = PulseParams(0, 0.6, 6.0, 0.2, 0.2)
+    for (nu, nd), members in (((2, 0), [(1, 0, 0, 2), (4, 1, 1, 0), (3, 0, 0, 0)]),
+                              ((3, 2), [(0, 0, 0, 1), (2, 0, 1, 0), (5, 1, 0, 2), (1, 1, 1, 3)])):
+        for k, got, ref in _greens_case(lat, 4.0, nu, nd, members, 10, 0.05, p, hub.HUB_C128, 1e-13, path=path):
+            assert np.max(np.abs(got - ref)) < 1e-10, ((nu, nd), k, np.max(np.abs(got - ref)))
+
+
 def test_greens_member_stepper_stops_at_m_max():
     """m_max too small for the tolerance in the members' steps only: at U = 0
     psi = (plane wave k = 1 up) x (plane wave k = 2 down) on the 6-site ring
