@@ -233,3 +233,52 @@ def test_greens_member_stepper_needs_three_term_recurrence():
         B.close()
         for t in T:
             t.close()
+
+
+@pytest.fixture(scope="module")
+def c3_reference():
+    """Oracle overlaps of all 64 members of the 10-site ring workload (c and
+    c^dag of both spins at sites 0, 3, 6, 9 from t' = 0.5, 1.0, 1.5, 2.0) for 6
+    relative steps, psi from a seeded state propagated once to every t'."""
+    w = workloads()["ring10_greens"]
+    ham = HubbardOracle(w.lattice, w.U, 5, 5)
+    psi0 = random_state(ham.dim, seed=11)[0]
+    from oracle.stepper import midpoint_step_exact
+    members = [(site, spin, dagger, int(round(tp / w.dt)))
+               for spin, dagger in ((0, 1), (1, 1), (0, 0), (1, 0))
+               for site in w.extra["sites"] for tp in w.extra["t_primes"]]
+    starts = sorted({m[3] for m in members})
+    psi_at, v = {}, psi0.copy()
+    for n in range(max(starts) + 1):
+        if n in starts:
+            psi_at[n] = v.copy()
+        v = midpoint_step_exact(ham, v, n * w.dt, w.dt, w.pulse)
+    oh, ref = {}, []
+    for site, spin, dagger, st in members:
+        sec = (5 + (1 if dagger else -1), 5) if spin == 0 else (5, 5 + (1 if dagger else -1))
+        if sec not in oh:
+            oh[sec] = HubbardOracle(w.lattice, w.U, *sec)
+        ref.append(greens_diag(ham, psi_at[st], w.pulse, st * w.dt, w.dt, 0, 6, site, spin, bool(dagger),
+                               ham_target=oh[sec]))
+    return w, ham, psi0, members, ref
+
+
+@_PATHS
+def test_greens_ring10_all_64_members(c3_reference, path):
+    """The batched Green's-function configuration at full size: all 64 members
+    in one call (complex64 apply, Krylov tol 1e-8), every member and step
+    against the oracle within 1e-5."""
+    w, ham, psi0, members, ref = c3_reference
+    B = hub.Basis(w.lattice, w.U, 5, 5)
+    hub.hub_set_greens_path(B.handle, path)
+    T = [hub.Basis(w.lattice, w.U, *sec) for sec in [(4, 5), (6, 5), (5, 4), (5, 6)]]
+    try:
+        psi = _dev(to_canonical(psi0, ham.states, 10), torch.complex64)
+        got = hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, 6,
+                                  hub.make_opts(tol=1e-8, m_max=30), members, psi)
+        err = max(float(np.max(np.abs(got[k] - ref[k]))) for k in range(len(members)))
+        assert err < 1e-5, err
+    finally:
+        B.close()
+        for t in T:
+            t.close()
