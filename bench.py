@@ -405,8 +405,8 @@ def controller_c5_variant(hub) -> dict:
     U[0.2, 1.2], omega ~ U[U/2, 2U], pulses centred at t0 = 1.5 with sigma =
     0.5.  Full-batch Adam on the GPU kernels.  Evaluation on held-out 12-site
     pulses (4 draws of another seed, 1000 steps of 0.005 from the ground state,
-    tol 1e-8): steps/s with the learned controller (chunk 16, margin 1), the
-    default chunked schedule and the synchronous one, launches per step,
+    tol 1e-8): steps/s with the learned controller (chunk 16, margin 1 and
+    margin 0), the default chunked schedule and the synchronous one, launches per step,
     fallback rate, and bit-identity of the states and logs with the
     synchronous schedule."""
     import numpy as np
@@ -433,7 +433,7 @@ def controller_c5_variant(hub) -> dict:
     n, dt = 1000, 0.005
     opts = hub.make_opts(tol=tol, m_max=30)
     tot = {k: {"seconds": 0.0, "steps": 0, "fallbacks": 0, "launches": 0, "m": 0.0} for k in
-           ("learned", "default", "synchronous")}
+           ("learned", "learned_margin0", "default", "synchronous")}
     same = True
     for U, mem in controller_groups(4, 1, 13599):
         B = hub.Basis(lat, U, 6, 6)
@@ -442,9 +442,9 @@ def controller_c5_variant(hub) -> dict:
         pulse = (0, mem[0][0], mem[0][1], 1.5, 0.5, 0.0)
         hub.hub_controller_load(B.handle, params)
         ref = None
-        for name in ("synchronous", "default", "learned"):
-            if name == "learned":
-                hub.hub_controller_enable(B.handle, True, chunk, margin)
+        for name in ("synchronous", "default", "learned", "learned_margin0"):
+            if name.startswith("learned"):
+                hub.hub_controller_enable(B.handle, True, chunk, margin if name == "learned" else 0)
             else:
                 hub.hub_controller_enable(B.handle, False)
                 hub.hub_set_schedule(B.handle, 0 if name == "synchronous" else 32, 0 if name == "synchronous" else 1)
@@ -476,8 +476,12 @@ def controller_c5_variant(hub) -> dict:
             res[name]["lanczos_launches_per_step"] = T["launches"] / T["steps"]
             res[name]["fallback_rate"] = T["fallbacks"] / T["steps"]
     res["speedup_learned_vs_default"] = res["learned"]["steps_per_s"] / res["default"]["steps_per_s"]
+    res["speedup_learned_margin0_vs_default"] = res["learned_margin0"]["steps_per_s"] / res["default"]["steps_per_s"]
     res["speedup_learned_vs_synchronous"] = res["learned"]["steps_per_s"] / res["synchronous"]["steps_per_s"]
     res["bit_identical_to_synchronous"] = same
+    print(f"[bench] controller, margin 0: {res['learned_margin0']['steps_per_s']:.0f} steps/s, "
+          f"{res['learned_margin0']['lanczos_launches_per_step']:.2f} launches per step, fallback rate "
+          f"{res['learned_margin0']['fallback_rate']:.3f}", file=sys.stderr, flush=True)
     print(f"[bench] controller (12 sites, held out): learned {res['learned']['steps_per_s']:.0f}, default "
           f"{res['default']['steps_per_s']:.0f}, synchronous {res['synchronous']['steps_per_s']:.0f} steps/s; "
           f"fallback rate {res['learned']['fallback_rate']:.3f}; bit-identical {same}", file=sys.stderr, flush=True)
