@@ -155,3 +155,29 @@ def test_controlled_schedule_stops_at_m_max_like_adaptive(ring8):
     _same(got, ref)
     got = _run(B, pulses, w, v0, torch.complex128, opts, ctl.constant_params(30), allow_nc=True)
     _same(got, ref)
+
+
+def test_trained_network_saves_speculative_launches(ring8, trained):
+    """What the trained network gains over the method without it: on pulses
+    it was not trained on, the learned schedule without a margin enqueues
+    fewer Lanczos launches per step than the default chunked schedule (32
+    steps, margin 1), with at most 5 % of the steps falling back to the
+    adaptive re-run, and the same results bit for bit (launch counts are
+    deterministic; their time is what bench.py's controller variant
+    measures)."""
+    w, B, v0 = ring8
+    opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
+    pulses = [PulseParams(0, a, om, 1.0, 0.3) for a, om in ((0.4, 7.0), (0.8, 10.0))]
+    ref = _run(B, pulses, w, v0, torch.complex128, opts)
+    hub.hub_controller_enable(B.handle, False)
+    hub.hub_set_schedule(B.handle, 32, 1)
+    hub.hub_controller_read_stats(B.handle)
+    v = v0.repeat(len(pulses)).contiguous()
+    st, obs, log = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, w.n_steps, opts, v)
+    dflt = hub.hub_controller_read_stats(B.handle)
+    _same((st, v, obs, log), ref)
+    lrn = _run(B, pulses, w, v0, torch.complex128, opts, trained[0], chunk=16, margin=0)
+    _same(lrn, ref)
+    s = lrn[4]
+    assert s["fallbacks"] <= 0.05 * s["steps"], s
+    assert s["lanczos_launches"] < dflt["lanczos_launches"], (s, dflt)
