@@ -279,9 +279,10 @@ hub_status hub_greens_diag(hub_basis basis, int32_t n_targets, const hub_basis *
  * Lanczos pass); path 1: the persistent member stepper, one launch for all
  * members, each member a workgroup that runs its Lanczos iterations
  * (three-term recurrence, Alg. 6's estimate), its combines and its overlaps
- * for every step, staging tile rows and tile columns in LDS; it needs
- * opts.reorth = 0, opts.substeps = 1 and target sectors with at most 32
- * grouped hop slots per string and a tile row and column of at most 144 KiB,
+ * for every step, with the sector's hop tables and the member's operator map
+ * in LDS beside staged tile rows and tile columns; it needs opts.reorth = 0,
+ * opts.substeps = 1 and target sectors with at most 32 grouped hop slots per
+ * string whose tables plus one tile row (and one tile column) fit 148 KiB,
  * else hub_greens_diag returns HUB_E_INVALID.  path -1 (default): 1 where it
  * applies, every target sector has at most 2^18 states and there are at
  * least as many members as compute units (one workgroup per member runs well
