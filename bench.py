@@ -732,6 +732,28 @@ def greens_variant(hub) -> dict:
         print(f"[bench] greens ({pname}): c64 {r['c64']['member_steps_per_s']:.0f} member-steps/s, c128 "
               f"{r['c128']['member_steps_per_s']:.0f}; |dG| {r['max_abs_overlap_err_c64_vs_c128']:.1e}",
               file=sys.stderr, flush=True)
+    # the per-sector batches again on the committed tuned plans of the target sectors
+    from paper_2005_13498_amd import tuning
+    tab = tuning.load().get(tuning.device_name(), {})
+    if all(tuning.key(t, p) in tab for t in T for p in (hub.HUB_C64, hub.HUB_C128)):
+        hub.hub_set_greens_path(B.handle, 0)
+        r = res["per_sector_tuned"] = {}
+        for name, dtype, prec in (("c64", torch.complex64, hub.HUB_C64), ("c128", torch.complex128, hub.HUB_C128)):
+            for t in T:
+                hub.hub_set_tuning(t.handle, prec, tab[tuning.key(t, prec)])
+            r[name + "_kernels_per_sector"] = plan_label(hub, T[0], prec, len(members) // len(T), True)
+            psi = g.to(dtype).clone()
+            hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, 8, opts, members[:4], psi.clone())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = hub.hub_greens_diag(B.handle, [t.handle for t in T], w.pulse, 0.0, w.dt, n_rel, opts, members, psi)
+            el = time.perf_counter() - t0
+            r[name] = {"seconds": el, "member_steps_per_s": len(members) * n_rel / el,
+                       "max_abs_diff_vs_default_plan": float(np.max(np.abs(o - outs[("per_sector", name)])))}
+            for t in T:
+                hub.hub_set_tuning(t.handle, prec, None)
+        print(f"[bench] greens (per_sector, tuned plans): c64 {r['c64']['member_steps_per_s']:.0f} member-steps/s, "
+              f"c128 {r['c128']['member_steps_per_s']:.0f}", file=sys.stderr, flush=True)
     hub.hub_set_greens_path(B.handle, -1)
     res["max_abs_overlap_diff_between_steppers_c128"] = float(
         np.max(np.abs(outs[("persistent_members", "c128")] - outs[("per_sector", "c128")])))
