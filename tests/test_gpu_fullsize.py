@@ -125,6 +125,33 @@ def test_cluster3x4_trajectory_through_pulse_c64(c2_reference):
         B.close()
 
 
+@pytest.mark.parametrize("dtype,tol,bar", [(torch.complex128, 1e-13, 1e-10), (torch.complex64, 1e-8, 1e-4)])
+def test_cluster3x4_block_trajectory_through_pulse(c2_reference, dtype, tol, bar):
+    """The 12-site trajectory of C2 as one block of 8 on the two-pass block
+    kernels (forced plan): members c_k psi0 with distinct complex c_k (the
+    midpoint stepper is linear and its Krylov decisions do not depend on the
+    norm), each against c_k times the oracle's trajectory."""
+    w, ham, psi0, psi_ref, obs_ref = c2_reference
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
+    try:
+        prec = hub.HUB_C128 if dtype == torch.complex128 else hub.HUB_C64
+        hub.hub_set_tuning(B.handle, prec, {"single_two_pass": 1, "block_two_pass": [0, 1, 1, 1],
+                                            "apply_group": 8, "prop_group": 8})
+        assert hub.hub_get_plan(B.handle, prec, 8, True) == [(8, 2)]
+        cs = [r * np.exp(1j * th) for r in (0.5, 1.0, 1.5, 2.0) for th in (0.0, 1.1)]
+        x0 = to_canonical(psi0, ham.states, 12)
+        v = torch.from_numpy(np.concatenate([c * x0 for c in cs])).to(DEV).to(dtype)
+        st, obs, log = hub.hub_propagate(B.handle, [w.pulse] * 8, C2_T_START, w.dt, C2_STEPS,
+                                         hub.make_opts(tol=tol, m_max=30), v)
+        got = v.to(torch.complex128).cpu().numpy().reshape(8, -1)
+        for k, c in enumerate(cs):
+            assert _rel(from_canonical(got[k], ham.states, 12), c * psi_ref) < bar, k
+        assert log[:, :, 0].max() >= (8 if prec == hub.HUB_C128 else 6)  # the pulse regime at this tolerance
+    finally:
+        B.close()
+        torch.cuda.empty_cache()
+
+
 def test_cluster3x4_observables_match_oracle(c2_reference):
     w, ham, psi0, psi_ref, obs_ref = c2_reference
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
