@@ -189,7 +189,8 @@ hub_status hub_observables_noalloc(hub_basis basis, const double *A, hub_prec pr
 /* One Krylov step (Alg. 6): v_k <- exp(-i dt H(A_mid_k)) v_k for nvec device
  * vectors (in place).  A_mid: host [nvec].  info: host [nvec] or NULL.
  * Returns HUB_E_NOT_CONVERGED if any vector hit m_max (its result is then
- * the m_max approximation, info.converged = 0).  Synchronises `stream`. */
+ * the m_max approximation, info.converged = 0), HUB_E_INVALID if a vector or
+ * its recurrence is not finite (NaN or Inf).  Synchronises `stream`. */
 hub_status hub_krylov_expm_step(hub_basis basis, const double *A_mid, double dt,
                                 const hub_krylov_opts *opts, hub_prec prec, int32_t nvec,
                                 void *v_inout, hub_step_info *info, void *stream);
@@ -199,7 +200,9 @@ hub_status hub_krylov_expm_step(hub_basis basis, const double *A_mid, double dt,
  * [nvec]).  v_inout: device, nvec vectors, in place.  obs: host
  * [(n_steps + 1) * nvec] or NULL: observables at t_start + n dt (row n,
  * column k), with H(t) evaluated at the sample time.  log: host
- * [n_steps * nvec] or NULL.  Returns HUB_E_NOT_CONVERGED (and stops) at the
+ * [n_steps * nvec] or NULL.  Returns HUB_E_INVALID (and stops) at the first
+ * step where a vector or its Krylov recurrence is not finite (NaN or Inf in
+ * the input or produced on the way), and HUB_E_NOT_CONVERGED (and stops) at the
  * first step where a vector hits m_max; v_inout then holds that step's
  * m_max approximation, the obs row after that step holds its observables and
  * later rows are NaN.  The schedule (hub_set_schedule,
@@ -261,8 +264,9 @@ hub_status hub_dot(hub_basis basis, hub_prec prec, int32_t nvec, const void *x, 
  * member runs all its steps in a workgroup of its own.  psi_inout: device
  * vector of `basis` in precision `prec`, advanced in place to t_start + (max
  * start_step + n_rel) dt.  overlaps: host [n_members][n_rel + 1][2].
- * HUB_E_NOT_CONVERGED when a member's step hits m_max (on the persistent
- * stepper that member's later overlaps are NaN).  Synchronises `stream`. */
+ * HUB_E_NOT_CONVERGED when a member's step hits m_max, HUB_E_INVALID when a
+ * member's vector becomes non-finite (on the persistent stepper that member's
+ * later overlaps are NaN).  Synchronises `stream`. */
 typedef struct {
   int32_t site, spin, dagger, start_step;
 } hub_greens_member;

@@ -831,7 +831,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
           int mm;
           step_hist(n + k, v, &e, &mm);
           for (int sub = 0; sub < S; ++sub)
-            maxed |= hlog[(static_cast<size_t>(n + k) * S + sub) * nv + v].status == 3;
+            maxed |= hlog[(static_cast<size_t>(n + k) * S + sub) * nv + v].status >= 3;
           W.cstats.iterations += mm;
         }
       W.cstats.steps += complete;
@@ -841,7 +841,7 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
         for (; k < complete; ++k) {
           bool mk = false;
           for (int sub = 0; sub < S; ++sub)
-            for (int v = 0; v < nv; ++v) mk |= hlog[(static_cast<size_t>(n + k) * S + sub) * nv + v].status == 3;
+            for (int v = 0; v < nv; ++v) mk |= hlog[(static_cast<size_t>(n + k) * S + sub) * nv + v].status >= 3;
           if (mk) break;
         }
         *steps_done = n + k + 1;
@@ -972,8 +972,9 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
           R.m = std::max(R.m, static_cast<int>(c.m));
           R.eps = std::max(R.eps, c.eps);
           R.beta_last = c.beta_last;
-          if (c.status == 3) R.status = 3;
-          else if (c.status == 2 && R.status != 3) R.status = 2;
+          if (c.status == 4) R.status = 4;
+          else if (c.status == 3 && R.status != 4) R.status = 3;
+          else if (c.status == 2 && R.status < 3) R.status = 2;
         }
       }
   }
@@ -1490,9 +1491,13 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
     if (R.ran && R.s != HUB_OK) return fail(R.s, R.err);
 
   bool any_nc = false;
+  int nonfinite_step = -1;
   for (const GroupRun& R : runs) {
     if (!R.ran) continue;
     const int nv = R.nv, k0 = R.k0, done = R.done;
+    for (int n = 0; n < done && nonfinite_step < 0; ++n)
+      for (int v = 0; v < nv; ++v)
+        if (R.reps[static_cast<size_t>(n) * nv + v].status == 4) nonfinite_step = n;
     if (log)
       for (int n = 0; n < done; ++n)
         for (int v = 0; v < nv; ++v) {
@@ -1500,7 +1505,7 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
           hub_step_info& I = log[static_cast<size_t>(n) * nvec + k0 + v];
           I.m_used = P.m;
           I.substeps = o.substeps;
-          I.converged = P.status != 3;
+          I.converged = P.status < 3;
           I.breakdown = P.status == 2;
           I.err_est = P.eps;
           I.beta_last = P.beta_last;
@@ -1518,6 +1523,9 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
     }
     any_nc |= R.ncv;
   }
+  if (nonfinite_step >= 0)
+    return fail(HUB_E_INVALID, "non-finite (NaN or Inf) vector in step " + std::to_string(nonfinite_step) +
+                                   ": the propagation stopped there");
   if (any_nc) return fail(HUB_E_NOT_CONVERGED, "a Krylov step reached m_max before the tolerance");
   return HUB_OK;
 }
@@ -1821,9 +1829,14 @@ hub_status greens_members(hub_basis h, const std::vector<GreensSector>& secs, co
                          hipMemcpyDeviceToHost, st));
   MEMBERS_HIP(hipMemcpyAsync(hstat.data(), stat, hstat.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   MEMBERS_HIP(hipStreamSynchronize(st));
-  bool maxed = false;
+  bool maxed = false, nonfinite = false;
   for (int k = 0; k < n_members; ++k)
-    for (int r = 0; r < n_rel; ++r) maxed |= hstat[static_cast<size_t>(k) * std::max(n_rel, 1) * 2 + r] == 3;
+    for (int r = 0; r < n_rel; ++r) {
+      const int32_t sk = hstat[static_cast<size_t>(k) * std::max(n_rel, 1) * 2 + r];
+      maxed |= sk == 3;
+      nonfinite |= sk == 4;
+    }
+  if (nonfinite) return done(fail(HUB_E_INVALID, "a member's vector became non-finite (NaN or Inf)"));
   if (maxed) return done(fail(HUB_E_NOT_CONVERGED, "a member's Krylov step reached m_max before the tolerance"));
   return done(HUB_OK);
 #undef MEMBERS_HIP

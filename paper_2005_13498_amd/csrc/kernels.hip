@@ -91,8 +91,8 @@ __device__ void record_step(const VecState* st, StepCtl* ctl, CombineLog* log, d
     ctl->iter = 0;
     ctl->steps_done += 1;
     int maxed = 0;
-    for (int w = 0; w < NV; ++w) maxed |= (st[w].status == 3);
-    if (maxed && log) {  // a vector hit m_max: later enqueued steps do nothing
+    for (int w = 0; w < NV; ++w) maxed |= (st[w].status >= 3);
+    if (maxed && log) {  // a vector hit m_max (or went non-finite): later enqueued steps do nothing
       ctl->halt_from = seq + 1;
       ctl->all_done = 1;
     }

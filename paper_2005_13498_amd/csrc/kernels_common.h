@@ -163,10 +163,12 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
     const double b = beta_new[v];
     if (j == 0) {
       if (lane == 0) {
+        // a zero vector stays zero; a NaN or infinite norm stops the run (status 4)
+        const bool fin = isfinite(b);
         S.beta0 = b;
-        S.scale[0] = b > 0.0 ? 1.0 / b : 0.0;
-        S.status = b > 0.0 ? 0 : 2;  // a zero vector stays zero
-        S.m = b > 0.0 ? 0 : 1;
+        S.scale[0] = (fin && b > 0.0) ? 1.0 / b : 0.0;
+        S.status = !fin ? 4 : (b > 0.0 ? 0 : 2);
+        S.m = (fin && b > 0.0) ? 0 : 1;
         S.eps = 0.0;
         S.y[0] = 1.0;
         S.y[1] = 0.0;
@@ -186,7 +188,8 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
       S.eps = eps;
       S.m = j;
       int status = 0;
-      if (b < norm_inf * tol) status = 2;
+      if (!isfinite(b) || !isfinite(eps)) status = 4;  // NaN or Inf in the recurrence
+      else if (b < norm_inf * tol) status = 2;
       else if (eps < tol) status = 1;
       else if (j >= m_max) status = 3;
       S.status = status;
@@ -198,7 +201,7 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
     int done = 1, maxed = 0;
     for (int v = 0; v < NV; ++v) {
       done &= (st[v].status != 0);
-      maxed |= (st[v].status == 3);
+      maxed |= (st[v].status >= 3);  // m_max, or a non-finite vector: the run stops
     }
     ctl->all_done = done;
     ctl->any_maxed = maxed;
@@ -213,10 +216,10 @@ __device__ void krylov_decide(int j, const double* beta_new, VecState* st, StepC
 __device__ inline void krylov_end_at(int j, double b, VecState& S, StepCtl* ctl, double tol, double norm_inf) {
   S.beta[j - 1] = b;
   S.m = j;
-  S.status = b < norm_inf * tol ? 2 : 1;
+  S.status = !isfinite(b) ? 4 : (b < norm_inf * tol ? 2 : 1);
   S.scale[j] = 0.0;
   ctl->all_done = 1;
-  ctl->any_maxed = 0;
+  ctl->any_maxed = S.status == 4;
   ctl->iter = j;
 }
 

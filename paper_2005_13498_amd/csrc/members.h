@@ -40,7 +40,7 @@ struct MemberDesc {
   const int8_t* sgn;
   int down;
   double* out;     // [n_rel + 1][2] overlaps
-  int32_t* status;  // [n_rel] 1 converged, 2 invariant subspace, 3 m_max (the member stops there)
+  int32_t* status;  // [n_rel] 1 converged, 2 invariant subspace, 3 m_max, 4 non-finite (3 and 4 stop the member)
   int32_t* m_used;  // [n_rel]
 };
 

@@ -284,15 +284,16 @@ __global__ __launch_bounds__(kMT) void k_members(MembersArgs P) {
     if (tid < gdn) cf_dn[tid] = V{static_cast<R>(ct[2 * S.dn_gclass[tid]]), static_cast<R>(ct[2 * S.dn_gclass[tid] + 1])};
     if (tid < gup) cf_up[tid] = V{static_cast<R>(ct[2 * S.up_gclass[tid]]), static_cast<R>(ct[2 * S.up_gclass[tid] + 1])};
     const double beta0 = sqrt(n2s);
+    const bool fin0 = isfinite(beta0);
     if (tid == 0) {
-      sh_s[0] = beta0 > 0.0 ? 1.0 / beta0 : 0.0;
+      sh_s[0] = (fin0 && beta0 > 0.0) ? 1.0 / beta0 : 0.0;
       sh_y[0] = 1.0;
       sh_y[1] = 0.0;
-      sh_ctl[1] = beta0 > 0.0 ? 0 : 2;  // a zero state stays zero
+      sh_ctl[1] = !fin0 ? 4 : (beta0 > 0.0 ? 0 : 2);  // a zero state stays zero; NaN or Inf stops the member
     }
     __syncthreads();
     int m = 1;
-    if (beta0 > 0.0) {
+    if (fin0 && beta0 > 0.0) {
       for (int j = 0;; ++j) {
         // row pass: u_j (for j > 0 formed in place as w - alpha_{j-1} s_{j-1}
         // u_{j-1}) and z = D u_j + down hops; at j = m_max only |u_j|
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(kMT) void k_members(MembersArgs P) {
           const double bj = sqrt(msum(nn, red));
           if (tid == 0) {
             sh_b[j - 1] = bj;
-            const int status = bj < S.norm_inf * P.tol ? 2 : (last ? 3 : 0);
+            const int status = !isfinite(bj) ? 4 : (bj < S.norm_inf * P.tol ? 2 : (last ? 3 : 0));
             sh_s[j] = (status == 0 && bj > 0.0) ? 1.0 / bj : 0.0;
             sh_ctl[1] = status;
           }
@@ -328,8 +329,9 @@ __global__ __launch_bounds__(kMT) void k_members(MembersArgs P) {
             sh_y[2 * tid + 1] = yi;
           }
           if (tid == 0) {
-            sh_ctl[0] = eps < P.tol ? 1 : 0;
+            sh_ctl[0] = (eps < P.tol || !isfinite(eps)) ? 1 : 0;
             if (eps < P.tol) sh_ctl[1] = 1;
+            else if (!isfinite(eps)) sh_ctl[1] = 4;
           }
         }
         __syncthreads();
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(kMT) void k_members(MembersArgs P) {
       M.status[s_rel] = status;
       M.m_used[s_rel] = m;
     }
-    if (status == 3) {  // m_max without the tolerance: the member stops, later overlaps are NaN
+    if (status >= 3) {  // m_max without the tolerance, or non-finite: the member stops, later overlaps are NaN
       for (int r = s_rel + 2 + tid; r <= P.n_rel; r += kMT) {
         M.out[2 * r] = __builtin_nan("");
         M.out[2 * r + 1] = __builtin_nan("");

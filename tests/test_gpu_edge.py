@@ -5,7 +5,11 @@
 * a zero vector: every Krylov step breaks down at once (beta_0 = 0) and the
   vector stays exactly zero, with zero observables;
 * a spin sector with a single string (every site occupied by one spin):
-  no hops of that spin, the apply and the midpoint steps against the oracle.
+  no hops of that spin, the apply and the midpoint steps against the oracle;
+* a non-finite input (one NaN or Inf element, in one vector of a group):
+  the propagation stops at its first step with HUB_E_INVALID on both
+  schedules and on the one- and two-pass paths, and so does a single Krylov
+  step and a Green's-function call.
 """
 import numpy as np
 import pytest
@@ -93,3 +97,43 @@ def test_single_string_spin_sector():
         assert np.allclose(obs[:, 0, 3], nd / 6, rtol=1e-10)
     finally:
         B.close()
+
+
+@pytest.mark.parametrize("name,nv,bad", [("ring8", 1, np.nan), ("ring8", 3, np.inf), ("cluster3x4", 1, np.nan),
+                                         ("cluster3x4", 2, np.inf)])
+@pytest.mark.parametrize("chunk", [0, 32])
+def test_non_finite_input_stops_the_run(name, nv, bad, chunk):
+    w = workloads()[name]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        hub.hub_set_schedule(B.handle, chunk, 1 if chunk else 0)
+        x = _vecs(B, nv, 62, torch.complex128)
+        x[(nv - 1) * B.dim + 17] = complex(bad, 0.0)
+        with pytest.raises(hub.HubError) as e:
+            hub.hub_propagate(B.handle, [w.pulse] * nv, 0.0, w.dt, 5, hub.make_opts(tol=1e-10, m_max=30), x)
+        assert e.value.status == hub.HUB_E_INVALID
+        assert "non-finite" in str(e.value)
+    finally:
+        hub.hub_set_schedule(B.handle, 32, 1)
+        B.close()
+
+
+def test_non_finite_single_step_and_greens():
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, 4, 4, device=0)
+    T = [hub.Basis(w.lattice, w.U, 3, 4, device=0)]
+    try:
+        x = _vecs(B, 1, 63, torch.complex64)
+        x[5] = complex(np.nan, 0.0)
+        with pytest.raises(hub.HubError) as e:
+            hub.hub_krylov_expm_step(B.handle, [0.3], w.dt, hub.make_opts(tol=1e-8, m_max=30), x.clone())
+        assert e.value.status == hub.HUB_E_INVALID
+        for path in (0, 1):
+            hub.hub_set_greens_path(B.handle, path)
+            with pytest.raises(hub.HubError) as e:
+                hub.hub_greens_diag(B.handle, [T[0].handle], w.pulse, 0.0, w.dt, 4,
+                                    hub.make_opts(tol=1e-8, m_max=30), [(2, 0, 0, 1)], x.clone())
+            assert e.value.status == hub.HUB_E_INVALID
+    finally:
+        B.close()
+        T[0].close()
