@@ -137,3 +137,29 @@ def test_non_finite_single_step_and_greens():
     finally:
         B.close()
         T[0].close()
+
+
+@pytest.mark.parametrize("name", ["ring8", "cluster3x4"])
+def test_checkpoint_and_resume(name):
+    """A run interrupted after 7 steps, its state copied to the host and back
+    (the checkpoint: psi, t, step), and resumed from t_start + 7 dt gives the
+    uninterrupted 15-step trajectory within rounding (the midpoint times are
+    summed in another order)."""
+    w = workloads()[name]
+    B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    try:
+        opts = hub.make_opts(tol=1e-12, m_max=30)
+        t0 = 2.3 if name == "cluster3x4" else 0.9
+        x = _vecs(B, 1, 64, torch.complex128)
+        full = x.clone()
+        st, obs_full, _ = hub.hub_propagate(B.handle, [w.pulse], t0, w.dt, 15, opts, full)
+        part = x.clone()
+        st, obs_a, _ = hub.hub_propagate(B.handle, [w.pulse], t0, w.dt, 7, opts, part)
+        saved = part.cpu().numpy().copy()  # checkpoint on the host
+        resumed = torch.from_numpy(saved).to(DEV)
+        st, obs_b, _ = hub.hub_propagate(B.handle, [w.pulse], t0 + 7 * w.dt, w.dt, 8, opts, resumed)
+        assert float(torch.linalg.vector_norm(resumed - full)) < 1e-11
+        both = np.concatenate([obs_a[:7], obs_b])
+        assert np.max(np.abs(both[:, 0, 1:] - obs_full[:, 0, 1:])) < 1e-11
+    finally:
+        B.close()
