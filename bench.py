@@ -591,11 +591,13 @@ def large_tile_variant(hub, steps: int = 4) -> dict:
 def ring8_variant(hub) -> dict:
     """The latency case: 8-site ring (U = 8, 4/4, dim 4900) from its ground
     state, 200 steps of 0.01 under the ring pulse, tol 1e-12, complex128
-    (a 157 KB apply: launch- and synchronisation-bound).  Steps/s with the
-    default and the synchronous schedule."""
+    (a 157 KB apply).  Steps/s on the resident stepper (one launch, the
+    default here) and on the launch path with the default and the
+    synchronous schedule; then 64 pulses of the same sweep in one call
+    (member-steps/s) on both paths."""
     import numpy as np
     import torch
-    from synth import workloads
+    from synth import PulseParams, workloads
 
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn)
@@ -603,19 +605,49 @@ def ring8_variant(hub) -> dict:
     hub.hub_ground_state(B.handle, hub.hub_pulse_A(w.pulse, 0.0), g, hub.make_opts(tol=1e-13, m_max=100))
     opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
     res = {"dim": int(B.dim), "steps": w.n_steps}
-    for name, chunk in (("default", None), ("synchronous", 0)):
+
+    def timed(pulses, x0, path, chunk=None):
+        hub.hub_set_propagate_path(B.handle, path)
         if chunk is not None:
             hub.hub_set_schedule(B.handle, chunk, 0)
-        hub.hub_propagate(B.handle, [w.pulse], 0.0, w.dt, w.n_steps, opts, g.clone())  # warm-up
-        x = g.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st, obs, log = hub.hub_propagate(B.handle, [w.pulse], 0.0, w.dt, w.n_steps, opts, x)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        try:
+            hub.hub_propagate(B.handle, pulses, 0.0, w.dt, w.n_steps, opts, x0.clone())  # warm-up
+            x = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, obs, log = hub.hub_propagate(B.handle, pulses, 0.0, w.dt, w.n_steps, opts, x)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        finally:
+            hub.hub_set_schedule(B.handle, 32, 1)
+            hub.hub_set_propagate_path(B.handle, -1)
+        return el, x, obs, log
+
+    el, x_res, obs_res, log = timed([w.pulse], g, 1)
+    res["resident"] = {"steps_per_s": w.n_steps / el, "mean_krylov_m": float(np.mean(log[:, 0, 0])),
+                       "kernels": "one launch for all steps (one workgroup, tile in LDS)"}
+    for name, chunk in (("launches_default", None), ("launches_synchronous", 0)):
+        el, x, obs, log = timed([w.pulse], g, 0, chunk)
         res[name] = {"steps_per_s": w.n_steps / el, "mean_krylov_m": float(np.mean(log[:, 0, 0]))}
-    print(f"[bench] ring8: {res['default']['steps_per_s']:.0f} steps/s (synchronous "
-          f"{res['synchronous']['steps_per_s']:.0f})", file=sys.stderr, flush=True)
+    res["resident_vs_launches_max_abs_psi_diff"] = float(torch.max(torch.abs(x_res - x)).item())
+    res["resident_vs_launches_max_abs_obs_diff"] = float(np.max(np.abs(obs_res[:, :, 1:] - obs[:, :, 1:])))
+    res["speedup_resident_vs_launches_default"] = (res["resident"]["steps_per_s"] /
+                                                   res["launches_default"]["steps_per_s"])
+    # a sweep of 64 amplitudes in one call
+    nb = 64
+    pulses = [PulseParams(0, 0.1 + 0.8 * k / (nb - 1), w.pulse.omega, w.pulse.t0, w.pulse.sigma) for k in range(nb)]
+    xb = g.repeat(nb).contiguous()
+    sweep = {"members": nb}
+    for name, path in (("resident", 1), ("launches", 0)):
+        el, x, obs, log = timed(pulses, xb, path)
+        sweep[name] = {"member_steps_per_s": nb * w.n_steps / el, "seconds": el}
+    sweep["speedup_resident_vs_launches"] = (sweep["resident"]["member_steps_per_s"] /
+                                             sweep["launches"]["member_steps_per_s"])
+    res["sweep64"] = sweep
+    print(f"[bench] ring8: resident {res['resident']['steps_per_s']:.0f} steps/s, launches "
+          f"{res['launches_default']['steps_per_s']:.0f} (synchronous {res['launches_synchronous']['steps_per_s']:.0f});"
+          f" 64-pulse sweep {sweep['resident']['member_steps_per_s']:.0f} vs "
+          f"{sweep['launches']['member_steps_per_s']:.0f} member-steps/s", file=sys.stderr, flush=True)
     B.close()
     return res
 

@@ -219,6 +219,29 @@ hub_status hub_propagate(hub_basis basis, const hub_pulse *pulses, double t_star
                          int32_t nvec, void *v_inout, hub_obs *obs, hub_step_info *log,
                          void *stream);
 
+/* Path of hub_propagate (and hub_krylov_expm_step) on this handle.  path 0:
+ * launches per Lanczos iteration (the kernels above, groups, lanes and the
+ * schedules of hub_set_schedule / hub_controller_enable).  path 1: the
+ * resident stepper, one launch for the whole call and one workgroup per
+ * vector that keeps the vector's tile (with a zero row and column) and the
+ * sector's hop tables in LDS and runs every step: the Lanczos recurrence of
+ * Alg. 6 with its a-posteriori estimate and the same stopping rules, the
+ * combine, and the observables of each step's input at its sample time; only
+ * the Krylov vectors u_1 .. u_{m-1} of a step go to device memory.  It takes
+ * sectors of at most 8,192 states (c128) or 16,384 (c64) whose tile and
+ * tables fit a workgroup's LDS (8 sites at half filling: 4,900 states),
+ * opts.scheme = 0, opts.substeps = 1, opts.reorth = 0, and neither apply
+ * timing (hub_profile_enable) nor the learned controller; else hub_propagate
+ * returns HUB_E_INVALID.  Each vector stops at its own first step that hits
+ * m_max or turns non-finite (its later observables are NaN), as concurrent
+ * groups do on the launch path.  path -1 (default): 1 where it applies, the
+ * apply kernels are automatic (hub_set_apply_path -1) and nvec * 6144 (c128)
+ * or nvec * 8192 (c64) is at least the sector's dimension (one workgroup per
+ * vector runs at one compute unit's LDS rate: a single large vector is
+ * better spread over the GPU), else 0.  Both paths give the same results up
+ * to rounding.  Errors: HUB_E_INVALID. */
+hub_status hub_set_propagate_path(hub_basis basis, int32_t path);
+
 /* Ground state of H(A) (Sec. 3.4 "Ground state"): restarted Lanczos with
  * full reorthogonalisation in FP64 until the residual |H x - E0 x| falls
  * below opts->tol * |H|_inf (opts NULL: tol 1e-12, m_max 60).  v_out:

@@ -53,7 +53,8 @@ EXPORTS = ("hub_basis_create", "hub_basis_destroy", "hub_basis_info", "hub_basis
            "hub_mlp_forward", "hub_mlp_workspace_bytes", "hub_mlp_train_step", "hub_controller_features",
            "hub_controller_load", "hub_controller_enable", "hub_controller_read_stats",
            "hub_set_apply_path", "hub_spectral", "hub_set_schedule", "hub_observables_noalloc",
-           "hub_tune", "hub_set_tuning", "hub_get_plan", "hub_set_greens_path")
+           "hub_tune", "hub_set_tuning", "hub_get_plan", "hub_set_greens_path",
+           "hub_set_propagate_path")
 
 # Controller MLP sizes (HUB_MLP_* in hub.h).
 MLP_IN, MLP_HID, MLP_OUT = 8, 64, 1
@@ -154,6 +155,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hub_controller_read_stats": ([vp, P(hub_controller_stats)], i32),
         "hub_set_apply_path": ([vp, i32], i32),
         "hub_set_greens_path": ([vp, i32], i32),
+        "hub_set_propagate_path": ([vp, i32], i32),
         "hub_set_schedule": ([vp, i32, i32], i32),
         "hub_tune": ([vp, i32, i32, P(hub_tuning), vp], i32),
         "hub_set_tuning": ([vp, i32, P(hub_tuning)], i32),
@@ -487,6 +489,12 @@ def hub_set_greens_path(h, path: int) -> None:
     """hub_greens_diag's member stepper: -1 automatic, 0 per-sector batches,
     1 the persistent one-launch member stepper."""
     _check(load_library().hub_set_greens_path(ctypes.c_void_p(h), int(path)))
+
+
+def hub_set_propagate_path(h, path: int) -> None:
+    """hub_propagate's path: -1 automatic, 0 launches per Lanczos iteration,
+    1 the resident one-launch stepper (small sectors)."""
+    _check(load_library().hub_set_propagate_path(ctypes.c_void_p(h), int(path)))
 
 
 def hub_set_schedule(h, chunk: int, margin: int = 1) -> None:

@@ -25,7 +25,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 HOST_SOURCES = ["basis.cpp", "host_eig.cpp"]
 HIP_SOURCES = ["apply_c128.hip", "apply_c64.hip", "block_c128.hip", "block_c64.hip", "kernels.hip", "mlp.hip",
-               "members.hip", "api.hip"]
+               "members.hip", "resident.hip", "api.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]

@@ -69,6 +69,7 @@ def test_mlp_gradient_and_adam_match_oracle(n_rows):
 def ring8():
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     v0 = torch.empty(B.dim, dtype=torch.complex128, device=DEV)
     hub.hub_ground_state(B.handle, hub.hub_pulse_A(w.pulse, 0.0), v0, hub.make_opts(tol=1e-13, m_max=100))
     yield w, B, v0

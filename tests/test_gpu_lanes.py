@@ -46,6 +46,7 @@ def _check_split(B, pulses, x0, dt, n, opts, splits):
 def test_cluster3x4_single_vector_groups(k):
     w = workloads()["cluster3x4"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         x0 = _members(B, k, 71, torch.complex128)
         hub.hub_controller_read_stats(B.handle)
@@ -59,6 +60,7 @@ def test_cluster3x4_single_vector_groups(k):
 def test_ring8_interleaved_groups(dtype, scheme):
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         x0 = _members(B, 12, 72, dtype)
         opts = hub.make_opts(tol=w.tol, m_max=w.m_max, scheme=scheme)
@@ -70,6 +72,7 @@ def test_ring8_interleaved_groups(dtype, scheme):
 def test_lane_not_converged_is_reported():
     w = workloads()["cluster3x4"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         x0 = _members(B, 3, 73, torch.complex128)
         st, obs, log = hub.hub_propagate(B.handle, _pulses(3), 0.0, 0.05, 3, hub.make_opts(tol=1e-15, m_max=3), x0,

@@ -19,6 +19,7 @@ def _vec(B, seed):
 
 def test_plain_applies_are_all_timed():
     B = hub.Basis(ring(8), 8.0, 4, 4, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         x = _vec(B, 61)
         y = torch.empty_like(x)
@@ -47,6 +48,7 @@ def test_propagation_counts_only_launches_that_work(name, chunk):
     since the column pass of j = m skips its apply."""
     w = workloads()[name]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         x = _vec(B, 62)
         opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
@@ -77,6 +79,7 @@ def test_propagation_with_fallbacks():
     the work, which the re-run repeats)."""
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         x = _vec(B, 63)
         opts = hub.make_opts(tol=1e-14, m_max=40, m_hint=2)

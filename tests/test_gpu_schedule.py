@@ -50,6 +50,7 @@ def _vecs(B, nv, seed, dtype):
 def test_chunked_equals_synchronous_ring8(dtype, nv, chunk, margin):
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         pulses = [w.pulse] + [PulseParams(0, 0.3 + 0.25 * k, 8.0, 1.0, 0.3) for k in range(nv - 1)]
         v0 = _vecs(B, nv, 51, dtype)
@@ -70,6 +71,7 @@ def test_chunked_handles_growing_m():
     where m grows."""
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         v0 = _vecs(B, 1, 52, torch.complex128)
         pulse = PulseParams(0, 1.2, 10.0, 2.0, 0.6)
@@ -87,6 +89,7 @@ def test_chunked_handles_growing_m():
 def test_chunked_with_substeps_and_cfet4(scheme, substeps):
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         v0 = _vecs(B, 2, 53, torch.complex128)
         pulses = [w.pulse, PulseParams(0, 0.8, 7.0, 1.0, 0.3)]
@@ -101,6 +104,7 @@ def test_chunked_with_substeps_and_cfet4(scheme, substeps):
 def test_chunked_stops_at_m_max_like_synchronous():
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         v0 = _vecs(B, 1, 54, torch.complex128)
         opts = hub.make_opts(tol=1e-15, m_max=4)
@@ -117,6 +121,7 @@ def test_chunked_equals_synchronous_cluster3x4_two_pass(dtype):
     """The 12-site tile runs the fused two-pass iterations."""
     w = workloads()["cluster3x4"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         v0 = _vecs(B, 1, 55, dtype)
         opts = hub.make_opts(tol=w.tol, m_max=w.m_max)
@@ -129,6 +134,7 @@ def test_chunked_equals_synchronous_cluster3x4_two_pass(dtype):
 
 def test_schedule_argument_checks():
     B = hub.Basis(ring(6), 4.0, 3, 3, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         for chunk, margin in ((-1, 1), (257, 1), (4, -1), (4, 17)):
             with pytest.raises(hub.HubError):
@@ -147,6 +153,7 @@ def test_stop_at_m_max_reports_the_last_state(path, chunk):
     kernels, synchronous and chunked schedules)."""
     w = workloads()["ring8"]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's own mechanics
     try:
         hub.hub_set_apply_path(B.handle, path)
         v0 = torch.empty(B.dim, dtype=torch.complex128, device=DEV)
