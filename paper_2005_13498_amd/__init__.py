@@ -317,8 +317,15 @@ def hub_observables(h, A: Sequence[float], v, site=False, stream=None, noalloc=F
 _n_sites_cache = {}
 
 
+_INFO_DTYPE = np.dtype([("m_used", np.int32), ("substeps", np.int32), ("converged", np.int32),
+                        ("breakdown", np.int32), ("err_est", np.float64), ("beta_last", np.float64)])
+
+
 def _info_array(info, n):
-    return np.array([(i.m_used, i.substeps, i.converged, i.breakdown, i.err_est, i.beta_last) for i in info[:n]])
+    """[n, 6] float array (m_used, substeps, converged, breakdown, err_est,
+    beta_last) read straight from the ctypes buffer."""
+    rec = np.frombuffer(info, dtype=_INFO_DTYPE, count=n)
+    return np.stack([rec[f].astype(np.float64) for f in _INFO_DTYPE.names], axis=1)
 
 
 def hub_krylov_expm_step(h, A_mid: Sequence[float], dt: float, opts: hub_krylov_opts, v, stream=None,
@@ -346,7 +353,7 @@ def hub_propagate(h, pulses, t_start: float, dt: float, n_steps: int, opts: hub_
                 allow=(HUB_E_NOT_CONVERGED,) if allow_not_converged else ())
     o = None
     if want_obs:
-        o = np.array([[x.t, x.norm, x.energy_per_site, x.docc_per_site] for x in obs]).reshape(n_steps + 1, nvec, 4)
+        o = np.frombuffer(obs, dtype=np.float64).reshape(n_steps + 1, nvec, 4).copy()
     lg = _info_array(log, n_steps * nvec).reshape(n_steps, nvec, 6) if (want_log and n_steps > 0) else None
     return st, o, lg
 

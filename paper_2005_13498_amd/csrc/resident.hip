@@ -144,6 +144,26 @@ __device__ inline double wave_estimate(int J, double a, const double* beta, doub
   return delta < 1.0 ? fmin(1.0 + ny, delta / (1.0 - delta) * ny) : 1.0 + ny;
 }
 
+// The same over staged columns, skipping padding entries (index dim): the
+// lanes of a wavefront mostly share the up string and so its padding, and a
+// padding read of the zero row would cost a full-width LDS access.
+template <typename V>
+__device__ __forceinline__ V slot_sum4_skip(uint2 w, const V* xs, uint32_t dim, int stride) {
+  V s = V{0, 0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t w2 = k < 2 ? w.x : w.y;
+    const uint32_t idx = (k & 1) ? (w2 >> 16) : (w2 & 0xFFFFu);
+    if (idx == dim) continue;
+    const bool neg = idx > dim;
+    const uint32_t src = neg ? idx - dim - 1u : idx;
+    const V t = xs[static_cast<int>(src) * stride];
+    s.x += neg ? -t.x : t.x;
+    s.y += neg ? -t.y : t.y;
+  }
+  return s;
+}
+
 // Hides x's value from the optimiser, so that what is derived from it (LDS
 // and table addresses of a thread's elements) is computed where it is used
 // instead of being kept live in registers across the whole propagation.
@@ -244,7 +264,7 @@ __global__ __launch_bounds__(kRT) void k_resident(ResidentArgs P) {
     const V* col = xs + b;
 #pragma unroll 1
     for (int g = 0; g < gup; ++g) {
-      const V s = slot_sum4(tup[a * gup + g], col, static_cast<uint32_t>(du), ld);
+      const V s = slot_sum4_skip(tup[a * gup + g], col, static_cast<uint32_t>(du), ld);
       if (mid) acc = cfma(cf_up[g], s, acc);
       if (obs) ko = cfma(of_up[g], make_double2(s.x, s.y), ko);
     }
