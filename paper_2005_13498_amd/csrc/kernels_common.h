@@ -94,12 +94,29 @@ template <typename V> __device__ __forceinline__ V cfma(V c, V s, V acc) {
 }
 
 // ---------------------------------------------------------------------------
+// x of lane i - 1 (wave_up) and of lane i + 1 (wave_down), zero past the
+// wavefront's ends (every lane active): whole-wavefront DPP shifts by one
+// lane, wave_shr:1 and wave_shl:1 with out-of-range lanes reading zero, so
+// the neighbour exchange of a tridiagonal product costs no LDS permute.
+__device__ __forceinline__ double wave_up(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_down(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
 // One wavefront: y = exp(-i tau T) e_1 for the j x j real symmetric
 // tridiagonal T.  Taylor series of the action on a vector with scaling,
 // exp(-i tau T) = exp(-i (tau/s) T)^s, s chosen so that |tau/s| |T|_inf <=
 // 1/2; each factor's series is summed until a term falls below 1e-18 of the
-// partial sum.  Lane i holds row i of T (diagonal a, off-diagonals bl left
-// and bu right of it; zero past j) and returns component i of y (j <= 64).
+// partial sum, tested every fourth term (the test's two wave-wide maxima cost
+// more than a term).  Lane i holds row i of T (diagonal a, off-diagonals bl
+// left and bu right of it; zero past j) and returns component i of y
+// (j <= 64).  Every lane of the wavefront must be active.
 __device__ inline void wave_small_expm(int j, double a, double bl, double bu, double tau, int lane, double& yr,
                                        double& yi) {
   const double nrm = wave_max(fabs(a) + fabs(bl) + fabs(bu));
@@ -109,8 +126,8 @@ __device__ inline void wave_small_expm(int j, double a, double bl, double bu, do
   for (int sub = 0; sub < s; ++sub) {
     double tr = zr, ti = zi, sr = zr, si = zi;
     for (int k = 1; k <= 60; ++k) {
-      const double tr_m = __shfl_up(tr, 1), ti_m = __shfl_up(ti, 1);
-      const double tr_p = __shfl_down(tr, 1), ti_p = __shfl_down(ti, 1);
+      const double tr_m = wave_up(tr), ti_m = wave_up(ti);
+      const double tr_p = wave_down(tr), ti_p = wave_down(ti);
       const double ur = a * tr + bl * tr_m + bu * tr_p;
       const double ui = a * ti + bl * ti_m + bu * ti_p;
       const double f = h / k;
@@ -118,9 +135,7 @@ __device__ inline void wave_small_expm(int j, double a, double bl, double bu, do
       ti = -f * ur;
       sr += tr;
       si += ti;
-      const double tm = wave_max(fabs(tr) + fabs(ti));
-      const double sm = wave_max(fabs(sr) + fabs(si));
-      if (tm <= 1e-18 * sm) break;
+      if ((k & 3) == 0 && wave_max(fabs(tr) + fabs(ti)) <= 1e-18 * wave_max(fabs(sr) + fabs(si))) break;
     }
     zr = sr;
     zi = si;

@@ -50,6 +50,26 @@ __device__ __forceinline__ V slot_sum4(uint2 w, const V* xs, uint32_t dim, int s
   return s;
 }
 
+// The same over staged columns, skipping padding entries (index dim): the
+// lanes of a wavefront mostly share the up string and so its padding, and a
+// padding read of the zero row would cost a full-width LDS access.
+template <typename V>
+__device__ __forceinline__ V slot_sum4_skip(uint2 w, const V* xs, uint32_t dim, int stride) {
+  V s = V{0, 0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t w2 = k < 2 ? w.x : w.y;
+    const uint32_t idx = (k & 1) ? (w2 >> 16) : (w2 & 0xFFFFu);
+    if (idx == dim) continue;
+    const bool neg = idx > dim;
+    const uint32_t src = neg ? idx - dim - 1u : idx;
+    const V t = xs[static_cast<int>(src) * stride];
+    s.x += neg ? -t.x : t.x;
+    s.y += neg ? -t.y : t.y;
+  }
+  return s;
+}
+
 // Sums over the workgroup of NQ per-thread values, identical on every
 // thread, fixed order: each wave's butterfly sum, then the kRW wave sums
 // butterflied across lanes (lane l reads wave l % kRW's sum).  lds holds
@@ -82,86 +102,6 @@ __device__ __forceinline__ double block_sum1(double v, double* lds2, int& flip) 
   double q[1] = {v};
   block_sums<1>(q, lds2, flip);
   return q[0];
-}
-
-// x of lane i - 1 (wave_up) and of lane i + 1 (wave_down), zero past the
-// wavefront's ends: whole-wavefront DPP shifts by one lane (wave_shr:1,
-// wave_shl:1 with out-of-range lanes reading zero), so the neighbour
-// exchange of the tridiagonal product stays off the LDS the applies use.
-__device__ __forceinline__ double wave_up(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double wave_down(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-
-// One wavefront: y = exp(-i tau T_J) e_1 for the J x J real symmetric
-// tridiagonal T_J (lane i holds row i: diagonal a, off-diagonals beta[i-1],
-// beta[i]; zero past J) by its Taylor series with scaling, exp(-i tau T) =
-// exp(-i (tau/s) T)^s with |tau/s| |T|_inf <= 1/2, each factor summed until
-// a term falls below 1e-18 of the partial sum, tested every fourth term (the
-// two wave-wide maxima of the test cost more than the terms); then the
-// estimate of Alg. 6 for m = J against y^(J-1) = yprev:
-//   delta = |y^(J) - y^(J-1)| / |y^(J)|,
-//   eps = min(1 + |y|, delta / (1 - delta) |y|), or 1 + |y| if delta >= 1.
-// Lane i returns component i of y^(J) (J <= 64).
-__device__ inline double wave_estimate(int J, double a, const double* beta, double tau, const double* yprev, int lane,
-                                       double& yr, double& yi) {
-  const double bl = (lane >= 1 && lane < J) ? beta[lane - 1] : 0.0;
-  const double bu = (lane + 1 < J) ? beta[lane] : 0.0;
-  const double nrm = wave_max(fabs(a) + fabs(bl) + fabs(bu));
-  const int s = max(1, static_cast<int>(ceil(fabs(tau) * nrm * 2.0)));
-  const double h = tau / s;
-  double zr = lane == 0 ? 1.0 : 0.0, zi = 0.0;
-  for (int sub = 0; sub < s; ++sub) {
-    double tr = zr, ti = zi, sr = zr, si = zi;
-    for (int k = 1; k <= 60; ++k) {
-      const double tr_m = wave_up(tr), ti_m = wave_up(ti);
-      const double tr_p = wave_down(tr), ti_p = wave_down(ti);
-      const double ur = a * tr + bl * tr_m + bu * tr_p;  // (T t)_lane
-      const double ui = a * ti + bl * ti_m + bu * ti_p;
-      const double f = h / k;
-      tr = f * ui;  // (-i f)(ur + i ui)
-      ti = -f * ur;
-      sr += tr;
-      si += ti;
-      if ((k & 3) == 0 && wave_max(fabs(tr) + fabs(ti)) <= 1e-18 * wave_max(fabs(sr) + fabs(si))) break;
-    }
-    zr = sr;
-    zi = si;
-  }
-  yr = zr;
-  yi = zi;
-  const double pr = lane < J - 1 ? yprev[2 * lane] : 0.0;
-  const double pi = lane < J - 1 ? yprev[2 * lane + 1] : 0.0;
-  const double d2 = wave_sum((yr - pr) * (yr - pr) + (yi - pi) * (yi - pi));
-  const double ny = sqrt(wave_sum(yr * yr + yi * yi));
-  const double delta = sqrt(d2) / ny;
-  return delta < 1.0 ? fmin(1.0 + ny, delta / (1.0 - delta) * ny) : 1.0 + ny;
-}
-
-// The same over staged columns, skipping padding entries (index dim): the
-// lanes of a wavefront mostly share the up string and so its padding, and a
-// padding read of the zero row would cost a full-width LDS access.
-template <typename V>
-__device__ __forceinline__ V slot_sum4_skip(uint2 w, const V* xs, uint32_t dim, int stride) {
-  V s = V{0, 0};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t w2 = k < 2 ? w.x : w.y;
-    const uint32_t idx = (k & 1) ? (w2 >> 16) : (w2 & 0xFFFFu);
-    if (idx == dim) continue;
-    const bool neg = idx > dim;
-    const uint32_t src = neg ? idx - dim - 1u : idx;
-    const V t = xs[static_cast<int>(src) * stride];
-    s.x += neg ? -t.x : t.x;
-    s.y += neg ? -t.y : t.y;
-  }
-  return s;
 }
 
 // Hides x's value from the optimiser, so that what is derived from it (LDS
@@ -402,7 +342,7 @@ __global__ __launch_bounds__(kRT) void k_resident(ResidentArgs P) {
       const bool work = isfinite(bj) && bj >= P.norm_inf * P.tol && J < P.m_max;
       if (tid < 64) {
         double yr, yi;
-        const double e = wave_estimate(J, tid < J ? sh_a[tid] : 0.0, sh_b, P.tau, sh_y, tid, yr, yi);
+        const double e = wave_krylov_eps(J, tid < J ? sh_a[tid] : 0.0, sh_b, P.tau, sh_y, tid, yr, yi);
         if (tid < J) {
           sh_y[2 * tid] = yr;
           sh_y[2 * tid + 1] = yi;
