@@ -207,9 +207,12 @@ hub_status hub_krylov_expm_step(hub_basis basis, const double *A_mid, double dt,
  * m_max approximation, the obs row after that step holds its observables and
  * later rows are NaN.  The schedule (hub_set_schedule,
  * hub_controller_enable) changes how the launches overlap the host, never the
- * result.  The library propagates the vectors in groups (interleaved blocks,
- * or single vectors where the two-pass kernels apply); several groups run
- * concurrently on up to 4 lanes, each with its own workspace, stream and host
+ * result.  In small sectors the whole call is one launch of the resident
+ * stepper (hub_set_propagate_path), each vector stopping at its own first
+ * m_max or non-finite step.  Otherwise the library propagates the vectors in
+ * groups (interleaved blocks, or single vectors where the two-pass kernels
+ * apply); several groups run concurrently on up to 4 lanes, each with its
+ * own workspace, stream and host
  * thread, started after the work already on `stream` (not while apply timing
  * or the learned controller is enabled, and not beyond 48 GiB of Krylov
  * workspace).  Results do not depend on this; with concurrent groups each
