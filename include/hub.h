@@ -233,8 +233,9 @@ hub_status hub_propagate(hub_basis basis, const hub_pulse *pulses, double t_star
  * the Krylov vectors u_1 .. u_{m-1} of a step go to device memory.  It takes
  * sectors of at most 8,192 states (c128) or 16,384 (c64) whose tile and
  * tables fit a workgroup's LDS (8 sites at half filling: 4,900 states),
- * opts.scheme = 0, opts.substeps = 1, opts.reorth = 0, and neither apply
- * timing (hub_profile_enable) nor the learned controller; else hub_propagate
+ * opts.reorth = 0 (either scheme, any substeps: the step's Krylov solves run
+ * one after another in the workgroup), and neither apply timing
+ * (hub_profile_enable) nor the learned controller; else hub_propagate
  * returns HUB_E_INVALID.  Each vector stops at its own first step that hits
  * m_max or turns non-finite (its later observables are NaN), as concurrent
  * groups do on the launch path.  path -1 (default): 1 where it applies, the

@@ -1369,12 +1369,11 @@ bool resident_fits(hub_basis h, int pi) {
   return lds <= static_cast<size_t>(hub::resident_lds_limit(pi));
 }
 
-// Options the resident stepper runs as the launch path does: the midpoint
-// scheme, one Krylov solve per step, the three-term recurrence, and none of
-// the launch-path instruments (apply timing, the learned controller's plan,
-// per-step hooks).
+// Options the resident stepper runs as the launch path does: either scheme,
+// any substeps, the three-term recurrence, and none of the launch-path
+// instruments (apply timing, the learned controller's plan, per-step hooks).
 bool resident_options(hub_basis h, const hub_krylov_opts& o, bool controlled, bool hooked) {
-  return o.scheme == 0 && o.substeps == 1 && o.reorth == 0 && !h->prof && !controlled && !hooked;
+  return o.reorth == 0 && !h->prof && !controlled && !hooked;
 }
 
 // hub_propagate on the resident stepper: coefficient tables of every vector
@@ -1382,7 +1381,8 @@ bool resident_options(hub_basis h, const hub_krylov_opts& o, bool controlled, bo
 // run_all gives them.
 hub_status run_resident(hub_basis h, hub_prec prec, int32_t nvec, void* v_inout, int n_steps,
                         const std::vector<std::vector<double>>& A_mid,
-                        const std::vector<std::vector<double>>* A_sample, double t_start, double dt,
+                        const std::vector<std::vector<double>>* A_sample,
+                        const std::vector<std::vector<double>>* A_gauss, double t_start, double dt,
                         const hub_krylov_opts& o, hub_obs* obs, hub_step_info* log, hipStream_t st) {
   const int pi = prec == HUB_C128 ? 0 : 1;
   const size_t es = elem_bytes(prec);
@@ -1392,12 +1392,27 @@ hub_status run_resident(hub_basis h, hub_prec prec, int32_t nvec, void* v_inout,
   Work& W = h->w;
   hub_status s = ensure_workspace(h, W, static_cast<size_t>(D.dim) * nvec * es, o.m_max, 0);
   if (s != HUB_OK) return s;
-  // host tables: [nvec][n_steps][2 nc] midpoint, [nvec][n_steps + 1][2 nc] sample times
-  std::vector<double> cm(std::max<size_t>(1, static_cast<size_t>(nvec) * n_steps * 2 * nc), 0.0);
+  // host tables: [nvec][n_steps][E][2 nc] for the step's exponentials (the
+  // midpoint, or the fourth-order scheme's two Gauss-node combinations as the
+  // launch path forms them), [nvec][n_steps + 1][2 nc] at the sample times
+  const int E = scheme_exps(o);
+  std::vector<double> cm(std::max<size_t>(1, static_cast<size_t>(nvec) * n_steps * E * 2 * nc), 0.0);
   std::vector<double> co(want_obs ? static_cast<size_t>(nvec) * (n_steps + 1) * 2 * nc : 0);
   for (int v = 0; v < nvec; ++v) {
-    for (int n = 0; n < n_steps; ++n)
-      coef_for(h->B, A_mid[v][n], cm.data() + (static_cast<size_t>(v) * n_steps + n) * 2 * nc);
+    for (int n = 0; n < n_steps; ++n) {
+      double* c = cm.data() + (static_cast<size_t>(v) * n_steps + n) * E * 2 * nc;
+      if (E == 1) {
+        coef_for(h->B, A_mid[v][n], c);
+        continue;
+      }
+      double c1[2 * kMaxClasses], c2[2 * kMaxClasses];
+      coef_for(h->B, (*A_gauss)[v][2 * n], c1);
+      coef_for(h->B, (*A_gauss)[v][2 * n + 1], c2);
+      for (int k = 0; k < 2 * nc; ++k) {
+        c[k] = 2.0 * (kCf4A2 * c1[k] + kCf4A1 * c2[k]);           // applied first
+        c[2 * nc + k] = 2.0 * (kCf4A1 * c1[k] + kCf4A2 * c2[k]);
+      }
+    }
     if (want_obs)
       for (int n = 0; n <= n_steps; ++n)
         coef_for(h->B, (*A_sample)[v][n], co.data() + (static_cast<size_t>(v) * (n_steps + 1) + n) * 2 * nc);
@@ -1449,10 +1464,12 @@ hub_status run_resident(hub_basis h, hub_prec prec, int32_t nvec, void* v_inout,
   A.U = D.U;
   A.norm_inf = h->B.norm_inf;
   A.tol = o.tol;
-  A.tau = dt;
+  A.tau = dt / solves_per_step(o);
   A.m_max = o.m_max;
   A.n_steps = n_steps;
   A.nvec = nvec;
+  A.n_exp = E;
+  A.substeps = o.substeps;
   A.coef_mid = dcm;
   A.coef_obs = dco;
   A.v = v_inout;
@@ -1526,15 +1543,15 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
     const bool opts_ok = resident_options(h, o, h->ctrl_on && dA_mid, hook != nullptr);
     const bool fits = resident_fits(h, pi);
     if (h->prop_path == 1 && !(opts_ok && fits))
-      return fail(HUB_E_INVALID, fits ? "the resident stepper takes scheme 0, substeps 1, reorth 0, and no "
-                                        "apply timing, learned controller or step hook"
+      return fail(HUB_E_INVALID, fits ? "the resident stepper takes reorth 0, and no apply timing, learned "
+                                        "controller or step hook"
                                       : "the sector does not fit the resident stepper");
     // automatic: not where the caller chose the apply kernels (hub_set_apply_path),
     // and only for enough vectors per state
     const bool kernels_auto = h->D.two_pass == -1 && h->D.block_path == -1;
     const bool worth = static_cast<int64_t>(nvec) * kResidentAutoElems[pi] >= dim;
     if (opts_ok && fits && (h->prop_path == 1 || (kernels_auto && worth)))
-      return run_resident(h, prec, nvec, v_inout, n_steps, A_mid, A_sample, t_start, dt, o, obs, log, st);
+      return run_resident(h, prec, nvec, v_inout, n_steps, A_mid, A_sample, A_gauss, t_start, dt, o, obs, log, st);
   }
   const std::vector<int> groups = groups_for(h, nvec, pi);
   const bool want_obs = obs != nullptr && A_sample != nullptr;

@@ -15,9 +15,10 @@ namespace hub {
 constexpr int kResidentThreads = 1024;
 constexpr int kResidentEpt[2] = {8, 16};
 
-// One launch propagates nvec vectors of one sector for all their midpoint
-// steps (Eq. (time-stepping)), one workgroup per vector.  Device pointers
-// unless noted.
+// One launch propagates nvec vectors of one sector for all their steps (Eq.
+// (time-stepping), or the fourth-order scheme's two exponentials, each split
+// into equal substeps), one workgroup per vector.  Device pointers unless
+// noted.
 struct ResidentArgs {
   int dim_up, dim_dn, gs_up, gs_dn, nc;
   uint8_t up_gclass[8], dn_gclass[8];  // class of each group of four slots
@@ -27,9 +28,11 @@ struct ResidentArgs {
   const double* eps_dn;
   const uint16_t* up_tab;  // grouped tables [dim_up][gs_up], [dim_dn][gs_dn]
   const uint16_t* dn_tab;
-  double U, norm_inf, tol, tau;
+  double U, norm_inf, tol, tau;  // tau: the length of one Krylov solve, dt / (n_exp substeps)
   int m_max, n_steps, nvec;
-  const double* coef_mid;  // [nvec][n_steps][2 nc]: class coefficients at each step's midpoint
+  int n_exp;     // exponentials per step (1: midpoint rule, 2: the fourth-order commutator-free scheme)
+  int substeps;  // equal Krylov solves per exponential
+  const double* coef_mid;  // [nvec][n_steps][n_exp][2 nc]: class coefficients of each exponential of each step
   const double* coef_obs;  // [nvec][n_steps + 1][2 nc] at the sample times, or null (no observables)
   void* v;                 // [nvec][dim] states, advanced in place
   void* slots;             // [nvec][m_max][dim] Krylov vectors u_1 .. u_{m_max - 1}

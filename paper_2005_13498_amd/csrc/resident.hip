@@ -260,172 +260,188 @@ __global__ __launch_bounds__(kRT) void k_resident(ResidentArgs P) {
 
   V w[EPT], up[EPT];  // w_j and u_{j-1} of this thread's elements
   int done = P.n_steps;
+  const int S = P.n_exp * P.substeps;  // Krylov solves per step, each of length tau
   for (int n = 0; n < P.n_steps; ++n) {
-    load_coefs(P.coef_mid + (static_cast<size_t>(vec) * P.n_steps + n) * 2 * P.nc, false);
-    if (want_obs) load_coefs(obs_row(n), true);
-    // u_0 = psi, staged; beta_0 = |psi|
-    double n2 = 0.0;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      if (ab[e] < 0) continue;
-      const int q = opaque(ab[e]);
-      const V x = psi[gidx(q)];
-      xs[lpos(q)] = x;
-      n2 += static_cast<double>(x.x) * x.x + static_cast<double>(x.y) * x.y;
-    }
-    const double beta0 = sqrt(block_sum1(n2, red, flip));
-    const bool fin0 = isfinite(beta0), live = fin0 && beta0 > 0.0;
-    const R s0 = static_cast<R>(live ? 1.0 / beta0 : 0.0);
-    // iteration 0: w_0 = s_0 H u_0, alpha_0, and the observables of psi(t_n)
-    {
-      double qa = 0.0, qd = 0.0, qo = 0.0, qn = 0.0, qh = 0.0;
-#pragma unroll
+    // the step's log: the largest m and eps of its solves, the last beta, the
+    // worst status (non-finite, then m_max, then invariant subspace)
+    int step_m = 0, step_status = 1;
+    double step_eps = 0.0, step_beta = 0.0;
+    for (int sub = 0; sub < S; ++sub) {
+      const bool obs_now = want_obs && sub == 0;
+      load_coefs(P.coef_mid + ((static_cast<size_t>(vec) * P.n_steps + n) * P.n_exp + sub / P.substeps) * 2 * P.nc,
+                 false);
+      if (obs_now) load_coefs(obs_row(n), true);
+      // u_0 = psi, staged; beta_0 = |psi|
+      double n2 = 0.0;
+  #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         if (ab[e] < 0) continue;
         const int q = opaque(ab[e]);
-        const V x = xs[lpos(q)];
-        V acc;
-        double2 ko;
-        double dg, nd;
-        hx(q, x, true, want_obs, acc, ko, dg, nd);
-        const V out = V{acc.x * s0, acc.y * s0};
-        w[e] = out;
-        qa += static_cast<double>(s0) * (static_cast<double>(x.x) * out.x + static_cast<double>(x.y) * out.y);
-        if (want_obs) {
-          const double m2 = static_cast<double>(x.x) * x.x + static_cast<double>(x.y) * x.y;
-          qd += dg * m2;
-          qo += nd * m2;
-          qn += m2;
-          qh += static_cast<double>(x.x) * ko.x + static_cast<double>(x.y) * ko.y;
-        }
+        const V x = psi[gidx(q)];
+        xs[lpos(q)] = x;
+        n2 += static_cast<double>(x.x) * x.x + static_cast<double>(x.y) * x.y;
       }
-      double q[1 + kObsQ] = {qa, qd, qo, qn, qh};
-      block_sums<1 + kObsQ>(q, red, flip);
-      const double a0 = q[0];
-      if (want_obs && tid == 0) {
-        double* o = P.obs + (static_cast<size_t>(n) * P.nvec + vec) * kObsQ;
-#pragma unroll
-        for (int k = 0; k < kObsQ; ++k) o[k] = q[1 + k];
-      }
-      if (tid == 0) {
-        sh_a[0] = a0;
-        sh_s[0] = static_cast<double>(s0);
-        sh_y[0] = 1.0;
-        sh_y[1] = 0.0;
-      }
-      __syncthreads();
-    }
-    // a zero state stays zero (m = 1, invariant subspace); NaN or Inf stops the vector
-    int m = 1, status = live ? 0 : (fin0 ? 2 : 4);
-    double eps = 0.0, blast = 0.0;
-    for (int j = 0; live; ++j) {
-      const int J = j + 1;
-      // u_J = w_j - alpha_j s_j u_j, staged in place of u_j
-      const R c = static_cast<R>(sh_a[j] * sh_s[j]);
-      double nn = 0.0;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        if (ab[e] < 0) continue;
-        const int p = lpos(opaque(ab[e]));
-        const V u = xs[p];
-        V t = w[e];
-        t.x -= c * u.x;
-        t.y -= c * u.y;
-        xs[p] = t;
-        up[e] = u;
-        nn += static_cast<double>(t.x) * t.x + static_cast<double>(t.y) * t.y;
-      }
-      const double bj = sqrt(block_sum1(nn, red, flip));
-      // Iteration J's apply is needed unless beta_{J-1} = |u_J| or J = m_max
-      // ends the step; it runs while wavefront 0 evaluates the estimate for
-      // m = J (T_J: alpha_0..j, beta_0..j-1), and is discarded if that ends it.
-      const bool work = isfinite(bj) && bj >= P.norm_inf * P.tol && J < P.m_max;
-      if (tid < 64) {
-        double yr, yi;
-        const double e = wave_krylov_eps(J, tid < J ? sh_a[tid] : 0.0, sh_b, P.tau, sh_y, tid, yr, yi);
-        if (tid < J) {
-          sh_y[2 * tid] = yr;
-          sh_y[2 * tid + 1] = yi;
-        }
-        if (tid == 0) {
-          sh_eps = e;
-          sh_b[j] = bj;
-          sh_s[J] = work ? 1.0 / bj : 0.0;
-        }
-      }
-      double qa = 0.0;
-      if (work) {
-        const R sJ = static_cast<R>(1.0 / bj), bp = static_cast<R>(bj * sh_s[j]);
-#pragma unroll
+      const double beta0 = sqrt(block_sum1(n2, red, flip));
+      const bool fin0 = isfinite(beta0), live = fin0 && beta0 > 0.0;
+      const R s0 = static_cast<R>(live ? 1.0 / beta0 : 0.0);
+      // iteration 0: w_0 = s_0 H u_0, alpha_0, and the observables of psi(t_n)
+      {
+        double qa = 0.0, qd = 0.0, qo = 0.0, qn = 0.0, qh = 0.0;
+  #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           if (ab[e] < 0) continue;
           const int q = opaque(ab[e]);
           const V x = xs[lpos(q)];
-          slot(J)[gidx(q)] = x;  // u_J for the combine
           V acc;
           double2 ko;
           double dg, nd;
-          hx(q, x, true, false, acc, ko, dg, nd);
-          V out = acc;
-          out.x = out.x * sJ - bp * up[e].x;
-          out.y = out.y * sJ - bp * up[e].y;
+          hx(q, x, true, obs_now, acc, ko, dg, nd);
+          const V out = V{acc.x * s0, acc.y * s0};
           w[e] = out;
-          qa += static_cast<double>(sJ) * (static_cast<double>(x.x) * out.x + static_cast<double>(x.y) * out.y);
+          qa += static_cast<double>(s0) * (static_cast<double>(x.x) * out.x + static_cast<double>(x.y) * out.y);
+          if (obs_now) {
+            const double m2 = static_cast<double>(x.x) * x.x + static_cast<double>(x.y) * x.y;
+            qd += dg * m2;
+            qo += nd * m2;
+            qn += m2;
+            qh += static_cast<double>(x.x) * ko.x + static_cast<double>(x.y) * ko.y;
+          }
         }
+        double q[1 + kObsQ] = {qa, qd, qo, qn, qh};
+        block_sums<1 + kObsQ>(q, red, flip);
+        const double a0 = q[0];
+        if (obs_now && tid == 0) {
+          double* o = P.obs + (static_cast<size_t>(n) * P.nvec + vec) * kObsQ;
+  #pragma unroll
+          for (int k = 0; k < kObsQ; ++k) o[k] = q[1 + k];
+        }
+        if (tid == 0) {
+          sh_a[0] = a0;
+          sh_s[0] = static_cast<double>(s0);
+          sh_y[0] = 1.0;
+          sh_y[1] = 0.0;
+        }
+        __syncthreads();
       }
-      const double aJ = block_sum1(qa, red, flip);  // also publishes the estimate
-      const double ej = sh_eps;
-      int st = 0;
-      if (!isfinite(bj) || !isfinite(ej)) st = 4;
-      else if (bj < P.norm_inf * P.tol) st = 2;
-      else if (ej < P.tol) st = 1;
-      else if (J >= P.m_max) st = 3;
-      if (st != 0) {
-        m = J;
-        status = st;
-        eps = ej;
-        blast = bj;
-        break;
-      }
-      if (tid == 0) sh_a[J] = aJ;
-      __syncthreads();
-    }
-    // psi <- beta_0 sum_{k < m} y_k s_k u_k (u_0 = psi itself), the loads of
-    // one Krylov vector for all of the thread's elements in flight together
-    if (tid < m) {
-      sh_c[2 * tid] = beta0 * sh_s[tid] * sh_y[2 * tid];
-      sh_c[2 * tid + 1] = beta0 * sh_s[tid] * sh_y[2 * tid + 1];
-    }
-    __syncthreads();
-    {
-      double ar[EPT], ai[EPT];
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) ar[e] = ai[e] = 0.0;
-      for (int k = 0; k < m; ++k) {
-        const V* __restrict__ sk = slot(k);
-        const double cr = sh_c[2 * k], ci = sh_c[2 * k + 1];
-        V u[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) u[e] = ab[e] >= 0 ? sk[gidx(opaque(ab[e]))] : V{0, 0};
-#pragma unroll
+      // a zero state stays zero (m = 1, invariant subspace); NaN or Inf stops the vector
+      int m = 1, status = live ? 0 : (fin0 ? 2 : 4);
+      double eps = 0.0, blast = 0.0;
+      for (int j = 0; live; ++j) {
+        const int J = j + 1;
+        // u_J = w_j - alpha_j s_j u_j, staged in place of u_j
+        const R c = static_cast<R>(sh_a[j] * sh_s[j]);
+        double nn = 0.0;
+  #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-          ar[e] += cr * u[e].x - ci * u[e].y;
-          ai[e] += cr * u[e].y + ci * u[e].x;
+          if (ab[e] < 0) continue;
+          const int p = lpos(opaque(ab[e]));
+          const V u = xs[p];
+          V t = w[e];
+          t.x -= c * u.x;
+          t.y -= c * u.y;
+          xs[p] = t;
+          up[e] = u;
+          nn += static_cast<double>(t.x) * t.x + static_cast<double>(t.y) * t.y;
         }
+        const double bj = sqrt(block_sum1(nn, red, flip));
+        // Iteration J's apply is needed unless beta_{J-1} = |u_J| or J = m_max
+        // ends the step; it runs while wavefront 0 evaluates the estimate for
+        // m = J (T_J: alpha_0..j, beta_0..j-1), and is discarded if that ends it.
+        const bool work = isfinite(bj) && bj >= P.norm_inf * P.tol && J < P.m_max;
+        if (tid < 64) {
+          double yr, yi;
+          const double e = wave_krylov_eps(J, tid < J ? sh_a[tid] : 0.0, sh_b, P.tau, sh_y, tid, yr, yi);
+          if (tid < J) {
+            sh_y[2 * tid] = yr;
+            sh_y[2 * tid + 1] = yi;
+          }
+          if (tid == 0) {
+            sh_eps = e;
+            sh_b[j] = bj;
+            sh_s[J] = work ? 1.0 / bj : 0.0;
+          }
+        }
+        double qa = 0.0;
+        if (work) {
+          const R sJ = static_cast<R>(1.0 / bj), bp = static_cast<R>(bj * sh_s[j]);
+  #pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            if (ab[e] < 0) continue;
+            const int q = opaque(ab[e]);
+            const V x = xs[lpos(q)];
+            slot(J)[gidx(q)] = x;  // u_J for the combine
+            V acc;
+            double2 ko;
+            double dg, nd;
+            hx(q, x, true, false, acc, ko, dg, nd);
+            V out = acc;
+            out.x = out.x * sJ - bp * up[e].x;
+            out.y = out.y * sJ - bp * up[e].y;
+            w[e] = out;
+            qa += static_cast<double>(sJ) * (static_cast<double>(x.x) * out.x + static_cast<double>(x.y) * out.y);
+          }
+        }
+        const double aJ = block_sum1(qa, red, flip);  // also publishes the estimate
+        const double ej = sh_eps;
+        int st = 0;
+        if (!isfinite(bj) || !isfinite(ej)) st = 4;
+        else if (bj < P.norm_inf * P.tol) st = 2;
+        else if (ej < P.tol) st = 1;
+        else if (J >= P.m_max) st = 3;
+        if (st != 0) {
+          m = J;
+          status = st;
+          eps = ej;
+          blast = bj;
+          break;
+        }
+        if (tid == 0) sh_a[J] = aJ;
+        __syncthreads();
       }
-#pragma unroll
-      for (int e = 0; e < EPT; ++e)
-        if (ab[e] >= 0) psi[gidx(opaque(ab[e]))] = V{static_cast<R>(ar[e]), static_cast<R>(ai[e])};
+      // psi <- beta_0 sum_{k < m} y_k s_k u_k (u_0 = psi itself), the loads of
+      // one Krylov vector for all of the thread's elements in flight together
+      if (tid < m) {
+        sh_c[2 * tid] = beta0 * sh_s[tid] * sh_y[2 * tid];
+        sh_c[2 * tid + 1] = beta0 * sh_s[tid] * sh_y[2 * tid + 1];
+      }
+      __syncthreads();
+      {
+        double ar[EPT], ai[EPT];
+  #pragma unroll
+        for (int e = 0; e < EPT; ++e) ar[e] = ai[e] = 0.0;
+        for (int k = 0; k < m; ++k) {
+          const V* __restrict__ sk = slot(k);
+          const double cr = sh_c[2 * k], ci = sh_c[2 * k + 1];
+          V u[EPT];
+  #pragma unroll
+          for (int e = 0; e < EPT; ++e) u[e] = ab[e] >= 0 ? sk[gidx(opaque(ab[e]))] : V{0, 0};
+  #pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            ar[e] += cr * u[e].x - ci * u[e].y;
+            ai[e] += cr * u[e].y + ci * u[e].x;
+          }
+        }
+  #pragma unroll
+        for (int e = 0; e < EPT; ++e)
+          if (ab[e] >= 0) psi[gidx(opaque(ab[e]))] = V{static_cast<R>(ar[e]), static_cast<R>(ai[e])};
+      }
+      step_m = max(step_m, m);
+      step_eps = fmax(step_eps, eps);
+      step_beta = blast;
+      if (status == 4) step_status = 4;
+      else if (status == 3 && step_status != 4) step_status = 3;
+      else if (status == 2 && step_status < 3) step_status = 2;
+      __syncthreads();  // the next solve restages the tile and reloads the coefficients
+      if (status >= 3) break;  // m_max without the tolerance, or non-finite: this vector stops here
     }
     if (tid == 0) {
       CombineLog& L = P.log[static_cast<size_t>(n) * P.nvec + vec];
-      L.m = m;
-      L.status = status;
-      L.eps = eps;
-      L.beta_last = blast;
+      L.m = step_m;
+      L.status = step_status;
+      L.eps = step_eps;
+      L.beta_last = step_beta;
     }
-    __syncthreads();  // the next step restages the tile and reloads the coefficients
-    if (status >= 3) {  // m_max without the tolerance, or non-finite: this vector stops here
+    if (step_status >= 3) {
       done = n + 1;
       break;
     }

@@ -62,6 +62,7 @@ def test_cfet4_controller_bit_identical(setup):
     w, ham, B, v0, psi_ref, ref, dt = setup
     opts = hub.make_opts(tol=1e-12, m_max=30, scheme=1)
     outs = []
+    hub.hub_set_propagate_path(B.handle, 0)  # the launch path's schedules
     for params in (None, ctl.constant_params(3), ctl.constant_params(12)):
         x = v0.clone()
         if params is not None:
@@ -72,6 +73,7 @@ def test_cfet4_controller_bit_identical(setup):
         finally:
             hub.hub_controller_enable(B.handle, False)
         outs.append((x, obs, log))
+    hub.hub_set_propagate_path(B.handle, -1)
     for x, obs, log in outs[1:]:
         assert torch.equal(x, outs[0][0])
         assert np.array_equal(obs, outs[0][1]) and np.array_equal(log, outs[0][2])

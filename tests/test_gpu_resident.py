@@ -11,6 +11,8 @@ one workgroup with its tile in LDS.  It must reproduce:
   Krylov dimension of every step, for single vectors and batches with
   different pulses, across its instantiations (1 to 16 elements per thread,
   ragged tiles up to 15,876 states);
+* the fourth-order scheme and substeps (several Krylov solves per step)
+  against the launch path and the oracle's exact exponentials;
 * the stopping rules: m_max (HUB_E_NOT_CONVERGED, that step's approximation
   kept, later observables NaN), a non-finite input (HUB_E_INVALID), a zero
   vector (stays zero), no steps (observables of the input only);
@@ -83,6 +85,56 @@ def test_resident_matches_launch_path(lat, U, nu, nd, dtype, nv, n):
         same_m = np.mean(l1[:, :, 0] == l0[:, :, 0])
         assert same_m == 1.0 if c128 else same_m >= 0.9, same_m
         assert (l1[:, :, 2] == 1).all() and (l1[:, :, 5] > 0).all()
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("dtype,scheme,subs", [(torch.complex128, 1, 1), (torch.complex128, 0, 3),
+                                               (torch.complex128, 1, 2), (torch.complex64, 1, 1)])
+def test_resident_substeps_and_fourth_order_match_launch_path(dtype, scheme, subs):
+    """The fourth-order scheme (two exponentials per step) and substeps (equal
+    Krylov solves per exponential) on both paths: states, observables, the
+    per-step log (largest m of the solves)."""
+    B = hub.Basis(ring(8), 8.0, 4, 4, device=0)
+    try:
+        x0 = _vecs(B.dim, 2, 102, dtype)
+        c128 = dtype == torch.complex128
+        opts = hub.make_opts(tol=1e-12 if c128 else 1e-7, m_max=30, scheme=scheme, substeps=subs)
+        _, v0, o0, l0 = _run(B, 0, _pulses(2), x0, 0.04, 20, opts)
+        _, v1, o1, l1 = _run(B, 1, _pulses(2), x0, 0.04, 20, opts)
+        bar = 1e-12 if c128 else 1e-5
+        a, b = v1.cpu().numpy().reshape(2, -1), v0.cpu().numpy().reshape(2, -1)
+        for k in range(2):
+            assert np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k]) < bar
+        assert np.max(np.abs(o1[:, :, 1:] - o0[:, :, 1:])) < bar
+        same_m = np.mean(l1[:, :, 0] == l0[:, :, 0])
+        assert same_m == 1.0 if c128 else same_m >= 0.9, same_m
+        assert (l1[:, :, 1] == subs).all() and (l1[:, :, 2] == 1).all()
+    finally:
+        B.close()
+
+
+def test_resident_fourth_order_matches_oracle():
+    """The fourth-order scheme on the resident stepper against the oracle's
+    exact exponentials of the same scheme (7-site chain with on-site
+    energies)."""
+    from oracle.stepper import cfet4_step_exact
+    lat = chain(7).with_onsite([0.3, -0.2, 0.0, 0.5, 0.1, -0.4, 0.2])
+    U, nu, nd = 3.0, 3, 4
+    ham = HubbardOracle(lat, U, nu, nd)
+    B = hub.Basis(lat, U, nu, nd, device=0)
+    try:
+        p = PulseParams(0, 0.6, 5.0, 0.3, 0.2)
+        psi = random_state(ham.dim, seed=103)[0]
+        n, dt = 15, 0.04
+        v = psi.copy()
+        for k in range(n):
+            v = cfet4_step_exact(ham, v, k * dt, dt, p)
+        x = torch.from_numpy(to_canonical(psi, ham.states, lat.n_sites)).to(DEV)
+        hub.hub_set_propagate_path(B.handle, 1)
+        hub.hub_propagate(B.handle, [p], 0.0, dt, n, hub.make_opts(tol=1e-13, m_max=40, scheme=1), x)
+        got = from_canonical(x.cpu().numpy(), ham.states, lat.n_sites)
+        assert np.linalg.norm(got - v) / np.linalg.norm(v) < 1e-10
     finally:
         B.close()
 
@@ -215,11 +267,10 @@ def test_resident_forced_path_checks():
     try:
         x = _vecs(B.dim, 1, 99, torch.complex128)
         hub.hub_set_propagate_path(B.handle, 1)
-        for opts in (hub.make_opts(tol=1e-10, m_max=30, reorth=1), hub.make_opts(tol=1e-10, m_max=30, substeps=2),
-                     hub.make_opts(tol=1e-10, m_max=30, scheme=1)):
-            with pytest.raises(hub.HubError) as e:
-                hub.hub_propagate(B.handle, [PulseParams(0, 0.5, 8.0, 0.1, 0.3)], 0.0, 0.01, 2, opts, x.clone())
-            assert e.value.status == hub.HUB_E_INVALID
+        with pytest.raises(hub.HubError) as e:
+            hub.hub_propagate(B.handle, [PulseParams(0, 0.5, 8.0, 0.1, 0.3)], 0.0, 0.01, 2,
+                              hub.make_opts(tol=1e-10, m_max=30, reorth=1), x.clone())
+        assert e.value.status == hub.HUB_E_INVALID
         hub.hub_set_propagate_path(big.handle, 1)
         y = _vecs(big.dim, 1, 100, torch.complex128)
         with pytest.raises(hub.HubError) as e:
