@@ -239,8 +239,8 @@ hub_status hub_propagate(hub_basis basis, const hub_pulse *pulses, double t_star
  * returns HUB_E_INVALID.  Each vector stops at its own first step that hits
  * m_max or turns non-finite (its later observables are NaN), as concurrent
  * groups do on the launch path.  path -1 (default): 1 where it applies, the
- * apply kernels are automatic (hub_set_apply_path -1) and nvec * 6144 (c128)
- * or nvec * 8192 (c64) is at least the sector's dimension (one workgroup per
+ * apply kernels are automatic (hub_set_apply_path -1) and nvec * 6144 is at
+ * least the sector's dimension (one workgroup per
  * vector runs at one compute unit's LDS rate: a single large vector is
  * better spread over the GPU), else 0.  Both paths give the same results up
  * to rounding.  Errors: HUB_E_INVALID. */

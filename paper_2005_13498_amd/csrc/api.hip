@@ -1349,13 +1349,13 @@ hub_status hub_observables_noalloc(hub_basis h, const double* A, hub_prec prec, 
 namespace {
 
 // Automatic choice of the resident stepper: nvec vectors of dim states run
-// there when nvec * kResidentAutoElems[prec] >= dim.  One workgroup per vector
-// runs at a compute unit's LDS rate, so a single large vector is better
-// spread over the GPU one launch at a time (measured, steps/s resident vs
-// launches: 6-site 400 states 2.6x, 8-site 4,900 states 1.27x (c128) and
-// 1.45x (c64), 9-site 7,056 states 0.82x (c128, 1.00x with 2 vectors, 1.17x
-// with 4) and 1.06x (c64); batches of 64 vectors 3-7x).
-constexpr int64_t kResidentAutoElems[2] = {6144, 8192};
+// there when nvec * kResidentAutoElems >= dim.  One workgroup per vector runs
+// at a compute unit's rate, so a single large vector is better spread over
+// the GPU one launch at a time (measured, steps/s resident vs launches, one
+// vector: 6-site 400 states 2.3x, 8-site 4,900 states 1.13-1.16x (c128) and
+// 1.27x (c64), 9-site 7,056 states 0.76x (c128; 1.11x with 4 vectors) and
+// 0.95x (c64); batches of 64 vectors 3-9x).
+constexpr int64_t kResidentAutoElems = 6144;
 
 // The resident stepper takes the sector: one workgroup's threads own every
 // state and the tile with the tables fits its LDS.
@@ -1549,7 +1549,7 @@ static hub_status run_all(hub_basis h, hub_prec prec, int32_t nvec, void* v_inou
     // automatic: not where the caller chose the apply kernels (hub_set_apply_path),
     // and only for enough vectors per state
     const bool kernels_auto = h->D.two_pass == -1 && h->D.block_path == -1;
-    const bool worth = static_cast<int64_t>(nvec) * kResidentAutoElems[pi] >= dim;
+    const bool worth = static_cast<int64_t>(nvec) * kResidentAutoElems >= dim;
     if (opts_ok && fits && (h->prop_path == 1 || (kernels_auto && worth)))
       return run_resident(h, prec, nvec, v_inout, n_steps, A_mid, A_sample, A_gauss, t_start, dt, o, obs, log, st);
   }

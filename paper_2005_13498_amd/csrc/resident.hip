@@ -195,14 +195,14 @@ __global__ __launch_bounds__(kRT) void k_resident(ResidentArgs P) {
     acc = V{static_cast<R>(dg) * x.x, static_cast<R>(dg) * x.y};
     ko = make_double2(0.0, 0.0);
     const V* row = xs + a * ld;
-#pragma unroll 1
+#pragma unroll 2
     for (int g = 0; g < gdn; ++g) {
       const V s = slot_sum4(tdn[b * gdn + g], row, static_cast<uint32_t>(dd), 1);
       if (mid) acc = cfma(cf_dn[g], s, acc);
       if (obs) ko = cfma(of_dn[g], make_double2(s.x, s.y), ko);
     }
     const V* col = xs + b;
-#pragma unroll 1
+#pragma unroll 2
     for (int g = 0; g < gup; ++g) {
       const V s = slot_sum4_skip(tup[a * gup + g], col, static_cast<uint32_t>(du), ld);
       if (mid) acc = cfma(cf_up[g], s, acc);

@@ -17,8 +17,8 @@ one workgroup with its tile in LDS.  It must reproduce:
   kept, later observables NaN), a non-finite input (HUB_E_INVALID), a zero
   vector (stays zero), no steps (observables of the input only);
 * the argument checks of a forced path, and the automatic choice (the
-  resident stepper where nvec * 6144 (c128) or nvec * 8192 (c64) covers the
-  sector's dimension, the launch path otherwise: seen in the launch counters).
+  resident stepper where nvec * 6144 covers the sector's dimension, the
+  launch path otherwise: seen in the launch counters).
 """
 import numpy as np
 import pytest
@@ -289,7 +289,7 @@ def test_resident_forced_path_checks():
     (ring(8), 4, 4, torch.complex128, 1, True),      # 4,900 states
     (ring(9), 3, 3, torch.complex128, 1, False),     # 7,056 states, one vector
     (ring(9), 3, 3, torch.complex128, 2, True),
-    (ring(9), 3, 3, torch.complex64, 1, True),
+    (ring(9), 3, 3, torch.complex64, 1, False),
     (ring(10), 5, 5, torch.complex128, 16, False),   # does not fit
 ])
 def test_resident_automatic_choice(lat, nu, nd, dtype, nv, resident):
