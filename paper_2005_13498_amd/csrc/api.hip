@@ -2627,9 +2627,13 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const DevBasis saved = h->D;
   const int saved_ag = h->apply_group[pi], saved_pg = h->prop_group[pi];
+  // the plans are the launch path's: its propagations are timed, not the resident stepper's
+  const int saved_path = h->prop_path;
+  h->prop_path = 0;
   auto done = [&](hub_status r) {
     h->D = saved;
     h->force_group = 0;
+    h->prop_path = saved_path;
     if (r != HUB_OK) {
       h->apply_group[pi] = saved_ag;
       h->prop_group[pi] = saved_pg;
@@ -2640,6 +2644,12 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
     if (e1) (void)hipEventDestroy(e1);
     return r;
   };
+  // a failed HIP call restores the handle and frees the buffers before it returns
+#define TUNE_HIP(call)                                                                                     \
+  do {                                                                                                     \
+    const hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess) return done(fail(HUB_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
+  } while (0)
   if (hipMalloc(&x, static_cast<size_t>(dim) * kN * es) != hipSuccess ||
       hipMalloc(&y, static_cast<size_t>(dim) * kN * es) != hipSuccess)
     return done(fail(HUB_E_NOMEM, "tuning buffers"));
@@ -2658,13 +2668,13 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
       h->force_group = g;
       for (int r = 0; r < 2; ++r)
         if ((s = hub_apply_H(h, A, prec, kN, x, y, stream)) != HUB_OK) return done(s);
-      HUB_HIP(hipEventRecord(e0, st));
+      TUNE_HIP(hipEventRecord(e0, st));
       for (int r = 0; r < reps; ++r)
         if ((s = hub_apply_H(h, A, prec, kN, x, y, stream)) != HUB_OK) return done(s);
-      HUB_HIP(hipEventRecord(e1, st));
-      HUB_HIP(hipEventSynchronize(e1));
+      TUNE_HIP(hipEventRecord(e1, st));
+      TUNE_HIP(hipEventSynchronize(e1));
       float ms = 0.0f;
-      HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
+      TUNE_HIP(hipEventElapsedTime(&ms, e0, e1));
       T.apply_us[gidx(g)][path] = 1e3 * ms / (static_cast<double>(reps) * kN);
     }
   auto best_path = [&](int g) {
@@ -2703,10 +2713,10 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
     h->force_group = g;
     if (hub::launch_fill_probe(pi, dim * kN, x, st) != hipSuccess) return done(fail(HUB_E_DEVICE, "fill kernel"));
     if ((s = run_all(h, prec, kN, x, 1, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream)) != HUB_OK) return done(s);
-    HUB_HIP(hipStreamSynchronize(st));
+    TUNE_HIP(hipStreamSynchronize(st));
     const auto t0 = std::chrono::steady_clock::now();
     if ((s = run_all(h, prec, kN, x, 2, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream)) != HUB_OK) return done(s);
-    HUB_HIP(hipStreamSynchronize(st));
+    TUNE_HIP(hipStreamSynchronize(st));
     const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     T.step_us[gidx(g)] = us / (2.0 * kN);
     if (best == 0.0 || T.step_us[gidx(g)] < best) {
@@ -2716,6 +2726,7 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
   }
   h->D = chosen;
   h->force_group = 0;
+  h->prop_path = saved_path;
   h->apply_group[pi] = T.apply_group;
   h->prop_group[pi] = T.prop_group;
   *out = T;
@@ -2724,6 +2735,7 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return HUB_OK;
+#undef TUNE_HIP
 }
 
 hub_status hub_set_tuning(hub_basis h, hub_prec prec, const hub_tuning* t) {
