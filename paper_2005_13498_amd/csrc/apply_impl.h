@@ -176,14 +176,19 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
     if (p.ctl->all_done) return;
     // norm of the vector just completed (|u_j|, j >= 1) or of the step input;
     // a row pass needs it only in the workgroup that takes the decision (the
-    // column pass reads the recorded value)
-    if (UPH || blockIdx.x == 0) {
+    // column pass reads the recorded value).  A one-pass apply takes the
+    // decision in an extra last workgroup, so that no apply workgroup waits
+    // for the estimate (a single round of workgroups would otherwise end with
+    // the decider's estimate plus its apply).
+    const bool decider = UPH ? blockIdx.x == gridDim.x - 1 : blockIdx.x == 0;
+    if (UPH || decider) {
       for (int t = 0; t < NV; ++t) {
         const double s = reduce_column<kWavesA>(p.prev_partials, p.prev_nblk, NV, t, red);
         if (tid == 0) sh_beta[t] = sqrt(s);
       }
       __syncthreads();
-      if (blockIdx.x == 0) krylov_decide<NV, kWavesA>(p.j, sh_beta, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+      if (decider) krylov_decide<NV, kWavesA>(p.j, sh_beta, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+      if (UPH && decider) return;
     }
     if (p.j >= p.m_max) return;  // only the decision was needed
     if (UPH) {
@@ -201,7 +206,8 @@ __global__ __launch_bounds__(BLK) void k_apply(KArgs p) {
   const int half = (p.dim_dn + 1) * NV;   // one staged copy incl. the zero slot
   // workgroup = (row a, column chunk); the chunks of one row are consecutive
   // logical blocks, so they run on one XCD and re-read the staged row from L2
-  const int lb = xcd_remap(blockIdx.x, FUSE ? gridDim.x - 1 : gridDim.x);
+  constexpr bool kExtra = FUSE || (kL && UPH);  // an extra last workgroup takes the decision
+  const int lb = xcd_remap(blockIdx.x, kExtra ? gridDim.x - 1 : gridDim.x);
   const int a = lb / p.chunks;
   const int cw = (rowlen + p.chunks - 1) / p.chunks;
   const int qbeg = (lb % p.chunks) * cw;
@@ -440,8 +446,10 @@ hipError_t apply_t(const ApplyLaunch& L, int grid, size_t lds) {
   // once per kernel, also when host threads launch it concurrently
   static const int max_dyn = dyn_lds_opt_in(reinterpret_cast<const void*>(fn));
   if (lds > static_cast<size_t>(max_dyn)) return hipErrorInvalidValue;
-  // fused row pass: one more workgroup for the early estimate
-  return launch_ev(fn, FUSE ? grid + 1 : grid, BLK, lds, L.stream, L.ev_start, L.ev_stop, p);
+  // fused row pass: one more workgroup for the early estimate; one-pass
+  // Lanczos apply: one more for the Krylov decision
+  constexpr bool kExtra = FUSE || ((MODE == M_LANCZOS || MODE == M_LANCZOS_OBS) && UPH);
+  return launch_ev(fn, kExtra ? grid + 1 : grid, BLK, lds, L.stream, L.ev_start, L.ev_stop, p);
 }
 
 template <typename R, int NV, int MODE, int BLK, bool UPH = true, bool FUSE = false>

@@ -123,9 +123,10 @@ __device__ __forceinline__ void group_sum(uint2 w, const uint4* xs, uint32_t dim
   }
 }
 
-// Row pass (one tile row a per workgroup).  Lanczos modes: workgroup 0 first
-// takes the Krylov decision for m = j from the |u_j|^2 partials (the column
-// pass reads what it recorded).  M_LANCZOS_OBS (the step's first apply): per
+// Row pass (one tile row a per workgroup).  Lanczos modes: an extra last
+// workgroup takes the Krylov decision for m = j from the |u_j|^2 partials
+// (the column pass reads what it recorded), so that no row waits for the
+// estimate.  M_LANCZOS_OBS (the step's first apply): per
 // row, [diag, docc, |x|^2, down-hop part of Re <x|K(t_obs)|x>] for every
 // vector into partials [dim_up][kObsQ][NV].
 template <typename R, int NV, int MODE, int MAXS, int BLK>
@@ -140,19 +141,20 @@ __global__ __launch_bounds__(BLK) void k_brow(BArgs p) {
   const int tid = threadIdx.x;
   if (kL) {
     if (p.ctl->all_done) return;
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == gridDim.x - 1) {
       for (int t = 0; t < NV; ++t) {
         const double s = reduce_column<W>(p.prev_partials, p.prev_nblk, NV, t, red);
         if (tid == 0) sh_beta[t] = sqrt(s);
       }
       __syncthreads();
       krylov_decide<NV, W>(p.j, sh_beta, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+      return;
     }
     if (p.j >= p.m_max) return;  // only the decision was needed
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint4* xs = reinterpret_cast<uint4*>(smem_raw);
-  const int a = xcd_remap(blockIdx.x, gridDim.x);
+  const int a = xcd_remap(blockIdx.x, kL ? gridDim.x - 1 : gridDim.x);
   const int dd = p.dim_dn;
   const int k = tid % L, e0 = tid / L;
   const size_t roww = static_cast<size_t>(a) * dd * L;  // first word of the row
@@ -384,7 +386,10 @@ hipError_t block_pair(const ApplyLaunch& L, int* pgrid) {
   static const int max_r = dyn_lds_opt_in(reinterpret_cast<const void*>(fr));
   const size_t lds_r = (static_cast<size_t>(db.dim_dn) + 1) * NV * es;
   if (lds_r > static_cast<size_t>(max_r)) return hipErrorInvalidValue;
-  hipError_t e = launch_ev(fr, db.dim_up, kBlkThreads, lds_r, L.stream, L.ev_start, L.ev_stop, pr);
+  // Lanczos modes: one more workgroup for the Krylov decision
+  constexpr bool kDecide = MODE == M_LANCZOS || MODE == M_LANCZOS_OBS;
+  hipError_t e = launch_ev(fr, kDecide ? db.dim_up + 1 : db.dim_up, kBlkThreads, lds_r, L.stream, L.ev_start,
+                           L.ev_stop, pr);
   if (e != hipSuccess) return e;
   // column pass
   BArgs pc = block_args(L, false);
