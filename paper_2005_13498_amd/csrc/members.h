@@ -66,7 +66,7 @@ inline size_t members_table_lds(int dim_up, int dim_dn, int gs_up, int gs_dn, bo
   return t + a16(size_t(map_len) * 4) + a16(size_t(map_len));
 }
 
-// One workgroup per member (512 threads, `lds` bytes: tables and staging).
+// One workgroup per member (1,024 threads, `lds` bytes: tables and staging).
 hipError_t launch_members(int prec, int n_members, const MembersArgs& a, size_t lds, hipStream_t s);
 
 }  // namespace hub

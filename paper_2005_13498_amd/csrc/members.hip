@@ -15,7 +15,7 @@ namespace dev {
 
 namespace {
 
-constexpr int kMT = 512;       // threads per member workgroup
+constexpr int kMT = 1024;      // threads per member workgroup
 constexpr int kMW = kMT / 64;  // its wavefronts
 constexpr int kB = 4;          // elements per thread whose memory loads are issued together
 
