@@ -61,6 +61,8 @@ CASES = [
     (ring_nnn(8), 6.0, 3, 4, torch.complex128, 1, 30),
     (ring(6), 4.0, 0, 3, torch.complex128, 2, 20),
     (two_site(), 8.0, 1, 1, torch.complex128, 2, 20),
+    (ring(4), 4.0, 4, 4, torch.complex128, 2, 5),     # full sector: one state, no hops
+    (chain(5), 3.0, 5, 2, torch.complex128, 2, 10),   # up species full: down hops only
     (ring(9), 8.0, 3, 3, torch.complex128, 1, 10),   # 7,056 states: 8 per thread
     (ring(9), 8.0, 4, 4, torch.complex64, 1, 10),    # 15,876 states: 16 per thread
 ]
@@ -84,7 +86,9 @@ def test_resident_matches_launch_path(lat, U, nu, nd, dtype, nv, n):
         assert np.array_equal(o1[:, :, 0], o0[:, :, 0])
         same_m = np.mean(l1[:, :, 0] == l0[:, :, 0])
         assert same_m == 1.0 if c128 else same_m >= 0.9, same_m
-        assert (l1[:, :, 2] == 1).all() and (l1[:, :, 5] > 0).all()
+        assert (l1[:, :, 2] == 1).all()
+        if B.dim > 1:
+            assert (l1[:, :, 5] > 0).all()
     finally:
         B.close()
 
