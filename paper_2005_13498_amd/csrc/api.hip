@@ -111,6 +111,12 @@ struct Work {
 };
 
 constexpr int kMaxLanes = 4;
+// Blocks on the two-pass block kernels take fused Lanczos iterations up to
+// this many states (measured, member-steps/s fused vs with an update kernel:
+// 8-site blocks of 8 122 k vs 114 k, 10-site Green's-function members per
+// sector 67.6 k vs 66.2 k; 12-site c64 blocks of 4 8,569 vs 9,135 and
+// 14-site 454 vs 485 lose).
+constexpr int64_t kBlockFuseMaxDim = 65536;
 // Extra lanes are used only while all lanes' Krylov workspaces together stay
 // below this many bytes of device memory.
 constexpr size_t kLaneWorkBudget = size_t(48) << 30;
@@ -239,9 +245,10 @@ hub_status ensure_workspace(hub_basis h, Work& W, size_t slot_bytes, int nslots,
   const int cgmax = std::max(hub::colpass_grid(h->D, 0), hub::colpass_grid(h->D, 1));
   pb = std::max(pb, (2 * static_cast<size_t>(cgmax) +
                      static_cast<size_t>(h->D.dim_up) * (kObsQ + 1)) * sizeof(double));
-  // block two-pass: column-pass partials [dim_dn][2][nv], row-pass obs partials [dim_up][kObsQ][nv]
-  pb = std::max(pb, (2 * static_cast<size_t>(h->D.dim_dn) + static_cast<size_t>(h->D.dim_up) * kObsQ) * kMaxNV *
-                        sizeof(double));
+  // block two-pass: column-pass partials [dim_dn][2][nv], row-pass obs partials [dim_up][kObsQ][nv],
+  // fused row norms [dim_up][nv]
+  pb = std::max(pb, (2 * static_cast<size_t>(h->D.dim_dn) + static_cast<size_t>(h->D.dim_up) * (kObsQ + 1)) *
+                        kMaxNV * sizeof(double));
   if (pb > W.partials_bytes) {
     if (W.partials) HUB_HIP(hipFree(W.partials));
     W.partials = nullptr;
@@ -584,20 +591,26 @@ hub_status run_group(hub_basis h, hub_prec prec, int nv, void* user, int n_steps
     const size_t cg2 = blk ? 2 * static_cast<size_t>(h->D.dim_dn) * nv
                            : 2 * static_cast<size_t>(hub::colpass_grid(h->D, pi));
     if (two_obs) A.row_obs = W.partials + cg2;
-    // From the second iteration on, the two-pass row pass also finishes the
-    // previous update (u_j = w_{j-1} - alpha s u_{j-1}) and the column pass
-    // takes the decision, so no separate update kernel runs in between
-    // (at j = 1 the row pass also finalizes the first apply's observables).
-    const bool fusable = !o.reorth && hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, false);
+    // From the second iteration on, the two-pass row pass (single vectors, or
+    // blocks on the block kernels in small sectors) also finishes the previous
+    // update (u_j = w_{j-1} - alpha s u_{j-1}) and the column pass takes the
+    // decision, so no separate update kernel runs in between (at j = 1 the row
+    // pass also finalizes the first apply's observables).  Fused blocks pay a
+    // full column pass in a step's last iteration (the decision comes one
+    // kernel later) and per-workgroup reductions over per-row and per-column
+    // partials; they gain only where the saved update launch dominates.
+    const bool blk_fuse = blk && dim <= kBlockFuseMaxDim;
+    const bool fusable = !o.reorth && (blk_fuse || hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, false));
     A.fuse = fusable && jj >= 1;
     if (A.fuse) {
       const bool after_obs = jj == 1 && want_obs && sub == 0 &&
-                             hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true);
+                             (blk_fuse || hub::apply_two_pass(h->D, pi, nv, hub::kLanczos, true));
       A.alpha_partials = W.partials;
-      A.alpha_nblk = hub::colpass_grid(h->D, pi);
+      A.alpha_nblk = blk ? h->D.dim_dn : hub::colpass_grid(h->D, pi);
       A.alpha_stride = after_obs ? hub::apply_nq_two_pass(true) : 1;
       A.obs_row = after_obs ? W.partials + cg2 : nullptr;
-      A.norm_partials = W.partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ;
+      // per-row |u_j|^2 [dim_up][nv] after the row pass's observables partials [dim_up][kObsQ][nv]
+      A.norm_partials = W.partials + cg2 + static_cast<size_t>(h->D.dim_up) * kObsQ * (blk ? nv : 1);
     }
     int agrid = 0;  // workgroups that wrote the apply's partial sums
     hub_status r = launch_apply_timed(h, A, &agrid, fusable, n, sub);

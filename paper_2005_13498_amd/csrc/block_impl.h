@@ -47,6 +47,11 @@ struct BArgs {
   double* partials;             // this kernel's partial sums
   const double* prev_partials;  // row pass, Lanczos: |u_j|^2 partials [prev_nblk][NV]
   int prev_nblk;
+  // fused iterations (j >= 1): the row pass finishes the previous update
+  const double* alpha_partials;  // the previous column pass's partials [alpha_nblk][alpha_stride][NV]
+  int alpha_nblk, alpha_stride;
+  const double* obs_row;         // j = 1 after the observables apply: its row-pass partials [dim_up][kObsQ][NV]
+  double* norm;                  // |u_j|^2 per row [dim_up][NV]: written by the row pass, read by the column pass
 };
 
 // The VPL complex values of one 16-byte word.
@@ -126,10 +131,14 @@ __device__ __forceinline__ void group_sum(uint2 w, const uint4* xs, uint32_t dim
 // Row pass (one tile row a per workgroup).  Lanczos modes: an extra last
 // workgroup takes the Krylov decision for m = j from the |u_j|^2 partials
 // (the column pass reads what it recorded), so that no row waits for the
-// estimate.  M_LANCZOS_OBS (the step's first apply): per
+// estimate.  FUSE (iterations j >= 1): x holds w_{j-1} and the row pass first
+// forms u_j = w_{j-1} - alpha_{j-1} s_{j-1} u_{j-1} of its row in place while
+// staging it, with |u_j|^2 per row and vector for the column pass, which then
+// takes the decision; the extra workgroup records alpha_{j-1} and, at j = 1,
+// the observables of the step's first apply.  M_LANCZOS_OBS (the step's first apply): per
 // row, [diag, docc, |x|^2, down-hop part of Re <x|K(t_obs)|x>] for every
 // vector into partials [dim_up][kObsQ][NV].
-template <typename R, int NV, int MODE, int MAXS, int BLK>
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool FUSE>
 __global__ __launch_bounds__(BLK) void k_brow(BArgs p) {
   using V = typename CT<R>::T;
   constexpr int VPL = 16 / sizeof(V), L = NV / VPL, EPW = BLK / L, W = BLK / 64, kG = MAXS / 4;
@@ -138,8 +147,33 @@ __global__ __launch_bounds__(BLK) void k_brow(BArgs p) {
   constexpr bool kO = MODE == M_LANCZOS_OBS;
   __shared__ double red[W * kObsQ * NV + W];
   __shared__ double sh_beta[NV];
+  static_assert(!FUSE || MODE == M_LANCZOS, "fused row pass: Lanczos iterations j >= 1");
   const int tid = threadIdx.x;
-  if (kL) {
+  const int k = tid % L, e0 = tid / L;
+  R cu[VPL];  // FUSE: alpha_{j-1} s_{j-1} of this lane's vectors
+  if (FUSE) {
+    if (p.ctl->all_done) return;
+    for (int t = 0; t < NV; ++t) {
+      const double s = reduce_column<W>(p.alpha_partials, p.alpha_nblk, p.alpha_stride * NV, t, red);
+      if (tid == 0) sh_beta[t] = s;  // alpha_{j-1} of vector t
+    }
+    __syncthreads();
+    if (blockIdx.x == gridDim.x - 1) {
+      if (tid < NV && p.st[tid].status == 0) p.st[tid].alpha[p.j - 1] = sh_beta[tid];
+      if (p.obs_row)  // [diag, docc, n2, down-hop part] of the rows, up-hop part in the columns' second column
+        for (int t = 0; t < kObsQ * NV; ++t) {
+          double s = reduce_column<W>(p.obs_row, p.dim_up, kObsQ * NV, t, red);
+          if (t / NV == kObsQ - 1) s += reduce_column<W>(p.alpha_partials, p.alpha_nblk, p.alpha_stride * NV, NV + t % NV, red);
+          if (tid == 0) p.st[t % NV].obs[t / NV] = s;
+        }
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      const int v = k * VPL + i;
+      cu[i] = static_cast<R>(sh_beta[v] * p.st[v].scale[p.j - 1]);
+    }
+  } else if (kL) {
     if (p.ctl->all_done) return;
     if (blockIdx.x == gridDim.x - 1) {
       for (int t = 0; t < NV; ++t) {
@@ -156,9 +190,38 @@ __global__ __launch_bounds__(BLK) void k_brow(BArgs p) {
   uint4* xs = reinterpret_cast<uint4*>(smem_raw);
   const int a = xcd_remap(blockIdx.x, kL ? gridDim.x - 1 : gridDim.x);
   const int dd = p.dim_dn;
-  const int k = tid % L, e0 = tid / L;
   const size_t roww = static_cast<size_t>(a) * dd * L;  // first word of the row
-  {
+  if (FUSE) {
+    // u_j = w_{j-1} - alpha s u_{j-1} of the row, in place and staged; |u_j|^2
+    // per vector (a thread's words all hold the vectors of word index k)
+    uint4* w4 = static_cast<uint4*>(const_cast<void*>(p.x)) + roww;
+    const uint4* u4 = static_cast<const uint4*>(p.xprev) + roww;
+    double n2[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) n2[i] = 0.0;
+    for (int t = tid; t < (dd + 1) * L; t += BLK) {
+      uint4 o = make_uint4(0u, 0u, 0u, 0u);
+      if (t < dd * L) {
+        V wv[VPL], uv[VPL];
+        from_word<V>(w4[t], wv);
+        from_word<V>(u4[t], uv);
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+          wv[i].x -= cu[i] * uv[i].x;
+          wv[i].y -= cu[i] * uv[i].y;
+          n2[i] += static_cast<double>(wv[i].x) * wv[i].x + static_cast<double>(wv[i].y) * wv[i].y;
+        }
+        o = to_word<V>(wv);
+        w4[t] = o;
+      }
+      xs[t] = o;
+    }
+    __shared__ double tn[NV];
+    word_sums<W, L, VPL>(n2, red, tn);
+    __syncthreads();
+    for (int t = tid; t < NV; t += BLK) p.norm[static_cast<size_t>(a) * NV + t] = tn[(t % VPL) * L + t / VPL];
+    if (!p.y) return;  // j = m_max: only the norm was needed
+  } else {
     const uint4* x4 = static_cast<const uint4*>(p.x) + roww;
     for (int t = tid; t < (dd + 1) * L; t += BLK) xs[t] = t < dd * L ? x4[t] : make_uint4(0u, 0u, 0u, 0u);
   }
@@ -233,8 +296,10 @@ __global__ __launch_bounds__(BLK) void k_brow(BArgs p) {
 // decision the row pass recorded and write alpha partials [grid][NV]
 // (M_LANCZOS_OBS: [grid][2][NV], alpha and the up-hop part of
 // Re <x|K(t_obs)|x>).  A vector whose step ended at an earlier iteration
-// gets a zero result.
-template <typename R, int NV, int MODE, int MAXS, int BLK>
+// gets a zero result.  FUSE: |u_j| comes from the row pass's per-row norms and
+// an extra last workgroup takes the decision for m = j (a vector that has
+// stopped gets a result no later step reads).
+template <typename R, int NV, int MODE, int MAXS, int BLK, bool FUSE>
 __global__ __launch_bounds__(BLK) void k_bcol(BArgs p) {
   using V = typename CT<R>::T;
   constexpr int VPL = 16 / sizeof(V), L = NV / VPL, EPW = BLK / L, W = BLK / 64, kG = MAXS / 4;
@@ -251,7 +316,28 @@ __global__ __launch_bounds__(BLK) void k_bcol(BArgs p) {
     sj[i] = 1;
     bp[i] = 0;
   }
-  if (kL) {
+  static_assert(!FUSE || MODE == M_LANCZOS, "fused column pass: Lanczos iterations j >= 1");
+  if (FUSE) {
+    if (p.ctl->all_done) return;
+    __shared__ double sh_b[NV];
+    for (int t = 0; t < NV; ++t) {
+      const double s = reduce_column<W>(p.norm, p.dim_up, NV, t, red);
+      if (tid == 0) sh_b[t] = sqrt(s);  // |u_j| = beta_{j-1} of vector t
+    }
+    __syncthreads();
+    if (blockIdx.x == gridDim.x - 1) {
+      krylov_decide<NV, W>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+      return;
+    }
+    if (p.j >= p.m_max) return;  // only the decision was needed
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      const int v = k * VPL + i;
+      const double bv = sh_b[v];
+      sj[i] = static_cast<R>(bv > 0.0 ? 1.0 / bv : 0.0);
+      bp[i] = static_cast<R>(bv > 0.0 ? bv * p.st[v].scale[p.j - 1] : 0.0);
+    }
+  } else if (kL) {
     if (p.ctl->all_done) return;
     if (p.j >= p.m_max) return;
 #pragma unroll
@@ -264,7 +350,7 @@ __global__ __launch_bounds__(BLK) void k_bcol(BArgs p) {
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint4* xs = reinterpret_cast<uint4*>(smem_raw);
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, FUSE ? gridDim.x - 1 : gridDim.x);
   const int du = p.dim_up, dd = p.dim_dn;
   {
     const uint4* x4 = static_cast<const uint4*>(p.x);
@@ -368,13 +454,18 @@ inline BArgs block_args(const ApplyLaunch& L, bool row) {
   p.ctl = L.ctl;
   p.prev_partials = L.prev_partials;
   p.prev_nblk = L.prev_nblk;
+  p.alpha_partials = L.alpha_partials;
+  p.alpha_nblk = L.alpha_nblk;
+  p.alpha_stride = L.alpha_stride;
+  p.obs_row = L.obs_row;
+  p.norm = L.norm_partials;
   return p;
 }
 
 // Threads per block-kernel workgroup.
 constexpr int kBlkThreads = 512;
 
-template <typename R, int NV, int MODE, int MAXS_R, int MAXS_C>
+template <typename R, int NV, int MODE, int MAXS_R, int MAXS_C, bool FUSE>
 hipError_t block_pair(const ApplyLaunch& L, int* pgrid) {
   const DevBasis& db = *L.db;
   constexpr bool kO = MODE == M_LANCZOS_OBS;
@@ -382,11 +473,12 @@ hipError_t block_pair(const ApplyLaunch& L, int* pgrid) {
   // row pass
   BArgs pr = block_args(L, true);
   pr.partials = kO ? L.row_obs : nullptr;
-  auto fr = k_brow<R, NV, MODE, MAXS_R, kBlkThreads>;
+  auto fr = k_brow<R, NV, MODE, MAXS_R, kBlkThreads, FUSE>;
   static const int max_r = dyn_lds_opt_in(reinterpret_cast<const void*>(fr));
   const size_t lds_r = (static_cast<size_t>(db.dim_dn) + 1) * NV * es;
   if (lds_r > static_cast<size_t>(max_r)) return hipErrorInvalidValue;
-  // Lanczos modes: one more workgroup for the Krylov decision
+  // Lanczos modes: one more workgroup for the Krylov decision (fused: for
+  // alpha_{j-1} and the observables)
   constexpr bool kDecide = MODE == M_LANCZOS || MODE == M_LANCZOS_OBS;
   hipError_t e = launch_ev(fr, kDecide ? db.dim_up + 1 : db.dim_up, kBlkThreads, lds_r, L.stream, L.ev_start,
                            L.ev_stop, pr);
@@ -394,34 +486,35 @@ hipError_t block_pair(const ApplyLaunch& L, int* pgrid) {
   // column pass
   BArgs pc = block_args(L, false);
   pc.partials = L.partials;
-  auto fc = k_bcol<R, NV, MODE, MAXS_C, kBlkThreads>;
+  auto fc = k_bcol<R, NV, MODE, MAXS_C, kBlkThreads, FUSE>;
   static const int max_c = dyn_lds_opt_in(reinterpret_cast<const void*>(fc));
   const size_t lds_c = (static_cast<size_t>(db.dim_up) + 1) * NV * es;
   if (lds_c > static_cast<size_t>(max_c)) return hipErrorInvalidValue;
   if (pgrid) *pgrid = db.dim_dn;
-  return launch_ev(fc, db.dim_dn, kBlkThreads, lds_c, L.stream, L.ev2_start, L.ev2_stop, pc);
+  // fused: one more workgroup for the Krylov decision
+  return launch_ev(fc, FUSE ? db.dim_dn + 1 : db.dim_dn, kBlkThreads, lds_c, L.stream, L.ev2_start, L.ev2_stop, pc);
 }
 
-template <typename R, int NV, int MODE, int MAXS_R>
+template <typename R, int NV, int MODE, int MAXS_R, bool FUSE>
 hipError_t block_col_s(const ApplyLaunch& L, int* pgrid) {
   switch (L.db->up_gslots) {
-    case 8: return block_pair<R, NV, MODE, MAXS_R, 8>(L, pgrid);
-    case 12: return block_pair<R, NV, MODE, MAXS_R, 12>(L, pgrid);
-    case 16: return block_pair<R, NV, MODE, MAXS_R, 16>(L, pgrid);
-    case 20: return block_pair<R, NV, MODE, MAXS_R, 20>(L, pgrid);
-    case 24: return block_pair<R, NV, MODE, MAXS_R, 24>(L, pgrid);
+    case 8: return block_pair<R, NV, MODE, MAXS_R, 8, FUSE>(L, pgrid);
+    case 12: return block_pair<R, NV, MODE, MAXS_R, 12, FUSE>(L, pgrid);
+    case 16: return block_pair<R, NV, MODE, MAXS_R, 16, FUSE>(L, pgrid);
+    case 20: return block_pair<R, NV, MODE, MAXS_R, 20, FUSE>(L, pgrid);
+    case 24: return block_pair<R, NV, MODE, MAXS_R, 24, FUSE>(L, pgrid);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename R, int NV, int MODE>
+template <typename R, int NV, int MODE, bool FUSE = false>
 hipError_t block_row_s(const ApplyLaunch& L, int* pgrid) {
   switch (L.db->dn_gslots) {
-    case 8: return block_col_s<R, NV, MODE, 8>(L, pgrid);
-    case 12: return block_col_s<R, NV, MODE, 12>(L, pgrid);
-    case 16: return block_col_s<R, NV, MODE, 16>(L, pgrid);
-    case 20: return block_col_s<R, NV, MODE, 20>(L, pgrid);
-    case 24: return block_col_s<R, NV, MODE, 24>(L, pgrid);
+    case 8: return block_col_s<R, NV, MODE, 8, FUSE>(L, pgrid);
+    case 12: return block_col_s<R, NV, MODE, 12, FUSE>(L, pgrid);
+    case 16: return block_col_s<R, NV, MODE, 16, FUSE>(L, pgrid);
+    case 20: return block_col_s<R, NV, MODE, 20, FUSE>(L, pgrid);
+    case 24: return block_col_s<R, NV, MODE, 24, FUSE>(L, pgrid);
     default: return hipErrorInvalidValue;
   }
 }
@@ -431,6 +524,7 @@ hipError_t block_mode(const ApplyLaunch& L, int* pgrid) {
   if (L.mode == kPlain) return block_row_s<R, NV, M_PLAIN>(L, pgrid);
   if (L.mode != kLanczos) return hipErrorInvalidValue;
   if (L.obs) return block_row_s<R, NV, M_LANCZOS_OBS>(L, pgrid);
+  if (L.fuse) return block_row_s<R, NV, M_LANCZOS, true>(L, pgrid);
   return block_row_s<R, NV, M_LANCZOS>(L, pgrid);
 }
 
