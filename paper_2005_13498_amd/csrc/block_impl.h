@@ -128,14 +128,52 @@ __device__ __forceinline__ void group_sum(uint2 w, const uint4* xs, uint32_t dim
   }
 }
 
+// The Krylov decision for m = j of every running vector (krylov_decide's
+// rule: non-finite, breakdown, tolerance, m_max) from the estimate the fused
+// row pass already recorded in S.eps and S.y; beta_new[v] = |u_j|.  Run by
+// one workgroup.
+template <int NV, int W>
+__device__ void block_decide_pre(int j, const double* beta_new, VecState* st, StepCtl* ctl, int m_max, double tol,
+                                 double norm_inf) {
+  if (threadIdx.x < NV) {
+    VecState& S = st[threadIdx.x];
+    if (S.status == 0) {
+      const double b = beta_new[threadIdx.x], eps = S.eps;
+      S.beta[j - 1] = b;
+      S.m = j;
+      int status = 0;
+      if (!isfinite(b) || !isfinite(eps)) status = 4;
+      else if (b < norm_inf * tol) status = 2;
+      else if (eps < tol) status = 1;
+      else if (j >= m_max) status = 3;
+      S.status = status;
+      S.scale[j] = (status == 0 && b > 0.0) ? 1.0 / b : 0.0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int done = 1, maxed = 0;
+    for (int v = 0; v < NV; ++v) {
+      done &= (st[v].status != 0);
+      maxed |= (st[v].status >= 3);
+    }
+    ctl->all_done = done;
+    ctl->any_maxed = maxed;
+    ctl->iter = j;
+  }
+}
+
 // Row pass (one tile row a per workgroup).  Lanczos modes: an extra last
 // workgroup takes the Krylov decision for m = j from the |u_j|^2 partials
 // (the column pass reads what it recorded), so that no row waits for the
 // estimate.  FUSE (iterations j >= 1): x holds w_{j-1} and the row pass first
 // forms u_j = w_{j-1} - alpha_{j-1} s_{j-1} u_{j-1} of its row in place while
 // staging it, with |u_j|^2 per row and vector for the column pass, which then
-// takes the decision; the extra workgroup records alpha_{j-1} and, at j = 1,
-// the observables of the step's first apply.  M_LANCZOS_OBS (the step's first apply): per
+// takes the decision; the extra workgroup records alpha_{j-1}, at j = 1 the
+// observables of the step's first apply, and the estimate for m = j of every
+// running vector (it needs T_j only, not |u_j|; one wavefront per vector), and
+// when every running vector's estimate is below tol the step ends at m = j
+// and the column pass skips its apply.  M_LANCZOS_OBS (the step's first apply): per
 // row, [diag, docc, |x|^2, down-hop part of Re <x|K(t_obs)|x>] for every
 // vector into partials [dim_up][kObsQ][NV].
 template <typename R, int NV, int MODE, int MAXS, int BLK, bool FUSE>
@@ -166,6 +204,27 @@ __global__ __launch_bounds__(BLK) void k_brow(BArgs p) {
           if (t / NV == kObsQ - 1) s += reduce_column<W>(p.alpha_partials, p.alpha_nblk, p.alpha_stride * NV, NV + t % NV, red);
           if (tid == 0) p.st[t % NV].obs[t / NV] = s;
         }
+      __shared__ int sh_end;  // every running vector's estimate for m = j is below tol
+      if (tid == 0) sh_end = 1;
+      __syncthreads();
+      const int lane = tid & 63, wv = tid >> 6;
+      for (int v = wv; v < NV; v += W) {
+        VecState& S = p.st[v];
+        if (S.status != 0) continue;
+        const double aj = lane < p.j - 1 ? S.alpha[lane] : (lane == p.j - 1 ? sh_beta[v] : 0.0);
+        double yr, yi;
+        const double eps = wave_krylov_eps(p.j, aj, S.beta, S.tau, S.y, lane, yr, yi);
+        if (lane < p.j) {  // every lane has read y^(j-1): its reductions fed eps
+          S.y[2 * lane] = yr;
+          S.y[2 * lane + 1] = yi;
+        }
+        if (lane == 0) {
+          S.eps = eps;
+          if (!(eps < p.tol)) sh_end = 0;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) p.ctl->eps_stop = sh_end ? p.j : -1;
       return;
     }
 #pragma unroll
@@ -319,14 +378,18 @@ __global__ __launch_bounds__(BLK) void k_bcol(BArgs p) {
   static_assert(!FUSE || MODE == M_LANCZOS, "fused column pass: Lanczos iterations j >= 1");
   if (FUSE) {
     if (p.ctl->all_done) return;
+    // the row pass found every running vector's estimate for m = j below tol:
+    // the step ends here and only the decision is left
+    const bool decide = blockIdx.x == gridDim.x - 1;
+    if (p.ctl->eps_stop == p.j && !decide) return;
     __shared__ double sh_b[NV];
     for (int t = 0; t < NV; ++t) {
       const double s = reduce_column<W>(p.norm, p.dim_up, NV, t, red);
       if (tid == 0) sh_b[t] = sqrt(s);  // |u_j| = beta_{j-1} of vector t
     }
     __syncthreads();
-    if (blockIdx.x == gridDim.x - 1) {
-      krylov_decide<NV, W>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
+    if (decide) {
+      block_decide_pre<NV, W>(p.j, sh_b, p.st, p.ctl, p.m_max, p.tol, p.norm_inf);
       return;
     }
     if (p.j >= p.m_max) return;  // only the decision was needed
