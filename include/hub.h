@@ -469,9 +469,16 @@ hub_status hub_set_apply_path(hub_basis basis, int32_t path);
  * hub_apply_H and hub_propagate.  Without tuning these follow built-in rules
  * (LDS fit and vector size); hub_tune measures them on this basis's sector:
  * plain H*v of 8 vectors in groups of 1, 2, 4, 8 on each feasible path
- * (`reps` timed calls each, HIP events), then one midpoint step of 8 vectors
- * per group size on the chosen paths (dt |H|_inf = 1/2, tol 1e-10, host
- * clock), and installs the fastest choices in the handle.  Results never
+ * (`reps` timed calls each, HIP events), then two midpoint steps (after one
+ * untimed) per group size on the chosen paths (dt |H|_inf = 1/2, tol 1e-10,
+ * host clock), of 8 vectors and of 32, and installs the fastest choices in
+ * the handle.  Groups run on up to 4 concurrent lanes, so the best group
+ * size depends on how many groups a call has: 8 vectors in groups of 8 run
+ * on one lane, 32 fill every lane at every group size.  A hub_propagate call
+ * of at most 8 vectors takes prop_group, a larger one prop_group_large.
+ * The 32-vector measurement skips a group size whose vectors and Krylov
+ * workspace would not fit the device's free memory (step_us_large 0 there;
+ * prop_group_large = prop_group when none fits).  Results never
  * depend on the plan (only how the work is split into kernels).  hub_tune
  * allocates its test vectors; hub_set_tuning installs a table from an
  * earlier hub_tune (e.g. cached per sector shape and device), or the
@@ -487,6 +494,9 @@ typedef struct {
                                  (one pass, two passes); 0 = infeasible                     */
   double step_us[4];          /* measured midpoint step time per vector (us) per group size;
                                  0 = infeasible                                             */
+  int32_t prop_group_large;   /* vectors per group of hub_propagate calls of more than 8
+                                 vectors (1, 2, 4, 8)                                       */
+  double step_us_large[4];    /* step_us measured with 32 vectors; 0 = infeasible or skipped */
 } hub_tuning;
 
 hub_status hub_tune(hub_basis basis, hub_prec prec, int32_t reps, hub_tuning *out, void *stream);

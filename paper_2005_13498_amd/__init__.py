@@ -102,7 +102,8 @@ class hub_controller_stats(ctypes.Structure):
 class hub_tuning(ctypes.Structure):
     _fields_ = [("single_two_pass", ctypes.c_int32), ("block_two_pass", ctypes.c_int32 * 4),
                 ("apply_group", ctypes.c_int32), ("prop_group", ctypes.c_int32),
-                ("apply_us", (ctypes.c_double * 2) * 4), ("step_us", ctypes.c_double * 4)]
+                ("apply_us", (ctypes.c_double * 2) * 4), ("step_us", ctypes.c_double * 4),
+                ("prop_group_large", ctypes.c_int32), ("step_us_large", ctypes.c_double * 4)]
 
 
 class hub_obs(ctypes.Structure):
@@ -513,7 +514,8 @@ def hub_set_schedule(h, chunk: int, margin: int = 1) -> None:
 def tuning_to_dict(t: hub_tuning) -> dict:
     return {"single_two_pass": t.single_two_pass, "block_two_pass": list(t.block_two_pass),
             "apply_group": t.apply_group, "prop_group": t.prop_group,
-            "apply_us": [list(r) for r in t.apply_us], "step_us": list(t.step_us)}
+            "apply_us": [list(r) for r in t.apply_us], "step_us": list(t.step_us),
+            "prop_group_large": t.prop_group_large, "step_us_large": list(t.step_us_large)}
 
 
 def tuning_from_dict(d: dict) -> hub_tuning:
@@ -522,10 +524,12 @@ def tuning_from_dict(d: dict) -> hub_tuning:
     for k in range(4):
         t.block_two_pass[k] = int(d["block_two_pass"][k])
         t.step_us[k] = float(d.get("step_us", [0.0] * 4)[k])
+        t.step_us_large[k] = float(d.get("step_us_large", [0.0] * 4)[k])
         for p in range(2):
             t.apply_us[k][p] = float(d.get("apply_us", [[0.0, 0.0]] * 4)[k][p])
     t.apply_group = int(d["apply_group"])
     t.prop_group = int(d["prop_group"])
+    t.prop_group_large = int(d.get("prop_group_large", d["prop_group"]))  # tables from before the large batch
     return t
 
 

@@ -144,6 +144,7 @@ struct hub_basis_s {
   // while hub_tune measures
   int apply_group[2] = {-1, -1};
   int prop_group[2] = {-1, -1};
+  int prop_group_large[2] = {-1, -1};  // hub_propagate with more than kMaxNV vectors
   int force_group = 0;
   // Green's functions: -1 automatic, 0 per-sector groups, 1 persistent members
   int greens_path = -1;
@@ -430,7 +431,8 @@ hub_status prof_harvest(hub_basis h, size_t from, size_t* end) {
 // at least three apply workgroups per CU (<= 48 KB of the 160 KB LDS), or one
 // vector per group; single vectors where the two-pass kernels apply.
 std::vector<int> groups_for(hub_basis h, int nvec, int prec, bool propagate = true) {
-  const int tuned = h->force_group > 0 ? h->force_group : (propagate ? h->prop_group[prec] : h->apply_group[prec]);
+  const int prop = nvec > kMaxNV && h->prop_group_large[prec] > 0 ? h->prop_group_large[prec] : h->prop_group[prec];
+  const int tuned = h->force_group > 0 ? h->force_group : (propagate ? prop : h->apply_group[prec]);
   if (tuned > 0) {
     std::vector<int> g;
     // a tuned size smaller where neither the block kernels nor the one-pass
@@ -2639,7 +2641,7 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
   void* y = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const DevBasis saved = h->D;
-  const int saved_ag = h->apply_group[pi], saved_pg = h->prop_group[pi];
+  const int saved_ag = h->apply_group[pi], saved_pg = h->prop_group[pi], saved_pgl = h->prop_group_large[pi];
   // the plans are the launch path's: its propagations are timed, not the resident stepper's
   const int saved_path = h->prop_path;
   h->prop_path = 0;
@@ -2650,6 +2652,7 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
     if (r != HUB_OK) {
       h->apply_group[pi] = saved_ag;
       h->prop_group[pi] = saved_pg;
+      h->prop_group_large[pi] = saved_pgl;
     }
     if (x) (void)hipFree(x);
     if (y) (void)hipFree(y);
@@ -2711,37 +2714,74 @@ hub_status hub_tune(hub_basis h, hub_prec prec, int32_t reps, hub_tuning* out, v
       T.apply_group = g;
     }
   }
-  // 2. midpoint steps of kN vectors in groups of g (the chosen paths), dt
-  // such that dt |H|_inf = 1/2, tol 1e-10: time per vector-step
+  // 2. midpoint steps of nv vectors in groups of g (the chosen paths), dt
+  // such that dt |H|_inf = 1/2, tol 1e-10: time per vector-step, for nv =
+  // kN (a group of 8 then runs on one lane) and nv = kN * kMaxLanes (every
+  // group size fills the concurrent lanes)
   hub_krylov_opts o{};
   o.tol = 1e-10;
   o.m_max = 30;
   o.substeps = 1;
   const double dtp = 0.5 / std::max(h->B.norm_inf, 1e-300);
-  std::vector<std::vector<double>> am(kN, std::vector<double>(3, 0.5));
-  best = 0.0;
-  for (int g : {1, 2, 4, 8}) {
-    if (g > 1 && !hub::block_two_pass(chosen, pi, g) && hub::apply_lds_bytes(chosen, pi, g, 1) > 150 * 1024) continue;
+  constexpr int kNL = kN * kMaxLanes;
+  std::vector<std::vector<double>> am(kNL, std::vector<double>(3, 0.5));
+  auto time_steps = [&](int nv, void* buf, int g, double* us_per_vector_step) -> hub_status {
     h->D = chosen;
     h->force_group = g;
-    if (hub::launch_fill_probe(pi, dim * kN, x, st) != hipSuccess) return done(fail(HUB_E_DEVICE, "fill kernel"));
-    if ((s = run_all(h, prec, kN, x, 1, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream)) != HUB_OK) return done(s);
-    TUNE_HIP(hipStreamSynchronize(st));
+    if (hub::launch_fill_probe(pi, dim * nv, buf, st) != hipSuccess) return fail(HUB_E_DEVICE, "fill kernel");
+    hub_status r = run_all(h, prec, nv, buf, 1, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream);
+    if (r != HUB_OK) return r;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(HUB_E_DEVICE, "tuning: stream synchronisation");
     const auto t0 = std::chrono::steady_clock::now();
-    if ((s = run_all(h, prec, kN, x, 2, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream)) != HUB_OK) return done(s);
-    TUNE_HIP(hipStreamSynchronize(st));
-    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-    T.step_us[gidx(g)] = us / (2.0 * kN);
+    if ((r = run_all(h, prec, nv, buf, 2, am, nullptr, 0.0, dtp, o, nullptr, nullptr, stream)) != HUB_OK) return r;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(HUB_E_DEVICE, "tuning: stream synchronisation");
+    *us_per_vector_step = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() /
+                          (2.0 * nv);
+    return HUB_OK;
+  };
+  auto group_ok = [&](int g) {
+    return g == 1 || hub::block_two_pass(chosen, pi, g) || hub::apply_lds_bytes(chosen, pi, g, 1) <= 150 * 1024;
+  };
+  best = 0.0;
+  for (int g : {1, 2, 4, 8}) {
+    if (!group_ok(g)) continue;
+    if ((s = time_steps(kN, x, g, &T.step_us[gidx(g)])) != HUB_OK) return done(s);
     if (best == 0.0 || T.step_us[gidx(g)] < best) {
       best = T.step_us[gidx(g)];
       T.prop_group = g;
     }
+  }
+  // the larger batch in its own buffer, each group size only where its
+  // vectors and the lanes' Krylov workspaces fit the free device memory
+  T.prop_group_large = T.prop_group;
+  void* xl = nullptr;
+  size_t mem_free = 0, mem_total = 0;
+  const size_t vec_b = static_cast<size_t>(dim) * es;
+  if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_free > kNL * vec_b &&
+      hipMalloc(&xl, kNL * vec_b) == hipSuccess) {
+    best = 0.0;
+    for (int g : {1, 2, 4, 8}) {
+      if (!group_ok(g)) continue;
+      const size_t lanes = std::min<size_t>(kMaxLanes, kNL / g);
+      const size_t need = lanes * static_cast<size_t>(o.m_max + 2) * g * vec_b;
+      if (hipMemGetInfo(&mem_free, &mem_total) != hipSuccess || need + need / 8 > mem_free) continue;
+      if ((s = time_steps(kNL, xl, g, &T.step_us_large[gidx(g)])) != HUB_OK) {
+        (void)hipFree(xl);
+        return done(s);
+      }
+      if (best == 0.0 || T.step_us_large[gidx(g)] < best) {
+        best = T.step_us_large[gidx(g)];
+        T.prop_group_large = g;
+      }
+    }
+    TUNE_HIP(hipFree(xl));
   }
   h->D = chosen;
   h->force_group = 0;
   h->prop_path = saved_path;
   h->apply_group[pi] = T.apply_group;
   h->prop_group[pi] = T.prop_group;
+  h->prop_group_large[pi] = T.prop_group_large;
   *out = T;
   if (x) (void)hipFree(x);
   if (y) (void)hipFree(y);
@@ -2758,11 +2798,12 @@ hub_status hub_set_tuning(hub_basis h, hub_prec prec, const hub_tuning* t) {
   if (!t) {  // back to the built-in rules
     h->D.tuned_single[pi] = -1;
     for (int k = 0; k < 4; ++k) h->D.tuned_block[pi][k] = -1;
-    h->apply_group[pi] = h->prop_group[pi] = -1;
+    h->apply_group[pi] = h->prop_group[pi] = h->prop_group_large[pi] = -1;
     return HUB_OK;
   }
   auto pow2 = [](int g) { return g == 1 || g == 2 || g == 4 || g == 8; };
-  if (!pow2(t->apply_group) || !pow2(t->prop_group) || (t->single_two_pass != 0 && t->single_two_pass != 1))
+  if (!pow2(t->apply_group) || !pow2(t->prop_group) || !pow2(t->prop_group_large) ||
+      (t->single_two_pass != 0 && t->single_two_pass != 1))
     return fail(HUB_E_INVALID, "tuning: groups must be 1, 2, 4 or 8 and paths 0 or 1");
   for (int k = 1; k < 4; ++k)
     if (t->block_two_pass[k] != 0 && t->block_two_pass[k] != 1) return fail(HUB_E_INVALID, "tuning: block path");
@@ -2770,6 +2811,7 @@ hub_status hub_set_tuning(hub_basis h, hub_prec prec, const hub_tuning* t) {
   for (int k = 1; k < 4; ++k) h->D.tuned_block[pi][k] = t->block_two_pass[k];
   h->apply_group[pi] = t->apply_group;
   h->prop_group[pi] = t->prop_group;
+  h->prop_group_large[pi] = t->prop_group_large;
   return HUB_OK;
 }
 

@@ -78,8 +78,8 @@ def main(out: str = TABLE) -> int:
         for prec in (HUB_C128, HUB_C64):
             ent = hub_tune(B.handle, prec, 10)
             tab[dev][key(B, prec)] = ent
-            print(key(B, prec), ent["prop_group"], ent["apply_group"], ent["single_two_pass"], ent["block_two_pass"],
-                  flush=True)
+            print(key(B, prec), ent["prop_group"], ent["prop_group_large"], ent["apply_group"], ent["single_two_pass"],
+                  ent["block_two_pass"], flush=True)
         B.close()
         torch.cuda.empty_cache()
     with open(out, "w") as f:

@@ -28,9 +28,15 @@ def test_tune_installs_a_measured_plan(prec):
         us = np.array(t["apply_us"])
         assert (us >= 0).all() and us[0, 0] > 0 and us[0, 1] > 0  # both single-vector paths fit at 12 sites
         assert np.array(t["step_us"])[0] > 0
+        # 32 vectors fit at 12 sites for every feasible group size
+        assert t["prop_group_large"] in (1, 2, 4, 8)
+        assert t["step_us_large"][{1: 0, 2: 1, 4: 2, 8: 3}[t["prop_group_large"]]] > 0
+        assert all((a > 0) == (b > 0) for a, b in zip(t["step_us"], t["step_us_large"]))
         # the installed plan is what the library reports
         plan = hub.hub_get_plan(B.handle, prec, 8, True)
         assert sum(g for g, _ in plan) == 8 and max(g for g, _ in plan) == t["prop_group"]
+        plan_l = hub.hub_get_plan(B.handle, prec, 32, True)
+        assert sum(g for g, _ in plan_l) == 32 and max(g for g, _ in plan_l) == t["prop_group_large"]
         plan_a = hub.hub_get_plan(B.handle, prec, 8, False)
         assert max(g for g, _ in plan_a) == t["apply_group"]
         # a cached table installs the same plan; None restores the built-in rules
@@ -39,6 +45,28 @@ def test_tune_installs_a_measured_plan(prec):
         assert hub.hub_get_plan(B.handle, prec, 8, True) == plan
         with pytest.raises(hub.HubError):
             hub.hub_set_tuning(B.handle, prec, dict(t, prop_group=3))
+        with pytest.raises(hub.HubError):
+            hub.hub_set_tuning(B.handle, prec, dict(t, prop_group_large=6))
+    finally:
+        B.close()
+
+
+def test_large_batches_take_their_own_group_size():
+    """A plan's prop_group serves hub_propagate calls of up to 8 vectors,
+    prop_group_large larger ones (the groups then fill the concurrent
+    lanes); a plan without the large entry uses prop_group for both."""
+    w = workloads()["ring8"]
+    B = hub.Basis(w.lattice, w.U, 4, 4)
+    try:
+        plan = {"single_two_pass": 0, "block_two_pass": [0, 1, 1, 1], "apply_group": 8, "prop_group": 2,
+                "prop_group_large": 8}
+        hub.hub_set_tuning(B.handle, hub.HUB_C64, plan)
+        assert [g for g, _ in hub.hub_get_plan(B.handle, hub.HUB_C64, 8, True)] == [2] * 4
+        assert [g for g, _ in hub.hub_get_plan(B.handle, hub.HUB_C64, 9, True)] == [8, 1]
+        assert [g for g, _ in hub.hub_get_plan(B.handle, hub.HUB_C64, 64, True)] == [8] * 8
+        old = {k: v for k, v in plan.items() if k != "prop_group_large"}
+        hub.hub_set_tuning(B.handle, hub.HUB_C64, old)
+        assert [g for g, _ in hub.hub_get_plan(B.handle, hub.HUB_C64, 64, True)] == [2] * 32
     finally:
         B.close()
 
