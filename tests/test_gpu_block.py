@@ -85,11 +85,16 @@ def test_block_apply_cluster3x4_full_size():
 @pytest.mark.parametrize("dtype,bar", [(torch.complex128, 1e-10), (torch.complex64, 1e-5)])
 def test_block_propagation_matches_exact(dtype, bar):
     """8-site ring, 8 members (pulse amplitudes 0.1 .. 0.8), 40 midpoint
-    steps of 0.01 from seeded states."""
+    steps of 0.01 from seeded states, on the launch path (a block of 8 on
+    the two-pass block kernels with fused iterations; the automatic choice
+    would take the resident stepper at this size)."""
     w = workloads()["ring8"]
     ham = HubbardOracle(w.lattice, w.U, 4, 4)
     B = hub.Basis(w.lattice, w.U, 4, 4)
+    hub.hub_set_propagate_path(B.handle, 0)
     try:
+        plan = hub.hub_get_plan(B.handle, hub.HUB_C128 if dtype == torch.complex128 else hub.HUB_C64, 8, True)
+        assert plan == [(8, 2)]
         nvec, n, dt = 8, 40, 0.01
         pulses = [PulseParams(0, 0.1 * (k + 1), 8.0, 0.2, 0.15) for k in range(nvec)]
         xs = random_state(ham.dim, seed=5, nvec=nvec)

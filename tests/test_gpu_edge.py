@@ -33,10 +33,14 @@ def _vecs(B, nv, seed, dtype):
     return torch.from_numpy(x).to(DEV).to(dtype).contiguous()
 
 
-@pytest.mark.parametrize("name,nv", [("ring8", 1), ("ring8", 3), ("cluster3x4", 1)])
-def test_zero_steps_report_the_input(name, nv):
+# path -1: the automatic choice (the resident stepper for the 8-site ring),
+# 0: the launch path
+@pytest.mark.parametrize("name,nv,path", [("ring8", 1, -1), ("ring8", 1, 0), ("ring8", 3, -1), ("ring8", 3, 0),
+                                          ("cluster3x4", 1, -1)])
+def test_zero_steps_report_the_input(name, nv, path):
     w = workloads()[name]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, path)
     try:
         x0 = _vecs(B, nv, 61, torch.complex128)
         x = x0.clone()
@@ -53,11 +57,13 @@ def test_zero_steps_report_the_input(name, nv):
         B.close()
 
 
-@pytest.mark.parametrize("name,dtype,nv", [("ring8", torch.complex128, 1), ("ring8", torch.complex64, 2),
-                                           ("cluster3x4", torch.complex128, 1)])
-def test_zero_vector_stays_zero(name, dtype, nv):
+@pytest.mark.parametrize("name,dtype,nv,path", [("ring8", torch.complex128, 1, -1), ("ring8", torch.complex128, 1, 0),
+                                                ("ring8", torch.complex64, 2, -1), ("ring8", torch.complex64, 2, 0),
+                                                ("cluster3x4", torch.complex128, 1, -1)])
+def test_zero_vector_stays_zero(name, dtype, nv, path):
     w = workloads()[name]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, path)
     try:
         x = torch.zeros(nv * B.dim, dtype=dtype, device=DEV)
         n = 6
@@ -99,12 +105,14 @@ def test_single_string_spin_sector():
         B.close()
 
 
-@pytest.mark.parametrize("name,nv,bad", [("ring8", 1, np.nan), ("ring8", 3, np.inf), ("cluster3x4", 1, np.nan),
-                                         ("cluster3x4", 2, np.inf)])
+@pytest.mark.parametrize("name,nv,bad,path", [("ring8", 1, np.nan, -1), ("ring8", 1, np.nan, 0),
+                                              ("ring8", 3, np.inf, -1), ("ring8", 3, np.inf, 0),
+                                              ("cluster3x4", 1, np.nan, -1), ("cluster3x4", 2, np.inf, -1)])
 @pytest.mark.parametrize("chunk", [0, 32])
-def test_non_finite_input_stops_the_run(name, nv, bad, chunk):
+def test_non_finite_input_stops_the_run(name, nv, bad, path, chunk):
     w = workloads()[name]
     B = hub.Basis(w.lattice, w.U, w.n_up, w.n_dn, device=0)
+    hub.hub_set_propagate_path(B.handle, path)
     try:
         hub.hub_set_schedule(B.handle, chunk, 1 if chunk else 0)
         x = _vecs(B, nv, 62, torch.complex128)

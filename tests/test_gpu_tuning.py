@@ -79,6 +79,7 @@ def test_every_plan_matches_oracle(group, block):
     w = workloads()["ring8"]
     ham = HubbardOracle(w.lattice, w.U, 4, 4)
     B = hub.Basis(w.lattice, w.U, 4, 4)
+    hub.hub_set_propagate_path(B.handle, 0)  # plans are the launch path's (the resident stepper has none)
     try:
         plan = {"single_two_pass": 1, "block_two_pass": [0, block, block, block], "apply_group": group,
                 "prop_group": group}
