@@ -125,10 +125,35 @@ def _find(d, suffix):
     return hits[0]
 
 
-def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -> None:
+def copy_calibration() -> None:
+    """A plain elementwise kernel over COPY_BYTES (read and written), whose
+    counters scale the H*v kernels' to bytes."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
+# Counter summaries: the fused Lanczos pair of each workload, its title and its
+# algorithmic bytes per iteration (4 N s: read w_{j-1}, u_{j-1}; write u_j, y)
+COUNTER_CASES = {
+    "cluster3x4": (DOMINANT_KERNELS,
+                   ["# HBM traffic of one fused Lanczos iteration (complex128, 12-site 3x4, dim 853776):"], UNIT_BYTES),
+    "ring14": (("k_apply<double, 1, 1, 16, 1024, false, true, false>", "k_colpass<double, 1, 16, 1024, true, true, 2>"),
+               ["# HBM traffic of one fused Lanczos iteration (complex128, 14-site ring 7/7, dim 11778624,",
+                "# vectors far beyond the Infinity Cache; column pass staging one copy of 2 tile columns):"],
+               4 * 11778624 * 16),
+}
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str, case: str = "cluster3x4") -> None:
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the H*v kernels and of the
     calibration copy, scaled by the copy's known bytes, written as text."""
     import statistics
+    kernels, title, unit_bytes = COUNTER_CASES[case]
 
     def per_kernel(d, counter):
         vals = {}
@@ -138,7 +163,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
             vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return vals
 
-    lines = ["# HBM traffic of one fused Lanczos iteration (complex128, 12-site 3x4, dim 853776):",
+    lines = title + [
              "# u_j = w_{j-1} - alpha s u_{j-1} and H u_j with the Lanczos epilogue, as the row pass",
              "# and the column pass of the two-pass apply, per dispatch, summed",
              f"# command: {command}",
@@ -153,7 +178,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
         cpk = max(statistics.mean(v[k]) for k in cp)
         factor = COPY_BYTES / (cpk * 1024.0)
         kib = 0.0
-        for want in DOMINANT_KERNELS:
+        for want in kernels:
             hit = [k for k in v if want in k]
             if not hit:
                 raise SystemExit(f"{counter}: kernel {want} missing: {sorted(v)[:8]}")
@@ -168,7 +193,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, out: str, command: str) -
         lines += [f"{counter}_copy_kib_per_dispatch: {cpk:.1f}", f"{counter}_copy_scale: {factor:.4f}"]
     lines += [f"hbm_fetch_bytes_per_launch: {res['fetch']:.0f}", f"hbm_write_bytes_per_launch: {res['write']:.0f}",
               f"hbm_bytes_per_launch: {res['fetch'] + res['write']:.0f}",
-              f"algorithmic_bytes_per_launch: {UNIT_BYTES}",
+              f"algorithmic_bytes_per_launch: {unit_bytes}",
               f"kernel_source_sha256_16: {kernel_source_hash()}"]
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -542,18 +567,21 @@ def cfet4_variant(hub, B, w, v_start, t_start: float, steps: int, v_plain, plain
             "mean_krylov_m_per_solve": float(np.mean(log[:, 0, 0]))}
 
 
-def large_tile_variant(hub, steps: int = 4) -> dict:
+def large_tile_variant(hub, steps: int = 4, sizes=(14, 16)) -> dict:
     """HBM-resident tiles: the 14-site ring (7/7, 188 MB per complex128 vector)
     and the 16-site ring (8/8, 2.65 GB; down hops gathered from the row in
     global memory).  Per size: the plain H*v's kernel time and algorithmic
-    GB/s (HIP events on 10 launches), and midpoint steps/s of a few complex128
-    steps from a seeded random state under the ring pulse."""
+    GB/s (HIP events on 10 launches), midpoint steps/s of a few complex128
+    steps from a seeded random state under the ring pulse, and, from two more
+    steps with HIP events on every Lanczos launch, the average working
+    iteration (at 14 sites the fused two-pass pair) against its algorithmic
+    4 N s bytes."""
     import numpy as np
     import torch
     from synth import ring, PulseParams
 
     out = {}
-    for ns in (14, 16):
+    for ns in sizes:
         half = ns // 2
         B = hub.Basis(ring(ns), 8.0, half, half)
         g = torch.Generator(device="cuda:0").manual_seed(ns)
@@ -571,6 +599,16 @@ def large_tile_variant(hub, steps: int = 4) -> dict:
         us = ms / max(n, 1) * 1e3
         p = PulseParams(0, 0.5, 8.0, 0.05, 0.3)
         opts = hub.make_opts(tol=1e-10, m_max=20)
+        # untimed steps on a copy for ~0.3 s first: a process's first long
+        # propagation runs slower than later ones over the same steps
+        xw = x.clone()
+        tw = time.perf_counter()
+        while True:
+            hub.hub_propagate(B.handle, [p], 0.0, 0.01, 1, opts, xw, want_obs=False)
+            torch.cuda.synchronize()
+            if time.perf_counter() - tw > 0.3:
+                break
+        del xw
         hub.hub_propagate(B.handle, [p], 0.0, 0.01, 1, opts, x, want_obs=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -580,8 +618,20 @@ def large_tile_variant(hub, steps: int = 4) -> dict:
         out[f"ring{ns}"] = {"dim": int(B.dim), "hv_us": us, "hv_bytes": bpl, "hv_gbps": bpl / (us * 1e-6) / 1e9,
                             "hv_frac_of_8TBs": bpl / (us * 1e-6) / 8e12, "steps": steps,
                             "midpoint_steps_per_s": steps / el, "mean_krylov_m": float(np.mean(log[:, 0, 0]))}
+        hub.hub_profile_enable(B.handle, 1)
+        hub.hub_profile_read(B.handle)
+        hub.hub_propagate(B.handle, [p], 0.01 * (steps + 1), 0.01, 2, opts, x, want_obs=False)
+        nl, lms, lbpl = hub.hub_profile_read(B.handle)
+        hub.hub_profile_enable(B.handle, 0)
+        if nl:
+            lus = lms / nl * 1e3
+            out[f"ring{ns}"].update({"lanczos_launches": nl, "lanczos_us": lus, "lanczos_bytes": lbpl,
+                                     "lanczos_gbps": lbpl / (lus * 1e-6) / 1e9,
+                                     "lanczos_frac_of_8TBs": lbpl / (lus * 1e-6) / 8e12})
         print(f"[bench] ring{ns}: H*v {us:.0f} us = {bpl / (us * 1e-6) / 1e9:.0f} GB/s, "
-              f"{steps / el:.1f} steps/s", file=sys.stderr, flush=True)
+              f"{steps / el:.1f} steps/s" + (f"; Lanczos iteration {lms / nl * 1e3:.0f} us = "
+                                            f"{lbpl / (lms / nl * 1e-3) / 1e9:.0f} GB/s" if nl else ""),
+              file=sys.stderr, flush=True)
         B.close()
         del x
         torch.cuda.empty_cache()
@@ -951,10 +1001,12 @@ def main() -> int:
                     help="after the timed region, run a plain copy of known size (counter scaling)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
     ap.add_argument("--summarize-stats", nargs=2, metavar=("TRACE_DIR", "OUT"))
+    ap.add_argument("--counters-case", choices=tuple(COUNTER_CASES), default="cluster3x4",
+                    help="workload whose fused Lanczos pair --summarize-counters reads")
     ap.add_argument("--command", default="", help="profiling command recorded in a summary")
     ap.add_argument("--note", default="", help="comment lines (separated by |) recorded in a summary")
     ap.add_argument("--variant", choices=("greens_ring10", "greens_scaling", "greens_persistent", "ring14_block",
-                                          "ring8", "hv12", "controller"),
+                                          "ring8", "hv12", "controller", "ring14"),
                     help="run only this variant and print its result (for profiling it alone)")
     args = ap.parse_args()
 
@@ -962,7 +1014,7 @@ def main() -> int:
         print(json.dumps(cpu_baseline(args.cpu_seconds, args.cpu_member)))
         return 0
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters, command=args.command)
+        summarize_counters(*args.summarize_counters, command=args.command, case=args.counters_case)
         return 0
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats, command=args.command, note=args.note)
@@ -990,8 +1042,10 @@ def main() -> int:
         run = {"greens_ring10": greens_variant, "greens_scaling": greens_scaling_variant,
                "greens_persistent": lambda h: greens_scaling_variant(h, ((1, "persistent_members"),)),
                "ring14_block": ring14_block_variant, "ring8": ring8_variant,
-               "controller": controller_c5_variant}
+               "controller": controller_c5_variant, "ring14": lambda h: large_tile_variant(h, sizes=(14,))}
         print(json.dumps({args.variant: run[args.variant](hub)}), flush=True)
+        if args.copy_calibration:
+            copy_calibration()
         return 0
 
     w = workloads()["cluster3x4"]
@@ -1079,12 +1133,7 @@ def main() -> int:
                      "kernels": "sum of both kernel times; bytes = 4 N s (read w_{j-1}, u_{j-1}; write u_j, y)"},
     }
     if args.copy_calibration:
-        a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(5):
-            torch.neg(a, out=b)  # plain elementwise kernel: reads and writes COPY_BYTES
-        torch.cuda.synchronize()
-        del a, b
+        copy_calibration()
     if not args.no_variants:
         var = {}
         var["copy"] = copy_bandwidth()
