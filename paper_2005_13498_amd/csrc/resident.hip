@@ -451,7 +451,8 @@ __global__ __launch_bounds__(kRT) void k_resident(ResidentArgs P) {
 }
 
 // Elements per thread of the instantiation a sector runs on: the smallest
-// that covers it (five covers 8 sites at half filling without spilling).
+// that covers it (five covers 8 sites at half filling; each larger one holds
+// more of a thread's elements in registers and spills more).
 int resident_ept(int prec, int64_t dim) {
   static constexpr int kEpts[] = {1, 2, 4, 5, 6, 8, 12, 16};
   for (int e : kEpts)
