@@ -450,11 +450,16 @@ std::vector<int> groups_for(hub_basis h, int nvec, int prec, bool propagate = tr
   // single vectors run the two-pass kernels with fused updates, which beat
   // interleaved one-pass blocks whenever they apply
   if (hub::apply_two_pass(h->D, prec, 1, hub::kLanczos, false)) gmax = 1;
+  // except complex64 propagations of several vectors: there blocks of 4 on
+  // the two-pass block kernels beat single vectors on concurrent lanes (per
+  // vector-step, 8 vectors: 12 sites 139.5 vs 165.5 us, 14 sites 2,204 vs
+  // 2,382 us; complex128 singles stay ahead at 12 sites, 251 vs 259 us)
+  if (propagate && prec == 1 && nvec > 1 && gmax == 1 && hub::block_two_pass(h->D, prec, 4)) gmax = 4;
   // plain applies of blocks on the two-pass block kernels: the largest group
   // whose staged row keeps two workgroups per CU (else one).  Propagations
-  // keep the rule above unless a tuned plan says otherwise: at 12 sites single
-  // vectors on the fused two-pass iterations, several groups on concurrent
-  // lanes, were measured faster than blocks.
+  // keep the rules above unless a tuned plan says otherwise: at 12 sites
+  // complex128 single vectors on the fused two-pass iterations, several groups
+  // on concurrent lanes, were measured faster than blocks.
   if (nvec > 1 && !propagate) {
     int gb = 0;
     for (int g = kMaxNV; g >= 2 && !gb; g /= 2)
