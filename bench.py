@@ -363,9 +363,9 @@ def tuned_run(hub, B, prec: int, pulses, t_start: float, dt: float, steps: int, 
 def batched_variants(hub, B, v0, t_start: float, w, steps: int) -> dict:
     """Mixed precision and batching at 12 sites: the same ground state under
     8 pulse amplitudes (the seeded A0 draws), propagated by one hub_propagate
-    call with 8 members in complex64 (FP64 Lanczos scalars) and in complex128
-    (at this size the library runs the members as single vectors on the fused
-    two-pass kernels, which beat interleaved blocks, on concurrent lanes);
+    call with 8 members in complex64 (FP64 Lanczos scalars; at this size two
+    interleaved blocks of 4 on the two-pass block kernels) and in complex128
+    (single vectors on the fused two-pass kernels, on concurrent lanes);
     member-steps/s of both (timed without apply timing, which would keep the
     lanes sequential), the fused iteration's kernel time and GB/s from a
     separate sequential run with apply timing, and the complex64 errors in
